@@ -1,0 +1,288 @@
+"""Pins of the oracle against facts fixed outside it: the paper's worked example,
+closed-form states, a brute-force state vector, SVD identities and invariants.
+
+Each test says which passage or fact pins which part of the oracle."""
+import math
+import os
+
+import mpmath
+import numpy as np
+import pytest
+
+from paper_1111_3124_amd import workloads as W
+from tests.ddutil import dd_abs_diff, mpc, mpr
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+INV_SQRT2 = mpmath.mpf(1) / mpmath.sqrt(2)
+
+
+def rdo_from_amplitudes(amps, n, keep):
+    """Reduced density operator of the qubits in ``keep`` from all 2^n amplitudes
+    (mpmath complex), basis index with qubit 0 most significant."""
+    rest = [q for q in range(n) if q not in keep]
+    dk = 1 << len(keep)
+    rho = [[mpmath.mpc(0) for _ in range(dk)] for _ in range(dk)]
+
+    def idx(kb, rb):
+        x = 0
+        for t, q in enumerate(keep):
+            x |= ((kb >> (len(keep) - 1 - t)) & 1) << (n - 1 - q)
+        for t, q in enumerate(rest):
+            x |= ((rb >> (len(rest) - 1 - t)) & 1) << (n - 1 - q)
+        return x
+
+    for r in range(1 << len(rest)):
+        for a in range(dk):
+            for b in range(dk):
+                rho[a][b] += amps[idx(a, r)] * mpmath.conj(amps[idx(b, r)])
+    return rho
+
+
+def all_amps(m, n):
+    out = []
+    for x in range(1 << n):
+        bits = [(x >> (n - 1 - q)) & 1 for q in range(n)]
+        hi, lo = m.amplitude(bits)
+        out.append(mpc(hi, lo))
+    return out
+
+
+def test_paper_sample_rdo(oracle_mod):
+    """Paper Section 3.2: |000>, H on qubit 0, CNOT(0 -> 2) (one U(8) on sites 0..2);
+    the printed reduced density operators at both stages."""
+    rows = [l.split() for l in open(os.path.join(GOLD, "paper_sample.txt")) if l.strip() and not l.startswith("#")]
+    m = oracle_mod.OracleMPS(3, 8, 0.0)
+    stages = {"initial": None, "final": None}
+    stages["initial"] = all_amps(m, 3)
+    for g in W.paper_sample_circuit():
+        m.apply_gate(g)
+    stages["final"] = all_amps(m, 3)
+    for stage in ("initial", "final"):
+        sel = [r for r in rows if r[0] == stage]
+        keep = [int(q) for q in sel[0][1].split(",")]
+        rho = rdo_from_amplitudes(stages[stage], 3, keep)
+        expect = {(int(r[2], 2), int(r[3], 2)): float(r[4]) for r in sel}
+        dk = 1 << len(keep)
+        for a in range(dk):
+            for b in range(dk):
+                v = rho[a][b]
+                e = expect.get((a, b), 0.0)
+                # printed to 8 significant digits; the exact values are 1 and 1/2
+                assert abs(v - e) <= 5e-9 * max(abs(e), 1.0)
+                assert abs(v - e) <= 1e-30  # outputs leave the oracle as double-double
+    # bond dimensions and Schmidt values (Eq. (2)): two equal values 2^-1/2
+    assert m.bond_dims() == [2, 2]
+    for b in range(2):
+        hi, lo = m.schmidt(b)
+        for j in range(2):
+            assert abs(mpr(hi[j], lo[j]) - INV_SQRT2) < 1e-30
+
+
+@pytest.mark.parametrize("n", [2, 5, 9])
+def test_ghz_closed_form(oracle_mod, n):
+    """GHZ: H then a CNOT chain; c(0^n) = c(1^n) = 2^-1/2, every cut has Schmidt
+    values [2^-1/2, 2^-1/2]."""
+    m = oracle_mod.OracleMPS(n, 4, 0.0)
+    for g in W.ghz_circuit(n):
+        m.apply_gate(g)
+    for x in range(1 << n):
+        bits = [(x >> (n - 1 - q)) & 1 for q in range(n)]
+        hi, lo = m.amplitude(bits)
+        want = INV_SQRT2 if x in (0, (1 << n) - 1) else 0
+        assert abs(mpc(hi, lo) - want) < 1e-30
+    for b in range(n - 1):
+        hi, lo = m.schmidt(b)
+        assert len(hi) == 2
+        assert all(abs(mpr(hi[j], lo[j]) - INV_SQRT2) < 1e-30 for j in range(2))
+
+
+def qft_closed_form_product(n, prep, y):
+    """QFT of the product state (x) (a_q|0> + b_q|1>) (qubit 0 most significant):
+    c(y) = 2^{-n/2} prod_q (a_q + b_q exp(2 pi i (y mod 2^{q+1}) / 2^{q+1}))."""
+    c = mpmath.mpf(2) ** (-mpmath.mpf(n) / 2)
+    for q, g in enumerate(prep):
+        a = mpc(g.u_hi[0, 0], g.u_lo[0, 0])
+        b = mpc(g.u_hi[1, 0], g.u_lo[1, 0])
+        mod = 1 << (q + 1)
+        c *= a + b * mpmath.expj(2 * mpmath.pi * (y % mod) / mod)
+    return c
+
+
+@pytest.mark.parametrize("n,x", [(4, 5), (6, 37)])
+def test_qft_basis_state(oracle_mod, n, x):
+    """QFT of a basis state: c(y) = 2^{-n/2} exp(2 pi i x y / 2^n)."""
+    bits = [(x >> (n - 1 - q)) & 1 for q in range(n)]
+    m = oracle_mod.OracleMPS(n, 1 << n, 0.0)
+    for g in W.basis_prep(bits) + W.qft_lnn_circuit(n):
+        m.apply_gate(g)
+    for y in range(1 << n):
+        yb = [(y >> (n - 1 - q)) & 1 for q in range(n)]
+        hi, lo = m.amplitude(yb)
+        want = mpmath.mpf(2) ** (-mpmath.mpf(n) / 2) * mpmath.expj(2 * mpmath.pi * x * y / mpmath.mpf(2 ** n))
+        assert abs(mpc(hi, lo) - want) < 1e-29
+    # a basis state stays a product state under the QFT
+    assert m.bond_dims() == [1] * (n - 1)
+
+
+def test_qft_product_state(oracle_mod):
+    """QFT of a seeded random product state, no truncation, vs the product formula."""
+    n = 7
+    prep = W.product_state_prep(n, 5)
+    m = oracle_mod.OracleMPS(n, 1 << n, 0.0)
+    for g in prep + W.qft_lnn_circuit(n):
+        m.apply_gate(g)
+    for y in range(0, 1 << n, 3):
+        yb = [(y >> (n - 1 - q)) & 1 for q in range(n)]
+        hi, lo = m.amplitude(yb)
+        assert abs(mpc(hi, lo) - qft_closed_form_product(n, prep, y)) < 1e-29
+
+
+def test_two_qubit_schmidt_closed_form(oracle_mod):
+    """Two qubits, c = U|00>: sigma^2 = (1 +- sqrt(1 - 4 |det C|^2)) / 2 with
+    C = [[c00, c01], [c10, c11]]."""
+    rng = W.rng_for(11)
+    for _ in range(5):
+        hi, lo = W.haar_unitary_dd(4, rng)
+        m = oracle_mod.OracleMPS(2, 2, 0.0)
+        m.apply(0, 2, hi, lo)
+        c = [mpc(hi[r, 0], lo[r, 0]) for r in range(4)]
+        norm2 = sum(abs(z) ** 2 for z in c)
+        det = c[0] * c[3] - c[1] * c[2]
+        disc = mpmath.sqrt(1 - 4 * abs(det / norm2) ** 2)
+        want = [mpmath.sqrt((1 + disc) / 2), mpmath.sqrt((1 - disc) / 2)]
+        sh, sl = m.schmidt(0)
+        assert len(sh) == 2
+        for j in range(2):
+            assert abs(mpr(sh[j], sl[j]) - want[j]) < 1e-29
+
+
+def _sv_compare(oracle_mod, n, gates, chi_max, tol):
+    m = oracle_mod.OracleMPS(n, chi_max, 0.0)
+    sv = oracle_mod.OracleSV(n)
+    for g in gates:
+        m.apply_gate(g)
+        sv.apply_gate(g)
+    hi, lo = sv.amplitudes()
+    worst = 0.0
+    for x in range(1 << n):
+        bits = [(x >> (n - 1 - q)) & 1 for q in range(n)]
+        ah, al = m.amplitude(bits)
+        worst = max(worst, float(abs(mpc(ah, al) - mpc(hi[x], lo[x]))))
+    assert worst < tol, worst
+    return m
+
+
+def test_brickwork_vs_state_vector(oracle_mod):
+    """No truncation (chi_max = 32 is never binding at n = 10): every amplitude of the
+    MPS equals the dense state vector's, both at 256 bits, exactly unitary gates."""
+    n = 10
+    gates = [g for layer in W.brickwork_dd(n, 10, 1) for g in layer]
+    m = _sv_compare(oracle_mod, n, gates, 32, 1e-28)
+    assert m.bond_dims() == [2, 4, 8, 16, 32, 16, 8, 4, 2]
+    # Eq. (2): Schmidt values normalised on every cut
+    for b in range(n - 1):
+        hi, lo = m.schmidt(b)
+        s = sum(mpr(h, l) ** 2 for h, l in zip(hi, lo))
+        assert abs(s - 1) < 1e-30
+        assert all(hi[j] >= hi[j + 1] for j in range(len(hi) - 1))
+
+
+def test_mixed_width_gates_vs_state_vector(oracle_mod):
+    """U(2), U(4) and U(8) gates on random windows (three-site splits included)."""
+    n = 7
+    gates = W.random_circuit_dd(n, 40, 21)
+    assert any(g.k == 3 for g in gates) and any(g.k == 1 for g in gates)
+    _sv_compare(oracle_mod, n, gates, 1 << n, 1e-28)
+
+
+def test_truncation_eckart_young(oracle_mod):
+    """One truncated update from a canonical state: with psi the exact state after the
+    gate, psi_k the truncated MPS state and w the reported discarded weight,
+    <psi|psi_k> = sqrt(1 - w) and ||psi - sqrt(1 - w) psi_k||^2 = w  (Eckart-Young:
+    the discarded part of theta has squared norm sum_{j>=k} sigma_j^2)."""
+    n = 8
+    rng = W.rng_for(31)
+    pre = [g for layer in W.brickwork_dd(n, 6, 30) for g in layer]
+    hi, lo = W.haar_unitary_dd(4, rng)
+    last = W.Gate(3, 2, hi, lo)
+    m = oracle_mod.OracleMPS(n, 256, 0.0)
+    sv = oracle_mod.OracleSV(n)
+    for g in pre:
+        m.apply_gate(g)
+        sv.apply_gate(g)
+    assert m.bond_dims()[3] > 3
+    m.set_trunc(3, 0.0)
+    m.apply_gate(last)
+    sv.apply_gate(last)
+    st = m.last_stats()[0]
+    assert st["k"] == 3
+    w = mpr(st["w"], st["w_lo"])
+    assert w > 1e-6
+    ex_hi, ex_lo = sv.amplitudes()
+    exact = [mpc(h, l) for h, l in zip(ex_hi, ex_lo)]
+    kept = all_amps(m, n)
+    ov = sum(mpmath.conj(e) * x for e, x in zip(exact, kept))
+    assert abs(ov - mpmath.sqrt(1 - w)) < 1e-28
+    resid = sum(abs(e - mpmath.sqrt(1 - w) * x) ** 2 for e, x in zip(exact, kept))
+    assert abs(resid - w) < 1e-28
+    # the kept Schmidt values are the exact state's largest three, renormalised
+    ref = oracle_mod.OracleMPS(n, 256, 0.0)
+    for g in pre + [last]:
+        ref.apply_gate(g)
+    rh, rl = ref.schmidt(3)
+    sh, sl = m.schmidt(3)
+    full = [mpr(a, b) for a, b in zip(rh, rl)]
+    nu = mpmath.sqrt(sum(x ** 2 for x in full[:3]))
+    for j in range(3):
+        assert abs(mpr(sh[j], sl[j]) - full[j] / nu) < 1e-29
+    assert abs(1 - sum(x ** 2 for x in full[:3]) - w) < 1e-29
+
+
+def test_eps_rule(oracle_mod):
+    """Truncation by discarded weight: k is the smallest count whose dropped weight
+    is <= eps * W (Section 3.1: small coefficients are cut; the threshold is the
+    documented reading)."""
+    n = 8
+    pre = [g for layer in W.brickwork_dd(n, 6, 40) for g in layer]
+    ref = oracle_mod.OracleMPS(n, 256, 0.0)
+    for g in pre:
+        ref.apply_gate(g)
+    sh, sl = ref.schmidt(3)
+    sig2 = [mpr(a, b) ** 2 for a, b in zip(sh, sl)]
+    tails = [sum(sig2[k:]) for k in range(len(sig2) + 1)]
+    for k_want in (2, 5, 9):
+        # an eps between the tails of k_want and k_want - 1
+        eps = float((tails[k_want] + tails[k_want - 1]) / 2)
+        # replay the last gate touching bond 3 with that eps
+        m = oracle_mod.OracleMPS(n, 256, 0.0)
+        idx = max(i for i, g in enumerate(pre) if g.first == 3)
+        last = pre[idx]
+        for g in pre[:idx]:
+            m.apply_gate(g)
+        m.set_trunc(256, eps)
+        m.apply_gate(last)
+        assert m.last_stats()[0]["k"] == k_want
+        assert m.bond_dim(3) == k_want
+
+
+def test_degenerate_cut_flag(oracle_mod):
+    """GHZ with chi_max = 1 cuts between two equal Schmidt values: the reported gap
+    at the cut is zero (the kept subspace is not unique)."""
+    m = oracle_mod.OracleMPS(3, 1, 0.0)
+    for g in W.ghz_circuit(3)[:2]:
+        m.apply_gate(g)
+    st = m.last_stats()[0]
+    assert st["k"] == 1 and st["rank"] == 2
+    assert st["gap"] < 1e-60
+
+
+def test_rank_guard(oracle_mod):
+    """A product gate (identity) on an entangled cut keeps the exact Schmidt rank."""
+    n = 6
+    pre = [g for layer in W.brickwork_dd(n, 4, 50) for g in layer]
+    m = oracle_mod.OracleMPS(n, 64, 0.0)
+    for g in pre:
+        m.apply_gate(g)
+    before = m.bond_dims()
+    m.apply(2, 2, np.eye(4, dtype=np.complex128))
+    assert m.bond_dims() == before
