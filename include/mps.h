@@ -1,0 +1,180 @@
+/* mps.h -- C ABI of the MI355X matrix-product-state gate-update library.
+ *
+ * The library keeps an n-qubit pure state in the matrix-product form of the
+ * paper's Section 3.1, Eq. (1), and applies quantum gates to it the way that
+ * section describes: a gate on qubits s (and s+1, s+2) updates only the tensors
+ * of those sites and the Schmidt coefficients between them (Eq. (2)); small
+ * Schmidt coefficients are truncated away.
+ *
+ * Representation (device memory, owned by the handle):
+ *   - Site s holds B_s[alpha][i][beta] = Q_s(i, alpha, beta) V_s(beta): the paper's
+ *     Q_s with the Schmidt coefficients of its right bond absorbed, so that every
+ *     B_s is right-canonical and no step divides by a Schmidt value.
+ *   - Bond s (between sites s and s+1, s = 0..n-2) holds m_s and the Schmidt
+ *     coefficients V_s(0..m_s-1) in descending order, with sum V_s^2 = 1.
+ *   The amplitude c_{i0..i(n-1)} of Eq. (1) is B_0[i0] B_1[i1] ... B_{n-1}[i(n-1)].
+ *
+ * Conventions:
+ *   - Qubit 0 is the leftmost qubit of |i_0 ... i_{n-1}>.
+ *   - A k-qubit gate U (k = 1, 2, 3) acts on sites first..first+k-1; it is a
+ *     2^k x 2^k complex matrix, row-major, U[r][c] = <r|U|c>, with basis index
+ *     r = sum_t i_{first+t} 2^{k-1-t} (the first site is the most significant bit).
+ *     It is passed as 2 * 4^k doubles, complex interleaved (re, im).
+ *   - Truncation after each split: with the singular values sigma_j sorted
+ *     descending and W = sum_j sigma_j^2, the kept count is
+ *       k = min(chi_max, k_eps, rank),
+ *     k_eps the smallest k >= 1 with sum_{j>=k} sigma_j^2 <= eps * W, and rank the
+ *     number of sigma_j above the precision's noise floor relative to sigma_0.
+ *     The kept values are renormalised: V_s = sigma_j / sqrt(sum_{j<k} sigma_j^2).
+ *   - A three-qubit gate splits left first (s | s+1 s+2), then (s+1 | s+2).
+ *   - Status: every int-returning call returns MPS_OK (0) or a negative MPS_E*
+ *     code; mps_last_error() gives a message.  No exception crosses the ABI.
+ *   - Ownership: the caller owns every host buffer passed in or out; the library
+ *     copies inputs before returning.  The handle owns all device memory.
+ *   - Synchronisation: gate application is queued on the handle's HIP stream and
+ *     returns without waiting for the device, except that the library waits for
+ *     the new bond dimensions at the end of each gate (or each wave of gates,
+ *     see mps_apply_gates).  Every call that returns host data synchronises.
+ *   - Threads: one thread at a time per handle.
+ */
+#ifndef MPS_H_
+#define MPS_H_
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mps_state* mps_handle;
+
+enum mps_status {
+  MPS_OK = 0,
+  MPS_EINVAL = -1,     /* bad argument (site out of range, k not in {1,2,3}, null buffer) */
+  MPS_ERANGE = -2,     /* size beyond a documented limit or a caller buffer too small   */
+  MPS_ENOMEM = -3,     /* device allocation failed                                      */
+  MPS_EDEVICE = -4,    /* a HIP runtime call failed                                     */
+  MPS_ENOCONV = -5,    /* the Jacobi iteration hit its sweep limit (state still updated) */
+  MPS_ENONFINITE = -6, /* a gate entry is NaN or infinite                               */
+  MPS_ESTATE = -7      /* operation not valid for this handle (e.g. dd call on FP64)    */
+};
+
+enum mps_precision {
+  MPS_PREC_FP64 = 0,   /* binary64 tensors and arithmetic                               */
+  MPS_PREC_DD = 1      /* double-double (hi + lo) tensors; FP64 SVD refined in dd       */
+};
+
+enum mps_option {
+  MPS_OPT_MAX_SWEEPS = 1,     /* Jacobi sweep limit (default 40 FP64, 8 dd polish)       */
+  MPS_OPT_JACOBI_TOL = 2,     /* relative off-diagonal tolerance multiplier (default 1)  */
+  MPS_OPT_KERNEL_TIMING = 3,  /* 1: time every kernel class with HIP events (see below)  */
+  MPS_OPT_RANK_FLOOR = 4      /* relative rank floor (default 2^-47 FP64, 2^-100 dd)      */
+};
+
+/* Diagnostics of the most recent split (the last one of a three-qubit gate). */
+struct mps_update_stats {
+  double W;        /* total weight sum sigma_j^2 before truncation                     */
+  double w;        /* discarded weight, relative: sum_{j>=k} sigma_j^2 / W              */
+  double gap;      /* (sigma_{k-1} - sigma_k) / sigma_0 when a non-zero value was cut, else +inf */
+  double epsdist;  /* relative distance of the eps decision from its boundary, +inf if eps = 0 */
+  int k;           /* kept count                                                      */
+  int rank;        /* values above the rank floor                                     */
+  int sweeps;      /* Jacobi sweeps of the last gate (FP64 + dd polish)                */
+  int splits;      /* number of splits in the last gate (0, 1 or 2)                    */
+};
+
+/* --- lifetime ------------------------------------------------------------------- */
+
+/* Create an n-qubit state |0...0> (paper, Section 3.2: "mps M(n)"): all m_s = 1,
+ * V_s = [1], B_s[0][0][0] = 1.  FP64 precision, the library's own stream.
+ * n >= 1, chi_max >= 1, eps >= 0.  Returns NULL on error (see mps_last_error(NULL)). */
+mps_handle mps_create(int n, int chi_max, double eps);
+
+/* As mps_create with a precision (enum mps_precision) and an optional HIP stream
+ * (hipStream_t passed as void*; NULL = a stream the handle creates and owns). */
+mps_handle mps_create_ex(int n, int chi_max, double eps, int prec, void* hip_stream);
+
+int mps_destroy(mps_handle h);
+
+/* --- gates (Section 3.1: U(2), U(4), U(8) are elementary) ----------------------- */
+
+/* Apply U (2 * 4^k doubles, see Conventions) to sites first..first+k-1.
+ * k = 1: B_first <- (U (x) 1) B_first; no SVD, Schmidt values unchanged.
+ * k = 2: theta = B_s B_{s+1} mixed by U, SVD of diag(V_{s-1}) theta, truncation,
+ *        split into B_s, V_s, B_{s+1} (Section 3.1; Vidal's update).
+ * k = 3: the same on three sites with two splits.
+ * Errors: MPS_EINVAL (first < 0, first + k > n, k not 1..3, U NULL),
+ * MPS_ENONFINITE, MPS_ENOCONV, MPS_EDEVICE, MPS_ENOMEM. */
+int mps_apply_gate(mps_handle h, int first, int k, const double* U);
+
+/* Double-double gate: U = U_hi + U_lo exactly (same layout each).  On an FP64
+ * handle U_lo is ignored. */
+int mps_apply_gate_dd(mps_handle h, int first, int k, const double* U_hi, const double* U_lo);
+
+/* Apply `count` gates in order.  Consecutive gates acting on disjoint sites form a
+ * wave that runs as one batched launch per kernel (gates on disjoint sites
+ * commute, so the result equals applying them one by one).  first[i], k[i];
+ * U packed back to back (2 * 4^k[i] doubles each); U_lo NULL or same packing. */
+int mps_apply_gates(mps_handle h, int count, const int* first, const int* k,
+                    const double* U, const double* U_lo);
+
+/* --- readout --------------------------------------------------------------------- */
+
+/* Bond dimension m_bond, bond in [0, n-2]. */
+int mps_bond_dim(mps_handle h, int bond, int* m);
+
+/* Schmidt coefficients V_bond (Eq. (2)), descending, into lam[0..m-1]; cap is the
+ * capacity of lam; *m receives m_bond.  MPS_ERANGE if cap < m_bond. */
+int mps_schmidt(mps_handle h, int bond, double* lam, int cap, int* m);
+
+/* Double-double Schmidt coefficients (hi, lo); on an FP64 handle lo = 0. */
+int mps_schmidt_dd(mps_handle h, int bond, double* lam_hi, double* lam_lo, int cap, int* m);
+
+/* Amplitude <b_0 ... b_{n-1}|Psi> of Eq. (1); bits[q] in {0,1} is qubit q.
+ * out = {re, im}. */
+int mps_amplitude(mps_handle h, const unsigned char* bits, double out[2]);
+
+/* Double-double amplitude: out = {re_hi, re_lo, im_hi, im_lo}. */
+int mps_amplitude_dd(mps_handle h, const unsigned char* bits, double out[4]);
+
+/* `count` amplitudes at once: bits is count x n (row per bitstring); out holds
+ * 2 doubles per amplitude (FP64 handle) or 4 (dd handle: re_hi, re_lo, im_hi, im_lo). */
+int mps_amplitudes(mps_handle h, int count, const unsigned char* bits, double* out);
+
+/* Diagnostics of the last split. */
+int mps_stats(mps_handle h, struct mps_update_stats* s);
+
+/* --- state import / export (B, V) gauge ---------------------------------------- */
+
+/* Replace the state.  dims[s] = m_s (s = 0..n-2, each <= the bond's capacity
+ * min(chi_max, 2^{s+1}, 2^{n-1-s})).  B[s] points to m_{s-1} * 2 * m_s complex
+ * values, row-major [alpha][i][beta], interleaved (re, im); lam[s] to m_s values.
+ * B_lo / lam_lo: NULL, or the lo planes on a dd handle. */
+int mps_load(mps_handle h, const int* dims, const double* const* B, const double* const* B_lo,
+             const double* const* lam, const double* const* lam_lo);
+
+/* Copy site tensor s (m_{s-1} * 2 * m_s complex) to host; lo may be NULL. */
+int mps_get_site(mps_handle h, int s, double* hi, double* lo, long cap_doubles);
+
+/* --- control --------------------------------------------------------------------- */
+
+int mps_set_option(mps_handle h, int key, double value);
+
+/* Wait for all work queued on the handle's stream. */
+int mps_sync(mps_handle h);
+
+/* With MPS_OPT_KERNEL_TIMING on, accumulated device time (ms, from HIP events
+ * recorded on the handle's stream around each launch) and launch count of kernel
+ * class `cls` (0 theta, 1 jacobi step, 2 truncate, 3 split, 4 single-site gate,
+ * 5 amplitude, 6 dd refinement); reset = 1 clears the counters after reading. */
+int mps_kernel_time(mps_handle h, int cls, double* ms, long* launches, int reset);
+
+/* Message for the last error on h (h may be NULL: the last error of mps_create*). */
+const char* mps_last_error(mps_handle h);
+
+/* Library version string. */
+const char* mps_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPS_H_ */

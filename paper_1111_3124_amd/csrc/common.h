@@ -1,0 +1,89 @@
+// Shared device/host definitions of the gate-update kernels (gfx950).
+//
+// Layouts (device memory):
+//   site tensor B_s[alpha][i][beta]  at  B[(alpha*2 + i)*ld + beta], complex double2,
+//                                     ld = capacity of the site's right bond;
+//   theta (M x N), column-major, ld = M (compact to the live dims);
+//     2-site rows r = 2*alpha + i (M = 2a), columns col = j*c + gamma (N = 2c);
+//   V (N x N), column-major, ld = N.
+// A double-double handle keeps a second "lo" plane beside every hi array.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mpsk {
+
+constexpr int kMaxSort = 4096;  // largest N the truncation kernel sorts in LDS
+
+// ------------------------------------------------------------------ complex FP64
+__host__ __device__ inline double2 cmk(double x, double y) { return make_double2(x, y); }
+__host__ __device__ inline double2 cadd(double2 a, double2 b) { return cmk(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline double2 csub(double2 a, double2 b) { return cmk(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline double2 cscale(double2 a, double s) { return cmk(a.x * s, a.y * s); }
+__host__ __device__ inline double2 cconj(double2 a) { return cmk(a.x, -a.y); }
+__host__ __device__ inline double2 cmul(double2 a, double2 b) {
+  return cmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// acc + a * b
+__host__ __device__ inline double2 cfma(double2 a, double2 b, double2 acc) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+  return acc;
+}
+// acc + conj(a) * b
+__host__ __device__ inline double2 cfmac(double2 a, double2 b, double2 acc) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(-a.y, b.x, acc.y);
+  return acc;
+}
+
+// ------------------------------------------------------------------ task descriptors
+// One two-site update (one SVD) of a wave.  The host fills these and copies the
+// array to the device; kernels index it with blockIdx.y / blockIdx.z.
+struct Task2 {
+  // state
+  double2* Bl;          // site s
+  double2* Br;          // site s+1
+  double2* Bl_lo;       // dd lo planes (null on FP64 handles)
+  double2* Br_lo;
+  int ldl, ldr;         // row lengths of Bl, Br
+  int a, b, c;          // live bond dims m_{s-1}, m_s, m_{s+1}
+  int M, N;             // theta shape: 2a x 2c
+  const double* lamL;   // V_{s-1}: a values (boundary: a 1)
+  const double* lamL_lo;
+  double* lamS;         // V_s output slot
+  double* lamS_lo;
+  int* dim_out;         // where the new m_s goes (device bond-dim table)
+  // gate, row-major 4x4
+  double2 U[16];
+  double2 U_lo[16];
+  // workspace (compact, sized for this task)
+  double2* thu;         // theta unweighted, M x N
+  double2* thw;         // theta weighted by V_{s-1}; becomes W = thw V
+  double2* V;           // N x N
+  double2* thu_lo;      // dd planes of the above (dd handles)
+  double2* thw_lo;
+  double2* V_lo;
+  double* sig2;         // N: squared column norms of W (from the Jacobi Gram diagonals)
+  double* sig2_lo;
+  int* perm;            // N: column order, sigma descending
+  double* fro2;         // ||thw||_F^2 (zero-column threshold)
+  double* stats;        // 8 doubles: W, w, gap, epsdist, k, rank, nu, W_lo
+  int* flags;           // 2 ints: rotation flags of the current / previous sweep
+};
+
+// One single-site gate.
+struct Task1 {
+  double2* B;
+  double2* B_lo;
+  int ld, a, b;
+  double2 U[4];
+  double2 U_lo[4];
+};
+
+}  // namespace mpsk

@@ -1,0 +1,26 @@
+// Host-side launchers of the gate-update kernels (one per kernel family).
+#pragma once
+#include "common.h"
+
+namespace mpsk {
+
+struct AmpArgs {
+  const double2* const* B;  // n device pointers (site tensors)
+  const int* ld;            // n row lengths
+  const int* dimx;          // n + 1 bond dims, dimx[0] = dimx[n] = 1
+  int n;
+  const unsigned char* bits;  // count x n
+  double2* out;               // count
+};
+
+hipError_t launch_prep2(Task2* d_tasks, int ntask, int maxN, hipStream_t st);
+hipError_t launch_theta2(Task2* d_tasks, int ntask, int maxM, int maxN, hipStream_t st);
+int jacobi_block_width();
+hipError_t launch_jacobi_step(Task2* d_tasks, int ntask, int maxN, int step, int sweep, double tol_mult,
+                              int maxin, hipStream_t st);
+hipError_t launch_truncate(Task2* d_tasks, int ntask, int chi, double eps, double floor_rel, hipStream_t st);
+hipError_t launch_split(Task2* d_tasks, int ntask, int maxM, int maxN, int maxK, hipStream_t st);
+hipError_t launch_gate1(Task1* d_tasks, int ntask, long maxel, hipStream_t st);
+hipError_t launch_amplitude(const AmpArgs& args, int count, hipStream_t st);
+
+}  // namespace mpsk
