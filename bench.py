@@ -1,0 +1,198 @@
+"""Benchmark: MPS gate updates per second at chi = 256 on one MI355X.
+
+Workload (seeded, synthetic): a 40-qubit MPS, chi_max = 256, eps = 1e-12, driven by
+a brickwork circuit of Haar-random U(4) gates (seed 2).  Untimed setup applies
+brickwork layers until every bond that can hold 256 Schmidt values does (bonds
+7..31).  One step then applies the next brickwork layer's gates on bonds 8..30,
+where a = b = c = 256 (theta is 512 x 512): 12 or 11 independent gate updates run
+as one batched wave (theta GEMM, Jacobi SVD, truncation, split; for the dd
+variant also the double-double refinement).
+
+Output: one JSON line.  `value` is the headline variant's gate updates per second
+(dd-refined when available, else FP64); the other variant is reported beside it.
+`roofline` is for the dominant kernel (the Jacobi step); `cpu_baseline` times the
+256-bit oracle on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MPS gate updates/s at χ=256: FP64 vs dd-refined, error vs 256-bit oracle"
+N_QUBITS, CHI, EPS, SEED = 40, 256, 1e-12, 2
+PEAK_FP64 = 78.6e12  # MI355X FP64 vector (and matrix) peak, FLOP/s
+
+
+def jacobi_flops(M: int, N: int) -> float:
+    """Scalar one-sided Jacobi work per sweep, J(M, N) = N(N-1)/2 (28 M + 20 N)."""
+    return N * (N - 1) / 2.0 * (28.0 * M + 20.0 * N)
+
+
+def update_flops(a: int, b: int, c: int, k: int, sweeps: float) -> float:
+    """Algorithmic FP64 flops of one 2-site update: theta GEMM + gate mix,
+    `sweeps` Jacobi sweeps on the 2a x 2c theta, and the split GEMM."""
+    return 32.0 * a * b * c + 128.0 * a * c + sweeps * jacobi_flops(2 * a, 2 * c) + 32.0 * a * c * k
+
+
+def saturate(m, B, W, rng, max_layers=40):
+    sat_bonds = [b for b in range(N_QUBITS - 1) if min(CHI, 2 ** (b + 1), 2 ** (N_QUBITS - 1 - b)) == CHI]
+    t = 0
+    while t < max_layers:
+        m.apply_gates(W.brickwork_layer(N_QUBITS, t, rng))
+        t += 1
+        dims = m.bond_dims()
+        if all(dims[b] == CHI for b in sat_bonds):
+            break
+    return t
+
+
+def step_gates(W, rng, t):
+    layer = W.brickwork_layer(N_QUBITS, t, rng)
+    return [g for g in layer if 8 <= g.first <= 30]
+
+
+def run_variant(B, W, prec: int, steps: int, warmup: int):
+    rng = W.rng_for(SEED)
+    m = B.MPS(N_QUBITS, CHI, EPS, prec)
+    t = saturate(m, B, W, rng)
+    dims = m.bond_dims()
+    # warmup
+    for _ in range(warmup):
+        m.apply_gates(step_gates(W, rng, t), allow_noconv=True)
+        t += 1
+    m.sync()
+    m.set_option(B.MPS_OPT_KERNEL_TIMING, 1)
+    for c in range(len(B.KERNEL_CLASSES)):
+        m.kernel_time(c, reset=True)
+    ngates = 0
+    sweeps = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        gates = step_gates(W, rng, t)
+        for g in gates:
+            assert dims[g.first - 1] == dims[g.first] == dims[g.first + 1] == CHI
+        m.apply_gates(gates, allow_noconv=True)
+        sweeps.append(m.stats()["sweeps"])
+        ngates += len(gates)
+        t += 1
+    m.sync()
+    dt = time.perf_counter() - t0
+    ktimes = {name: m.kernel_time(c) for c, name in enumerate(B.KERNEL_CLASSES)}
+    dims = m.bond_dims()
+    lam_ok = all(abs(float((m.schmidt(b) ** 2).sum()) - 1.0) < 1e-12 for b in range(N_QUBITS - 1))
+    m.close()
+    return dict(rate=ngates / dt, ms_per_step=1e3 * dt / steps, gates=ngates, seconds=dt, sweeps=sweeps,
+                ktimes=ktimes, setup_layers=t - steps - warmup, lam_ok=lam_ok, dims_mid=dims[19])
+
+
+def roofline(res):
+    """Dominant kernel: the Jacobi step.  Algorithmic flops per launch = (updates in
+    the wave) x J(512, 512) / (steps per sweep); duration = HIP-event time / launches."""
+    ms, launches = res["ktimes"]["jacobi"]
+    if launches == 0:
+        return None
+    M = N = 2 * CHI
+    bw = 8
+    nb = N // bw
+    steps_per_sweep = nb + (nb & 1) - 1
+    per_wave = res["gates"] / len(res["sweeps"])
+    flops_per_launch = per_wave * jacobi_flops(M, N) / steps_per_sweep
+    avg_s = ms * 1e-3 / launches
+    achieved = flops_per_launch / avg_s
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64, "traffic": None, "kernel": "k_jacobi_step<8>",
+            "avg_launch_us": avg_s * 1e6, "launches": launches, "flops_per_launch": flops_per_launch}
+
+
+def cpu_baseline():
+    """The 256-bit oracle on the host cores: one two-site update at a = b = c = 128
+    (theta 256 x 256) of a seeded 40-qubit state, scaled to a = b = c = 256 by the
+    paper's O(m^3) cost of one U(4) update (x 8)."""
+    import oracle
+    from paper_1111_3124_amd import workloads as W
+    n, chi = N_QUBITS, 128
+    dims = [min(chi, 2 ** (b + 1), 2 ** (n - 1 - b)) for b in range(n - 1)]
+    rng = W.rng_for(1000)
+    Bt, lam = W.random_mps_B(dims, rng, spread=2.0)
+    om = oracle.OracleMPS(n, chi, EPS)
+    om.load(Bt, lam)
+    U = W.haar_unitary(4, rng)
+    t0 = time.perf_counter()
+    om.apply(19, 2, U)
+    dt = time.perf_counter() - t0
+    scale = (CHI / chi) ** 3
+    return {"value": 1.0 / (dt * scale), "unit": "gate updates/s", "cores": oracle.oracle_threads(),
+            "kind": "oracle",
+            "sample": f"1 two-site update at a=b=c={chi} (theta {2*chi}x{2*chi}), 256-bit MPFR, "
+                      f"{dt:.1f} s measured; scaled x{scale:.0f} to a=b=c={CHI} by the O(m^3) per-gate cost",
+            "measured_s": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--variants", default="auto", help="fp64, dd, both or auto")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one MI355X: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    from paper_1111_3124_amd import binding as B
+    from paper_1111_3124_amd import workloads as W
+
+    want = args.variants
+    dd_ok = True
+    try:
+        B.MPS(2, 2, 0.0, B.MPS_PREC_DD).close()
+    except B.MPSError:
+        dd_ok = False
+    if want == "auto":
+        want = "both" if dd_ok else "fp64"
+    results = {}
+    if want in ("fp64", "both"):
+        results["fp64"] = run_variant(B, W, B.MPS_PREC_FP64, args.steps, args.warmup)
+        print(f"# fp64: {results['fp64']['rate']:.1f} updates/s, sweeps {results['fp64']['sweeps']}",
+              file=sys.stderr, flush=True)
+    if want in ("dd", "both"):
+        results["dd"] = run_variant(B, W, B.MPS_PREC_DD, args.steps, args.warmup)
+        print(f"# dd: {results['dd']['rate']:.1f} updates/s, sweeps {results['dd']['sweeps']}",
+              file=sys.stderr, flush=True)
+    head = "dd" if "dd" in results else "fp64"
+    r = results[head]
+    line = {
+        "metric": METRIC,
+        "value": r["rate"],
+        "unit": "gate updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "dd" if head == "dd" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "40-qubit MPS, brickwork Haar U(4) layers on bonds 8..30 with "
+                               "a=b=c=256 (theta 512x512), chi_max=256, eps=1e-12, seed 2",
+                   "updates_per_step": r["gates"] / args.steps, "variant": head},
+        "variants": {k: {"value": v["rate"], "ms_per_step": v["ms_per_step"],
+                         "mean_sweeps": sum(v["sweeps"]) / len(v["sweeps"]),
+                         "kernel_ms": {n: t[0] for n, t in v["ktimes"].items()},
+                         "schmidt_normalised": v["lam_ok"]} for k, v in results.items()},
+        "roofline": roofline(r),
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -63,10 +63,12 @@ enum mps_precision {
 };
 
 enum mps_option {
-  MPS_OPT_MAX_SWEEPS = 1,     /* Jacobi sweep limit (default 40 FP64, 8 dd polish)       */
+  MPS_OPT_MAX_SWEEPS = 1,     /* Jacobi sweep limit (default 40 FP64, 16 dd polish)      */
   MPS_OPT_JACOBI_TOL = 2,     /* relative off-diagonal tolerance multiplier (default 1)  */
   MPS_OPT_KERNEL_TIMING = 3,  /* 1: time every kernel class with HIP events (see below)  */
-  MPS_OPT_RANK_FLOOR = 4      /* relative rank floor (default 2^-47 FP64, 2^-100 dd)      */
+  MPS_OPT_RANK_FLOOR = 4,     /* relative rank floor (default 2^-44 FP64, 2^-96 dd)       */
+  MPS_OPT_BLOCK_WIDTH = 5,    /* Jacobi column block width: 4, 8 (default) or 16          */
+  MPS_OPT_MAX_INNER = 6       /* inner Jacobi sweeps per block pair (default 12)          */
 };
 
 /* Diagnostics of the most recent split (the last one of a three-qubit gate). */
@@ -77,8 +79,10 @@ struct mps_update_stats {
   double epsdist;  /* relative distance of the eps decision from its boundary, +inf if eps = 0 */
   int k;           /* kept count                                                      */
   int rank;        /* values above the rank floor                                     */
-  int sweeps;      /* Jacobi sweeps of the last gate (FP64 + dd polish)                */
+  int sweeps;      /* FP64 Jacobi sweeps of the last gate's wave                       */
   int splits;      /* number of splits in the last gate (0, 1 or 2)                    */
+  int dd_sweeps;   /* dd polish sweeps of the last gate's wave (dd handles)            */
+  int reserved;
 };
 
 /* --- lifetime ------------------------------------------------------------------- */

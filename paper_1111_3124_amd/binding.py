@@ -24,6 +24,7 @@ MPS_OK, MPS_EINVAL, MPS_ERANGE, MPS_ENOMEM, MPS_EDEVICE, MPS_ENOCONV, MPS_ENONFI
     0, -1, -2, -3, -4, -5, -6, -7)
 MPS_PREC_FP64, MPS_PREC_DD = 0, 1
 MPS_OPT_MAX_SWEEPS, MPS_OPT_JACOBI_TOL, MPS_OPT_KERNEL_TIMING, MPS_OPT_RANK_FLOOR = 1, 2, 3, 4
+MPS_OPT_BLOCK_WIDTH, MPS_OPT_MAX_INNER = 5, 6
 KERNEL_CLASSES = ["theta", "jacobi", "truncate", "split", "gate1", "amplitude", "dd_refine"]
 
 _STATUS = {0: "MPS_OK", -1: "MPS_EINVAL", -2: "MPS_ERANGE", -3: "MPS_ENOMEM", -4: "MPS_EDEVICE",
@@ -38,7 +39,8 @@ class MPSError(RuntimeError):
 
 class mps_update_stats(C.Structure):
     _fields_ = [("W", C.c_double), ("w", C.c_double), ("gap", C.c_double), ("epsdist", C.c_double),
-                ("k", C.c_int), ("rank", C.c_int), ("sweeps", C.c_int), ("splits", C.c_int)]
+                ("k", C.c_int), ("rank", C.c_int), ("sweeps", C.c_int), ("splits", C.c_int),
+                ("dd_sweeps", C.c_int), ("reserved", C.c_int)]
 
 
 _dp = C.POINTER(C.c_double)

@@ -32,8 +32,21 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
+def build_dd_host(verbose: bool = False) -> str:
+    """Host (g++) build of the double-double header, for the CPU tests of its arithmetic."""
+    out = os.path.join(HERE, "libdd_host.so")
+    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+           os.path.join(CSRC, "dd_host.cpp"), "-o", out + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(out + ".tmp", out)
+    return out
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    build_dd_host(verbose)
     with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", OUT + ".tmp",

@@ -69,6 +69,8 @@ struct Task2 {
   double2* thu_lo;      // dd planes of the above (dd handles)
   double2* thw_lo;
   double2* V_lo;
+  double2* aux1;        // dd handles: N x N scratch (V^H V - I), binary64
+  double2* aux2;        // dd handles: N x N scratch (V (V^H V - I)), binary64
   double* sig2;         // N: squared column norms of W (from the Jacobi Gram diagonals)
   double* sig2_lo;
   int* perm;            // N: column order, sigma descending

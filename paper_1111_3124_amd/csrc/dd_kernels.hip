@@ -1,14 +1,716 @@
-// Double-double variants (not yet enabled: every entry reports unavailability).
+// Double-double refinement path of the two-site update (gfx950).
+//
+// The state lives in double-double (hi + lo planes).  Per update:
+//   theta, theta_w in dd                       [k_theta2_dd: dd GEMM + U epilogue]
+//   FP64 block Jacobi on round(theta_w)        [k_jacobi_step<BW> of kernels.hip] -> V0
+//   V <- V (I - E/2), E = V^H V - I, twice     [k_gram_dd + k_ns_fix] (Newton-Schulz step of
+//                                              the polar factor: orthogonality error squares)
+//   W = theta_w V in dd                        [k_wmul_dd]
+//   dd block Jacobi polish sweeps on (W, V)    [k_jacobi_step_dd]
+//   sort / truncate / renormalise in dd        [k_truncate_dd]
+//   B_{s+1}' = Z_k^H, B_s' = theta Z_k / nu    [k_split_*_dd]
+// No step divides by a Schmidt value (same gauge as the FP64 path).
+#include "dd.h"
 #include "dd_kernels.h"
+#include "gemm.h"
 
 namespace mpsk {
 
-bool dd_available() { return false; }
-hipError_t launch_gate1_dd(Task1*, int, long, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_theta2_dd(Task2*, int, int, int, hipStream_t) { return hipErrorNotSupported; }
-int run_dd_refine(Task2*, int, int, int, int, int, double, int*, int*, hipStream_t, int*, bool*) { return -1; }
-hipError_t launch_truncate_dd(Task2*, int, int, double, double, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_split_dd(Task2*, int, int, int, int, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_amplitude_dd(const AmpArgs&, const double2* const*, int, hipStream_t) { return hipErrorNotSupported; }
+using dd::cacc;
+using dd::cdd;
+using dd::ddr;
+
+__device__ __forceinline__ cdd ldc(const double2* hi, const double2* lo, long i) {
+  const double2 h = hi[i];
+  const double2 l = lo ? lo[i] : make_double2(0.0, 0.0);
+  return {{h.x, l.x}, {h.y, l.y}};
+}
+__device__ __forceinline__ void stc(double2* hi, double2* lo, long i, cdd v) {
+  hi[i] = make_double2(v.re.hi, v.im.hi);
+  lo[i] = make_double2(v.re.lo, v.im.lo);
+}
+__device__ __forceinline__ cdd czero() { return {{0.0, 0.0}, {0.0, 0.0}}; }
+__device__ __forceinline__ cacc cacc0() { return {{0.0, 0.0}, {0.0, 0.0}}; }
+__device__ __forceinline__ cdd ld_gate(const double2* U, const double2* Ul, int e) {
+  return {{U[e].x, Ul[e].x}, {U[e].y, Ul[e].y}};
+}
+
+// ------------------------------------------------------------------ dd GEMM tile
+// C (m x n) = A B with dd operands: 32 x 32 output tile per 256-thread block, a
+// 2 x 2 register block per thread, K slices of 16 staged through LDS as hi/lo planes.
+template <class Op>
+__device__ __forceinline__ void ddgemm_tile(const Op& op, int m, int n, int kd, int tm, int tn) {
+  __shared__ double2 Ah[16][33], Al[16][33], Bh[16][33], Bl[16][33];
+  const int tid = threadIdx.x;
+  const int tr = tid >> 4, tc = tid & 15;
+  cacc acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = cacc0();
+  for (int k0 = 0; k0 < kd; k0 += 16) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int e = tid + 256 * q;
+      int row, kk;
+      if (Op::kARowFast) { row = e & 31; kk = e >> 5; } else { kk = e & 15; row = e >> 4; }
+      const int gr = tm + row, gk = k0 + kk;
+      const cdd v = (gr < m && gk < kd) ? op.a(gr, gk) : czero();
+      Ah[kk][row] = make_double2(v.re.hi, v.im.hi);
+      Al[kk][row] = make_double2(v.re.lo, v.im.lo);
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int e = tid + 256 * q;
+      int col, kk;
+      if (Op::kBColFast) { col = e & 31; kk = e >> 5; } else { kk = e & 15; col = e >> 4; }
+      const int gc = tn + col, gk = k0 + kk;
+      const cdd v = (gc < n && gk < kd) ? op.b(gk, gc) : czero();
+      Bh[kk][col] = make_double2(v.re.hi, v.im.hi);
+      Bl[kk][col] = make_double2(v.re.lo, v.im.lo);
+    }
+    __syncthreads();
+    for (int kk = 0; kk < 16; ++kk) {
+      cdd av[2], bv[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const double2 h = Ah[kk][tr * 2 + i], l = Al[kk][tr * 2 + i];
+        av[i] = {{h.x, l.x}, {h.y, l.y}};
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const double2 h = Bh[kk][tc * 2 + j], l = Bl[kk][tc * 2 + j];
+        bv[j] = {{h.x, l.x}, {h.y, l.y}};
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) dd::cacc_fma(acc[i][j], av[i], bv[j]);
+    }
+    __syncthreads();
+  }
+  cdd out[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) out[i][j] = dd::cnorm(acc[i][j]);
+  op.epilogue(tm + tr * 2, tn + tc * 2, out);
+}
+
+// ------------------------------------------------------------------ single-site gate
+__global__ __launch_bounds__(256) void k_gate1_dd(Task1* tasks) {
+  const Task1& T = tasks[blockIdx.y];
+  const long nel = (long)T.a * T.b;
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < nel; e += (long)gridDim.x * 256) {
+    const int al = (int)(e / T.b), be = (int)(e - (long)al * T.b);
+    const long i0 = (long)(2 * al) * T.ld + be, i1 = i0 + T.ld;
+    const cdd x0 = ldc(T.B, T.B_lo, i0), x1 = ldc(T.B, T.B_lo, i1);
+    cacc y0 = cacc0(), y1 = cacc0();
+    dd::cacc_fma(y0, ld_gate(T.U, T.U_lo, 0), x0);
+    dd::cacc_fma(y0, ld_gate(T.U, T.U_lo, 1), x1);
+    dd::cacc_fma(y1, ld_gate(T.U, T.U_lo, 2), x0);
+    dd::cacc_fma(y1, ld_gate(T.U, T.U_lo, 3), x1);
+    stc(T.B, T.B_lo, i0, dd::cnorm(y0));
+    stc(T.B, T.B_lo, i1, dd::cnorm(y1));
+  }
+}
+
+// ------------------------------------------------------------------ theta (2 sites)
+// Same contraction as the FP64 k_theta2 (B-operand columns 2*gamma + j'), each
+// thread's 2 x 2 block is one (alpha, gamma) with its four (i', j') entries.
+struct ThetaOpDD {
+  static constexpr bool kARowFast = false;
+  static constexpr bool kBColFast = true;
+  const Task2* t;
+  __device__ cdd a(int row, int kk) const { return ldc(t->Bl, t->Bl_lo, (long)row * t->ldl + kk); }
+  __device__ cdd b(int kk, int col) const {
+    return ldc(t->Br, t->Br_lo, (long)(2 * kk + (col & 1)) * t->ldr + (col >> 1));
+  }
+  __device__ void epilogue(int r0, int c0, cdd (&T4)[2][2]) const {
+    const int al = r0 >> 1, ga = c0 >> 1, M = t->M;
+    double fro = 0.0;
+    if (al < t->a && ga < t->c) {
+      const ddr wl = {t->lamL[al], t->lamL_lo[al]};
+      cdd Tin[4] = {T4[0][0], T4[0][1], T4[1][0], T4[1][1]};
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          cacc o = cacc0();
+#pragma unroll
+          for (int q = 0; q < 4; ++q) dd::cacc_fma(o, ld_gate(t->U, t->U_lo, (i * 2 + j) * 4 + q), Tin[q]);
+          const cdd v = dd::cnorm(o);
+          const long idx = (long)(j * t->c + ga) * M + (2 * al + i);
+          stc(t->thu, t->thu_lo, idx, v);
+          const cdd w = dd::cscale(v, wl);
+          t->thw[idx] = make_double2(w.re.hi, w.im.hi);
+          fro += w.re.hi * w.re.hi + w.im.hi * w.im.hi;
+        }
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = fro;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(t->fro2, red[0]);
+  }
+};
+
+__global__ __launch_bounds__(256) void k_theta2_dd(Task2* tasks) {
+  const Task2* t = &tasks[blockIdx.z];
+  const int tm = blockIdx.x * 32, tn = blockIdx.y * 32;
+  if (tm >= t->M || tn >= t->N) return;
+  ThetaOpDD op{t};
+  ddgemm_tile(op, t->M, t->N, t->b, tm, tn);
+}
+
+// ------------------------------------------------------------------ Newton-Schulz
+// E = V^H V - I (dd accumulation, stored binary64: E is of the size of V's
+// orthogonality error, so its binary64 rounding is far below dd precision of V).
+struct GramOpDD {
+  static constexpr bool kARowFast = false;
+  static constexpr bool kBColFast = false;
+  const Task2* t;
+  __device__ cdd a(int row, int kk) const { return dd::cconj(ldc(t->V, t->V_lo, (long)row * t->N + kk)); }
+  __device__ cdd b(int kk, int col) const { return ldc(t->V, t->V_lo, (long)col * t->N + kk); }
+  __device__ void epilogue(int r0, int c0, cdd (&v)[2][2]) const {
+    const int N = t->N;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int r = r0 + i, c = c0 + j;
+        if (r >= N || c >= N) continue;
+        cdd e = v[i][j];
+        if (r == c) e.re = dd::add_d(e.re, -1.0);
+        t->aux1[(long)c * N + r] = make_double2(e.re.hi, e.im.hi);  // column-major
+      }
+  }
+};
+
+__global__ __launch_bounds__(256) void k_gram_dd(Task2* tasks) {
+  const Task2* t = &tasks[blockIdx.z];
+  const int tm = blockIdx.x * 32, tn = blockIdx.y * 32;
+  if (tm >= t->N || tn >= t->N) return;
+  GramOpDD op{t};
+  ddgemm_tile(op, t->N, t->N, t->N, tm, tn);
+}
+
+// C = V_hi E (binary64), into aux2
+struct NsOp {
+  static constexpr bool kARowFast = true;
+  static constexpr bool kBColFast = false;
+  const Task2* t;
+  __device__ double2 a(int row, int kk) const { return t->V[(long)kk * t->N + row]; }
+  __device__ double2 b(int kk, int col) const { return t->aux1[(long)col * t->N + kk]; }
+  __device__ void epilogue(int r0, int c0, double2 (&acc)[4][4]) const {
+    const int N = t->N;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = r0 + i, c = c0 + j;
+        if (r < N && c < N) t->aux2[(long)c * N + r] = acc[i][j];
+      }
+  }
+};
+
+__global__ __launch_bounds__(256) void k_ns_mul(Task2* tasks) {
+  const Task2* t = &tasks[blockIdx.z];
+  const int tm = blockIdx.x * 64, tn = blockIdx.y * 64;
+  if (tm >= t->N || tn >= t->N) return;
+  NsOp op{t};
+  cgemm_tile(op, t->N, t->N, t->N, tm, tn);
+}
+
+// V <- V - C / 2 (dd minus binary64)
+__global__ __launch_bounds__(256) void k_ns_fix(Task2* tasks) {
+  const Task2& T = tasks[blockIdx.y];
+  const long nn = (long)T.N * T.N;
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < nn; e += (long)gridDim.x * 256) {
+    cdd v = ldc(T.V, T.V_lo, e);
+    const double2 c = T.aux2[e];
+    v.re = dd::add_d(v.re, -0.5 * c.x);
+    v.im = dd::add_d(v.im, -0.5 * c.y);
+    stc(T.V, T.V_lo, e, v);
+  }
+}
+
+// promote V (binary64 from the FP64 Jacobi) to dd, clear the rotation flags
+__global__ __launch_bounds__(256) void k_promote(Task2* tasks) {
+  const Task2& T = tasks[blockIdx.y];
+  const long nn = (long)T.N * T.N;
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < nn; e += (long)gridDim.x * 256)
+    T.V_lo[e] = make_double2(0.0, 0.0);
+  if (blockIdx.x == 0 && threadIdx.x == 0) T.flags[0] = T.flags[1] = T.flags[2] = 0;
+}
+
+// ------------------------------------------------------------------ W = theta_w V
+struct WOpDD {
+  static constexpr bool kARowFast = true;
+  static constexpr bool kBColFast = false;
+  const Task2* t;
+  __device__ cdd a(int row, int kk) const {
+    const cdd x = ldc(t->thu, t->thu_lo, (long)kk * t->M + row);
+    const ddr w = {t->lamL[row >> 1], t->lamL_lo[row >> 1]};
+    return dd::cscale(x, w);
+  }
+  __device__ cdd b(int kk, int col) const { return ldc(t->V, t->V_lo, (long)col * t->N + kk); }
+  __device__ void epilogue(int r0, int c0, cdd (&v)[2][2]) const {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int r = r0 + i, c = c0 + j;
+        if (r < t->M && c < t->N) stc(t->thw, t->thw_lo, (long)c * t->M + r, v[i][j]);
+      }
+  }
+};
+
+__global__ __launch_bounds__(256) void k_wmul_dd(Task2* tasks) {
+  const Task2* t = &tasks[blockIdx.z];
+  const int tm = blockIdx.x * 32, tn = blockIdx.y * 32;
+  if (tm >= t->M || tn >= t->N) return;
+  WOpDD op{t};
+  ddgemm_tile(op, t->M, t->N, t->N, tm, tn);
+}
+
+// ------------------------------------------------------------------ dd Jacobi step
+// The block one-sided Jacobi step of kernels.hip in double-double: dd Gram of the
+// pair, dd two-sided Jacobi on it (rotation coefficients computed once per pair in
+// dd, so every rotation is unitary to dd precision), dd update of W and V.
+__device__ __forceinline__ int rrp(int i, int r, int np) { return i == 0 ? 0 : 1 + (i - 1 + r) % (np - 1); }
+__device__ __forceinline__ int rr_pos(int x, int r, int np) {
+  return x == 0 ? 0 : 1 + ((x - 1 - r) % (np - 1) + (np - 1)) % (np - 1);
+}
+
+__global__ __launch_bounds__(256) void k_jacobi_step_dd(Task2* tasks, int step, int sweep, double tol_mult,
+                                                         int maxin) {
+  constexpr int BW = 8, W2 = 16, TB = 2;
+  const Task2& T = tasks[blockIdx.y];
+  const int N = T.N, M = T.M;
+  const int nb = (N + BW - 1) / BW;
+  const int nbp = nb + (nb & 1);
+  const int pi = blockIdx.x;
+  if (step >= nbp - 1 || pi >= nbp / 2) return;
+  int* flags = T.flags;
+  const int tid = threadIdx.x;
+  if (step == 0 && pi == 0 && tid == 0) flags[(sweep + 1) % 3] = 0;
+  if (sweep > 0 && flags[(sweep + 2) % 3] == 0) return;
+
+  __shared__ int cols[W2];
+  __shared__ double2 Chh[64][W2 + 1], Chl[64][W2 + 1];
+  __shared__ cdd Gb[2][W2][W2 + 1];
+  __shared__ cdd Rb[2][W2][W2 + 1];
+  __shared__ cdd cal[W2], cbe[W2];  // per index: (X J)[:, x] = cal X[:, x] + cbe X[:, partner]
+  __shared__ int crot[W2];
+  __shared__ int swf[3];
+  __shared__ int any_rot;
+
+  const int I = rrp(pi, step, nbp), J = rrp(nbp - 1 - pi, step, nbp);
+  if (tid < W2) {
+    const int blk = tid < BW ? I : J;
+    const int c = blk * BW + (tid % BW);
+    cols[tid] = (blk < nb && c < N) ? c : -1;
+  }
+  if (tid < 3) swf[tid] = 0;
+  if (tid == 0) any_rot = 0;
+  __syncthreads();
+
+  const int wave = tid >> 6, lane = tid & 63;
+  const int bi = lane >> 3, bj = lane & 7;
+  cacc acc[TB][TB];
+#pragma unroll
+  for (int i = 0; i < TB; ++i)
+#pragma unroll
+    for (int j = 0; j < TB; ++j) acc[i][j] = cacc0();
+  for (int r0 = 0; r0 < M; r0 += 64) {
+    for (int e = tid; e < 64 * W2; e += 256) {
+      const int rr = e & 63, l = e >> 6;
+      const int c = cols[l], r = r0 + rr;
+      const bool ok = c >= 0 && r < M;
+      Chh[rr][l] = ok ? T.thw[(long)c * M + r] : make_double2(0.0, 0.0);
+      Chl[rr][l] = ok ? T.thw_lo[(long)c * M + r] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int rr = wave; rr < 64; rr += 4) {
+      cdd x[TB], y[TB];
+#pragma unroll
+      for (int i = 0; i < TB; ++i) {
+        const double2 h = Chh[rr][bi * TB + i], l = Chl[rr][bi * TB + i];
+        x[i] = {{h.x, l.x}, {h.y, l.y}};
+      }
+#pragma unroll
+      for (int j = 0; j < TB; ++j) {
+        const double2 h = Chh[rr][bj * TB + j], l = Chl[rr][bj * TB + j];
+        y[j] = {{h.x, l.x}, {h.y, l.y}};
+      }
+#pragma unroll
+      for (int i = 0; i < TB; ++i)
+#pragma unroll
+        for (int j = 0; j < TB; ++j) dd::cacc_fmac(acc[i][j], x[i], y[j]);
+    }
+    __syncthreads();
+  }
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int i = 0; i < TB; ++i)
+#pragma unroll
+        for (int j = 0; j < TB; ++j) {
+          const int gi = bi * TB + i, gj = bj * TB + j;
+          const cdd v = dd::cnorm(acc[i][j]);
+          Gb[0][gi][gj] = (w == 0) ? v : dd::cadd(Gb[0][gi][gj], v);
+        }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < W2 * W2; e += 256) {
+    const int i = e / W2, j = e % W2;
+    Rb[0][i][j] = {{i == j ? 1.0 : 0.0, 0.0}, {0.0, 0.0}};
+  }
+  const double tol = tol_mult * (double)(M > 16 ? M : 16) * 0x1p-101;
+  const double ztol = *T.fro2 * 0x1p-192;  // columns below 2^-96 ||theta|| are rounding noise
+  __syncthreads();
+
+  int cur = 0;
+  for (int isw = 0; isw < maxin; ++isw) {
+    if (tid == 0) swf[(isw + 1) % 3] = 0;
+    for (int rnd = 0; rnd < W2 - 1; ++rnd) {
+      // coefficients, one thread per pair
+      if (tid < W2 / 2) {
+        const int pa = rrp(tid, rnd, W2), pb = rrp(W2 - 1 - tid, rnd, W2);
+        const int p = pa < pb ? pa : pb, q = pa < pb ? pb : pa;
+        const cdd gpq = Gb[cur][p][q];
+        const ddr a = Gb[cur][p][p].re, b = Gb[cur][q][q].re;
+        const double gah = hypot(gpq.re.hi, gpq.im.hi);
+        const bool rot = cols[p] >= 0 && cols[q] >= 0 && a.hi > ztol && b.hi > ztol &&
+                         gah > tol * sqrt(a.hi * b.hi);
+        cdd alp = {{1.0, 0.0}, {0.0, 0.0}}, bep = czero(), alq = alp, beq = czero();
+        if (rot) {
+          const ddr ga = dd::sqrt(dd::add(dd::mul(gpq.re, gpq.re), dd::mul(gpq.im, gpq.im)));
+          const ddr zeta = dd::div(dd::sub(b, a), dd::mul_d(ga, 2.0));
+          const ddr az = zeta.hi < 0 ? dd::neg(zeta) : zeta;
+          const ddr root = dd::sqrt(dd::add_d(dd::mul(zeta, zeta), 1.0));
+          ddr t = dd::div(dd::from(1.0), dd::add(az, root));
+          if (zeta.hi < 0) t = dd::neg(t);
+          const ddr c = dd::div(dd::from(1.0), dd::sqrt(dd::add_d(dd::mul(t, t), 1.0)));
+          const ddr sn = dd::mul(t, c);
+          const cdd e = {dd::div(gpq.re, ga), dd::neg(dd::div(gpq.im, ga))};  // e^{-i phi}
+          alp = {c, {0.0, 0.0}};
+          bep = dd::cscale(e, dd::neg(sn));
+          alq = dd::cscale(e, c);
+          beq = {sn, {0.0, 0.0}};
+          swf[isw % 3] = 1;
+        }
+        cal[p] = alp; cbe[p] = bep; cal[q] = alq; cbe[q] = beq;
+        crot[p] = rot; crot[q] = rot;
+      }
+      __syncthreads();
+      {
+        const int i = tid / W2, j = tid % W2;
+        const int pi_ = rrp(W2 - 1 - rr_pos(i, rnd, W2), rnd, W2);
+        const int pj = rrp(W2 - 1 - rr_pos(j, rnd, W2), rnd, W2);
+        const cdd ai = cal[i], bi_ = cbe[i], aj = cal[j], bj_ = cbe[j];
+        const cdd (*G)[W2 + 1] = Gb[cur];
+        const cdd colj = dd::cadd(dd::cmul(aj, G[i][j]), dd::cmul(bj_, G[i][pj]));
+        const cdd colpj = dd::cadd(dd::cmul(aj, G[pi_][j]), dd::cmul(bj_, G[pi_][pj]));
+        cdd v = dd::cadd(dd::cmul(dd::cconj(ai), colj), dd::cmul(dd::cconj(bi_), colpj));
+        if (crot[i] && j == pi_) v = czero();
+        if (i == j) v.im = {0.0, 0.0};
+        const cdd rn = dd::cadd(dd::cmul(aj, Rb[cur][i][j]), dd::cmul(bj_, Rb[cur][i][pj]));
+        Gb[cur ^ 1][i][j] = v;
+        Rb[cur ^ 1][i][j] = rn;
+      }
+      cur ^= 1;
+      __syncthreads();
+    }
+    if (!swf[isw % 3]) break;
+    if (tid == 0) any_rot = 1;
+  }
+  __syncthreads();
+
+  if (any_rot) {
+    for (int pass = 0; pass < 2; ++pass) {
+      double2* Xh = pass ? T.V : T.thw;
+      double2* Xl = pass ? T.V_lo : T.thw_lo;
+      const int rows = pass ? N : M;
+      for (int r = tid; r < rows; r += 256) {
+        cdd x[W2];
+#pragma unroll
+        for (int l = 0; l < W2; ++l) x[l] = cols[l] >= 0 ? ldc(Xh, Xl, (long)cols[l] * rows + r) : czero();
+        for (int pc = 0; pc < W2; ++pc) {
+          cacc y = cacc0();
+#pragma unroll
+          for (int l = 0; l < W2; ++l) dd::cacc_fma(y, x[l], Rb[cur][l][pc]);
+          if (cols[pc] >= 0) stc(Xh, Xl, (long)cols[pc] * rows + r, dd::cnorm(y));
+        }
+      }
+    }
+    if (tid == 0) flags[sweep % 3] = 1;
+  }
+  if (tid < W2 && cols[tid] >= 0) {
+    T.sig2[cols[tid]] = Gb[cur][tid][tid].re.hi;
+    T.sig2_lo[cols[tid]] = Gb[cur][tid][tid].re.lo;
+  }
+}
+
+// ------------------------------------------------------------------ truncation (dd)
+__device__ __forceinline__ bool dd_before(ddr a, int ia, ddr b, int ib) {
+  return dd::lt(b, a) || (a.hi == b.hi && a.lo == b.lo && ia < ib);
+}
+
+__global__ __launch_bounds__(1024) void k_truncate_dd(Task2* tasks, int chi, double eps, double floor_rel) {
+  Task2& T = tasks[blockIdx.x];
+  const int N = T.N, M = T.M;
+  int P = 1;
+  while (P < N) P <<= 1;
+  __shared__ ddr key[kMaxSort];
+  __shared__ int idx[kMaxSort];
+  __shared__ ddr sc[kMaxSort];
+  __shared__ int s_rank, s_keps;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int j = tid; j < P; j += nt) {
+    if (j < N) {
+      ddr v = {T.sig2[j], T.sig2_lo[j]};
+      if (v.hi < 0) v = {0.0, 0.0};
+      key[j] = v;
+    } else {
+      key[j] = {-1.0, 0.0};
+    }
+    idx[j] = j;
+  }
+  if (tid == 0) { s_rank = 0; s_keps = N; }
+  __syncthreads();
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = tid; i < P; i += nt) {
+        const int l = i ^ stride;
+        if (l > i) {
+          const bool before = dd_before(key[i], idx[i], key[l], idx[l]);
+          const bool dir = (i & size) == 0;
+          if (dir != before) {
+            const ddr tk = key[i]; key[i] = key[l]; key[l] = tk;
+            const int ti = idx[i]; idx[i] = idx[l]; idx[l] = ti;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int j = tid; j < P; j += nt) sc[j] = j < N ? key[j] : ddr{0.0, 0.0};
+  __syncthreads();
+  for (int off = 1; off < P; off <<= 1) {
+    ddr v[kMaxSort / 1024];
+    int cnt = 0;
+    for (int j = tid; j < P; j += nt) v[cnt++] = (j + off < P) ? sc[j + off] : ddr{0.0, 0.0};
+    __syncthreads();
+    cnt = 0;
+    for (int j = tid; j < P; j += nt) { sc[j] = dd::add(sc[j], v[cnt]); ++cnt; }
+    __syncthreads();
+  }
+  const ddr W = sc[0];
+  const double s0 = sqrt(key[0].hi);
+  const ddr epsW = dd::mul_d(W, eps);
+  int myrank = 0;
+  for (int j = tid; j < N; j += nt) {
+    if (sqrt(key[j].hi) > floor_rel * s0) ++myrank;
+    const int kk = j + 1;
+    const ddr tailk = kk < N ? sc[kk] : ddr{0.0, 0.0};
+    if (!dd::lt(epsW, tailk)) atomicMin(&s_keps, kk);
+  }
+  atomicAdd(&s_rank, myrank);
+  __syncthreads();
+  int k = chi;
+  if (s_keps < k) k = s_keps;
+  if (s_rank < k) k = s_rank;
+  const int mn = M < N ? M : N;
+  if (mn < k) k = mn;
+  if (k < 1) k = 1;
+  const ddr tail = k < N ? sc[k] : ddr{0.0, 0.0};
+  const ddr nu = dd::sqrt(dd::sub(W, tail));
+  for (int j = tid; j < N; j += nt) {
+    T.perm[j] = idx[j];
+    if (j < k) {
+      const ddr l = dd::div(dd::sqrt(key[j]), nu);
+      T.lamS[j] = l.hi;
+      T.lamS_lo[j] = l.lo;
+    }
+  }
+  if (tid == 0) {
+    double* st = T.stats;
+    st[0] = W.hi;
+    st[1] = W.hi > 0 ? dd::div(tail, W).hi : 0.0;
+    st[2] = (k < s_rank) ? (dd::sub(dd::sqrt(key[k - 1]), dd::sqrt(key[k]))).hi / s0 : INFINITY;
+    double ed = INFINITY;
+    if (eps > 0) {
+      for (int kk = s_keps - 1; kk <= s_keps; ++kk) {
+        if (kk < 1 || kk > N) continue;
+        const ddr tk = kk < N ? sc[kk] : ddr{0.0, 0.0};
+        const double d = fabs(dd::sub(tk, epsW).hi) / epsW.hi;
+        ed = d < ed ? d : ed;
+      }
+    }
+    st[3] = ed;
+    st[4] = k;
+    st[5] = s_rank;
+    st[6] = nu.hi;
+    st[7] = nu.lo;
+    *T.dim_out = k;
+  }
+}
+
+// ------------------------------------------------------------------ split (dd)
+__global__ __launch_bounds__(256) void k_split_right_dd(Task2* tasks) {
+  const Task2& T = tasks[blockIdx.z];
+  const int k = *T.dim_out, N = T.N, c = T.c;
+  const int nu = blockIdx.y;
+  if (nu >= k) return;
+  const int col = T.perm[nu];
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < N; e += gridDim.x * 256) {
+    const int j = e / c, ga = e - j * c;
+    const cdd v = dd::cconj(ldc(T.V, T.V_lo, (long)col * N + e));
+    stc(T.Br, T.Br_lo, (long)(2 * nu + j) * T.ldr + ga, v);
+  }
+}
+
+struct SplitLeftOpDD {
+  static constexpr bool kARowFast = true;
+  static constexpr bool kBColFast = false;
+  const Task2* t;
+  int k;
+  ddr inv_nu;
+  __device__ cdd a(int row, int kk) const { return ldc(t->thu, t->thu_lo, (long)kk * t->M + row); }
+  __device__ cdd b(int kk, int col) const { return ldc(t->V, t->V_lo, (long)t->perm[col] * t->N + kk); }
+  __device__ void epilogue(int r0, int c0, cdd (&v)[2][2]) const {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int r = r0 + i, cc = c0 + j;
+        if (r < t->M && cc < k) stc(t->Bl, t->Bl_lo, (long)r * t->ldl + cc, dd::cscale(v[i][j], inv_nu));
+      }
+  }
+};
+
+__global__ __launch_bounds__(256) void k_split_left_dd(Task2* tasks) {
+  const Task2* t = &tasks[blockIdx.z];
+  const int k = *t->dim_out;
+  const int tm = blockIdx.x * 32, tn = blockIdx.y * 32;
+  if (tm >= t->M || tn >= k) return;
+  const ddr nu = {t->stats[6], t->stats[7]};
+  SplitLeftOpDD op{t, k, dd::div(dd::from(1.0), nu)};
+  ddgemm_tile(op, t->M, k, t->N, tm, tn);
+}
+
+// ------------------------------------------------------------------ amplitudes (dd)
+__global__ __launch_bounds__(256) void k_amplitude_dd(const AmpArgs args, const double2* const* Blo) {
+  __shared__ cdd v[1024], w[1024];
+  const int tid = threadIdx.x;
+  const unsigned char* bits = args.bits + (long)blockIdx.x * args.n;
+  if (tid == 0) v[0] = {{1.0, 0.0}, {0.0, 0.0}};
+  __syncthreads();
+  for (int s = 0; s < args.n; ++s) {
+    const int ml = args.dimx[s], mr = args.dimx[s + 1];
+    const int b = bits[s] ? 1 : 0;
+    const double2* Bh = args.B[s];
+    const double2* Bl = Blo[s];
+    const int ld = args.ld[s];
+    for (int be = tid; be < mr; be += 256) {
+      cacc acc = cacc0();
+      for (int al = 0; al < ml; ++al) dd::cacc_fma(acc, v[al], ldc(Bh, Bl, (long)(2 * al + b) * ld + be));
+      w[be] = dd::cnorm(acc);
+    }
+    __syncthreads();
+    for (int be = tid; be < mr; be += 256) v[be] = w[be];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double2* o = args.out + 2 * blockIdx.x;
+    o[0] = make_double2(v[0].re.hi, v[0].re.lo);
+    o[1] = make_double2(v[0].im.hi, v[0].im.lo);
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+#define MPS_LAUNCH_CHECK() \
+  do { hipError_t e_ = hipGetLastError(); if (e_ != hipSuccess) return e_; } while (0)
+
+bool dd_available() { return true; }
+
+static int grid_for(long n) {
+  long g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+hipError_t launch_gate1_dd(Task1* d_tasks, int ntask, long maxel, hipStream_t st) {
+  hipLaunchKernelGGL(k_gate1_dd, dim3(grid_for(maxel), ntask), dim3(256), 0, st, d_tasks);
+  MPS_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_theta2_dd(Task2* d_tasks, int ntask, int maxM, int maxN, hipStream_t st) {
+  hipLaunchKernelGGL(k_theta2_dd, dim3((maxM + 31) / 32, (maxN + 31) / 32, ntask), dim3(256), 0, st, d_tasks);
+  MPS_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+int run_dd_refine(Task2* d_tasks, int ntask, int maxM, int maxN, int max_sweeps, int maxin, double tol_mult,
+                  int* h_flags, int* d_flags, hipStream_t st, int* sweeps, bool* converged) {
+  const long nn = (long)maxN * maxN;
+  hipLaunchKernelGGL(k_promote, dim3(grid_for(nn), ntask), dim3(256), 0, st, d_tasks);
+  if (hipGetLastError() != hipSuccess) return -1;
+  for (int it = 0; it < 2; ++it) {
+    hipLaunchKernelGGL(k_gram_dd, dim3((maxN + 31) / 32, (maxN + 31) / 32, ntask), dim3(256), 0, st, d_tasks);
+    hipLaunchKernelGGL(k_ns_mul, dim3((maxN + 63) / 64, (maxN + 63) / 64, ntask), dim3(256), 0, st, d_tasks);
+    hipLaunchKernelGGL(k_ns_fix, dim3(grid_for(nn), ntask), dim3(256), 0, st, d_tasks);
+    if (hipGetLastError() != hipSuccess) return -1;
+  }
+  hipLaunchKernelGGL(k_wmul_dd, dim3((maxM + 31) / 32, (maxN + 31) / 32, ntask), dim3(256), 0, st, d_tasks);
+  if (hipGetLastError() != hipSuccess) return -1;
+  const int nb = (maxN + 7) / 8;
+  const int nbp = nb + (nb & 1);
+  *converged = false;
+  *sweeps = 0;
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    for (int stp = 0; stp < nbp - 1; ++stp)
+      hipLaunchKernelGGL(k_jacobi_step_dd, dim3(nbp / 2, ntask), dim3(256), 0, st, d_tasks, stp, sw, tol_mult, maxin);
+    if (hipGetLastError() != hipSuccess) return -1;
+    if (hipMemcpyAsync(h_flags, d_flags, sizeof(int) * 3 * ntask, hipMemcpyDeviceToHost, st) != hipSuccess) return -1;
+    if (hipStreamSynchronize(st) != hipSuccess) return -1;
+    *sweeps = sw + 1;
+    bool any = false;
+    for (int i = 0; i < ntask; ++i) any |= h_flags[3 * i + sw % 3] != 0;
+    if (!any) {
+      *converged = true;
+      break;
+    }
+  }
+  return 0;
+}
+
+hipError_t launch_truncate_dd(Task2* d_tasks, int ntask, int chi, double eps, double floor_rel, hipStream_t st) {
+  hipLaunchKernelGGL(k_truncate_dd, dim3(ntask), dim3(1024), 0, st, d_tasks, chi, eps, floor_rel);
+  MPS_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_split_dd(Task2* d_tasks, int ntask, int maxM, int maxN, int maxK, hipStream_t st) {
+  hipLaunchKernelGGL(k_split_right_dd, dim3((maxN + 255) / 256, maxK, ntask), dim3(256), 0, st, d_tasks);
+  MPS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_split_left_dd, dim3((maxM + 31) / 32, (maxK + 31) / 32, ntask), dim3(256), 0, st, d_tasks);
+  MPS_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_amplitude_dd(const AmpArgs& args, const double2* const* B_lo, int count, hipStream_t st) {
+  hipLaunchKernelGGL(k_amplitude_dd, dim3(count), dim3(256), 0, st, args, B_lo);
+  MPS_LAUNCH_CHECK();
+  return hipSuccess;
+}
 
 }  // namespace mpsk

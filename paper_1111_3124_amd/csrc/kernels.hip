@@ -12,60 +12,9 @@
 // the paper's Q_s' V_s' without ever dividing by a Schmidt value.
 #include "common.h"
 #include "launch.h"
+#include "gemm.h"
 
 namespace mpsk {
-
-// ------------------------------------------------------------------ complex GEMM tile
-// C (m x n) = A (m x kd) B (kd x n), one 64 x 64 output tile per 256-thread block,
-// each thread a 4 x 4 register block (rows tr*4.., columns tc*4..).  Operands are
-// staged through LDS in K slices of 16.  Op supplies the element loaders, which
-// index varies fastest across threads in each load (for coalescing), and the
-// epilogue that consumes the 4 x 4 block.
-template <class Op>
-__device__ __forceinline__ void cgemm_tile(const Op& op, int m, int n, int kd, int tm, int tn) {
-  __shared__ double2 As[16][64 + 1];
-  __shared__ double2 Bs[16][64 + 1];
-  const int tid = threadIdx.x;
-  const int tr = tid >> 4, tc = tid & 15;
-  double2 acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = cmk(0.0, 0.0);
-  for (int k0 = 0; k0 < kd; k0 += 16) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q;
-      int row, kk;
-      if (Op::kARowFast) { row = e & 63; kk = e >> 6; } else { kk = e & 15; row = e >> 4; }
-      const int gr = tm + row, gk = k0 + kk;
-      As[kk][row] = (gr < m && gk < kd) ? op.a(gr, gk) : cmk(0.0, 0.0);
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q;
-      int col, kk;
-      if (Op::kBColFast) { col = e & 63; kk = e >> 6; } else { kk = e & 15; col = e >> 4; }
-      const int gc = tn + col, gk = k0 + kk;
-      Bs[kk][col] = (gc < n && gk < kd) ? op.b(gk, gc) : cmk(0.0, 0.0);
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < 16; ++kk) {
-      double2 av[4], bv[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = As[kk][tr * 4 + i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][tc * 4 + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = cfma(av[i], bv[j], acc[i][j]);
-    }
-    __syncthreads();
-  }
-  op.epilogue(tm + tr * 4, tn + tc * 4, acc);
-}
 
 // ------------------------------------------------------------------ prep
 // V = I_N, zero the Frobenius accumulator and the rotation flags.
@@ -152,18 +101,61 @@ __global__ __launch_bounds__(256) void k_theta2(Task2* tasks) {
 // BW; the blocks are paired by the round-robin ("circle") schedule, so that the
 // 2*BW-column groups of one step are disjoint and all block pairs meet once per
 // sweep.  Each 256-thread block takes one pair of one task:
-//   1. G = A_P^H A_P (2BW x 2BW) from the pair's columns A_P of W (LDS row chunks);
-//   2. cyclic two-sided Jacobi on G in LDS, R accumulating the rotations
-//      (each rotation the complex symmetric Schur 2x2 of Golub & Van Loan 8.4/8.5,
-//      applied to columns then rows for the disjoint pairs of a round);
-//   3. A_P <- A_P R and V_P <- V_P R (row per thread), and sig2 <- diag(R^H G R).
+//   1. G = A_P^H A_P (W2 x W2, W2 = 2 BW) from the pair's columns A_P of W: row chunks
+//      staged in LDS, each wavefront a quarter of the rows, each lane a TB x TB
+//      register block of G;
+//   2. cyclic two-sided Jacobi on G in LDS, R accumulating the rotations.  Each
+//      rotation is the complex symmetric Schur 2x2 (Golub & Van Loan 8.4/8.5) for
+//      the pair's Gram entries.  The disjoint pairs of a round act as one unitary J;
+//      every thread forms its elements of J^H G J and R J directly from the
+//      2x2 neighbourhood of the old values (double-buffered: one barrier a round);
+//   3. A_P <- A_P R and V_P <- V_P R (a row per thread), sig2 <- diag(R^H G R).
 // A pair whose off-diagonal entries are all below tol * sqrt(G_pp G_qq) is left
 // alone; a task whose previous sweep rotated nothing is converged and skipped.
+__device__ __forceinline__ int rr_player(int i, int r, int np) { return i == 0 ? 0 : 1 + (i - 1 + r) % (np - 1); }
+// partner of index x in round r of the circle schedule on np players
+__device__ __forceinline__ int rr_partner(int x, int r, int np) {
+  const int pos = x == 0 ? 0 : 1 + ((x - 1 - r) % (np - 1) + (np - 1)) % (np - 1);
+  return rr_player(np - 1 - pos, r, np);
+}
+
+struct RotCoef {
+  double2 al, be;  // (X J)[:, x] = al X[:, x] + be X[:, partner(x)]
+  bool rot;
+};
+
+// rotation coefficients of index x (partner px) from the current Gram buffer
+template <int LD>
+__device__ __forceinline__ RotCoef rot_coef(const double2 (*G)[LD], const int* cols, int x, int px, double tol,
+                                            double ztol) {
+  RotCoef r;
+  r.al = cmk(1.0, 0.0);
+  r.be = cmk(0.0, 0.0);
+  r.rot = false;
+  const int p = x < px ? x : px, q = x < px ? px : x;
+  if (cols[p] < 0 || cols[q] < 0) return r;
+  const double a = G[p][p].x, b = G[q][q].x;
+  const double2 g = G[p][q];
+  const double ga = hypot(g.x, g.y);
+  if (!(a > ztol && b > ztol && ga > tol * sqrt(a * b))) return r;
+  const double zeta = (b - a) / (2.0 * ga);
+  const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double c = 1.0 / sqrt(1.0 + t * t);
+  const double sn = t * c;
+  const double2 e = cmk(g.x / ga, -g.y / ga);  // e^{-i phi}
+  r.rot = true;
+  if (x == p) { r.al = cmk(c, 0.0); r.be = cscale(e, -sn); }
+  else        { r.al = cscale(e, c); r.be = cmk(sn, 0.0); }
+  return r;
+}
+
 template <int BW>
 __global__ __launch_bounds__(256) void k_jacobi_step(Task2* tasks, int step, int sweep, double tol_mult,
                                                       int maxin) {
   constexpr int W2 = 2 * BW;
-  static_assert(W2 * W2 == 256, "one Gram entry per thread");
+  constexpr int TB = W2 / 8;          // register block edge of the Gram phase
+  constexpr int EPT = (W2 * W2 + 255) / 256;  // inner-phase elements per thread
+  static_assert(W2 == 8 || W2 == 16 || W2 == 32, "block width");
   const Task2& T = tasks[blockIdx.y];
   const int N = T.N, M = T.M;
   const int nb = (N + BW - 1) / BW;
@@ -179,27 +171,30 @@ __global__ __launch_bounds__(256) void k_jacobi_step(Task2* tasks, int step, int
 
   __shared__ int cols[W2];
   __shared__ double2 Ch[64][W2 + 1];
-  __shared__ double2 G[W2][W2 + 1];
-  __shared__ double2 R[W2][W2 + 1];
-  __shared__ double rc[W2 / 2], rs[W2 / 2];
-  __shared__ double2 rev[W2 / 2];
-  __shared__ int rp[W2 / 2], rq[W2 / 2], rf[W2 / 2];
-  __shared__ int any_rot, sweep_rot;
+  __shared__ double2 Gb[2][W2][W2 + 1];
+  __shared__ double2 Rb[2][W2][W2 + 1];
+  __shared__ int swf[3];
+  __shared__ int any_rot;
 
-  auto player = [&](int i, int r, int np) { return i == 0 ? 0 : 1 + (i - 1 + r) % (np - 1); };
-  const int I = player(pi, step, nbp), J = player(nbp - 1 - pi, step, nbp);
+  const int I = rr_player(pi, step, nbp), J = rr_player(nbp - 1 - pi, step, nbp);
   if (tid < W2) {
     const int blk = tid < BW ? I : J;
     const int c = blk * BW + (tid % BW);
     cols[tid] = (blk < nb && c < N) ? c : -1;
   }
+  if (tid < 3) swf[tid] = 0;
   if (tid == 0) any_rot = 0;
   __syncthreads();
 
+  // 1. Gram: wave g takes rows g, g+4, ... of each 64-row chunk; lane (bi, bj) a TB x TB block
   const double2* __restrict__ A = T.thw;
-  // 1. Gram of the pair
-  const int p = tid / W2, q = tid % W2;
-  double2 acc = cmk(0.0, 0.0);
+  const int wave = tid >> 6, lane = tid & 63;
+  const int bi = lane >> 3, bj = lane & 7;
+  double2 acc[TB][TB];
+#pragma unroll
+  for (int i = 0; i < TB; ++i)
+#pragma unroll
+    for (int j = 0; j < TB; ++j) acc[i][j] = cmk(0.0, 0.0);
   for (int r0 = 0; r0 < M; r0 += 64) {
     for (int e = tid; e < 64 * W2; e += 256) {
       const int rr = e & 63, l = e >> 6;
@@ -207,78 +202,89 @@ __global__ __launch_bounds__(256) void k_jacobi_step(Task2* tasks, int step, int
       Ch[rr][l] = (c >= 0 && r < M) ? A[(long)c * M + r] : cmk(0.0, 0.0);
     }
     __syncthreads();
-#pragma unroll 8
-    for (int rr = 0; rr < 64; ++rr) acc = cfmac(Ch[rr][p], Ch[rr][q], acc);
+#pragma unroll 4
+    for (int rr = wave; rr < 64; rr += 4) {
+      double2 x[TB], y[TB];
+#pragma unroll
+      for (int i = 0; i < TB; ++i) x[i] = Ch[rr][bi * TB + i];
+#pragma unroll
+      for (int j = 0; j < TB; ++j) y[j] = Ch[rr][bj * TB + j];
+#pragma unroll
+      for (int i = 0; i < TB; ++i)
+#pragma unroll
+        for (int j = 0; j < TB; ++j) acc[i][j] = cfmac(x[i], y[j], acc[i][j]);
+    }
     __syncthreads();
   }
-  G[p][q] = acc;
-  R[p][q] = cmk(p == q ? 1.0 : 0.0, 0.0);
+  // reduce the four waves' partial Grams into Gb[0] (one wave at a time: deterministic)
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int i = 0; i < TB; ++i)
+#pragma unroll
+        for (int j = 0; j < TB; ++j) {
+          const int gi = bi * TB + i, gj = bj * TB + j;
+          if (gi < W2 && gj < W2) Gb[0][gi][gj] = (w == 0) ? acc[i][j] : cadd(Gb[0][gi][gj], acc[i][j]);
+        }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < W2 * W2; e += 256) Rb[0][e / W2][e % W2] = cmk(e / W2 == e % W2 ? 1.0 : 0.0, 0.0);
   const double tol = tol_mult * (double)(M > 16 ? M : 16) * 0x1p-53;
-  const double ztol = *T.fro2 * 0x1p-96;
+  const double ztol = *T.fro2 * 0x1p-88;  // columns below 2^-44 ||theta|| are rounding noise
   __syncthreads();
 
-  // 2. two-sided Jacobi on G (W2 x W2 Hermitian)
+  // 2. two-sided Jacobi on G, one barrier per round
+  int cur = 0;
   for (int isw = 0; isw < maxin; ++isw) {
-    if (tid == 0) sweep_rot = 0;
-    __syncthreads();
+    // slot isw%3 is written this sweep and read after its last barrier; slot
+    // (isw+1)%3 was last read two sweeps ago (many barriers back): clear it now
+    if (tid == 0) swf[(isw + 1) % 3] = 0;
     for (int rnd = 0; rnd < W2 - 1; ++rnd) {
-      if (tid < W2 / 2) {
-        const int pa = player(tid, rnd, W2), pb = player(W2 - 1 - tid, rnd, W2);
-        const int pp = pa < pb ? pa : pb, qq = pa < pb ? pb : pa;
-        const double al = G[pp][pp].x, be = G[qq][qq].x;
-        const double2 g = G[pp][qq];
-        const double gabs = hypot(g.x, g.y);
-        int rot = cols[pp] >= 0 && cols[qq] >= 0 && al > ztol && be > ztol && gabs > tol * sqrt(al * be);
-        rp[tid] = pp; rq[tid] = qq; rf[tid] = rot;
-        if (rot) {
-          const double zeta = (be - al) / (2.0 * gabs);
-          const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double c = 1.0 / sqrt(1.0 + t * t);
-          rc[tid] = c;
-          rs[tid] = t * c;
-          rev[tid] = cmk(g.x / gabs, -g.y / gabs);  // e^{-i phi}
-          sweep_rot = 1;
-        }
+      const double2(*G)[W2 + 1] = Gb[cur];
+      const double2(*R)[W2 + 1] = Rb[cur];
+      double2 gn[EPT], rn[EPT];
+      int ei[EPT], ej[EPT];
+      bool any = false;
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const int e = tid + 256 * q;
+        ei[q] = -1;
+        if (e >= W2 * W2) continue;
+        const int i = e / W2, j = e % W2;
+        ei[q] = i; ej[q] = j;
+        const int pi_ = rr_partner(i, rnd, W2), pj = rr_partner(j, rnd, W2);
+        const RotCoef ci = rot_coef<W2 + 1>(G, cols, i, pi_, tol, ztol);
+        const RotCoef cj = (pj == pi_ && j == i) ? ci : rot_coef<W2 + 1>(G, cols, j, pj, tol, ztol);
+        any |= ci.rot;
+        // (J^H G J)_{ij} and (R J)_{ij}
+        const double2 gij = G[i][j], gipj = G[i][pj], gpij = G[pi_][j], gpipj = G[pi_][pj];
+        const double2 colj = cadd(cmul(cj.al, gij), cmul(cj.be, gipj));
+        const double2 colpj = cadd(cmul(cj.al, gpij), cmul(cj.be, gpipj));
+        double2 v = cadd(cmul(cconj(ci.al), colj), cmul(cconj(ci.be), colpj));
+        if (ci.rot && j == pi_) v = cmk(0.0, 0.0);  // the rotated pair's off-diagonal is zero
+        if (i == j) v.y = 0.0;
+        gn[q] = v;
+        rn[q] = cadd(cmul(cj.al, R[i][j]), cmul(cj.be, R[i][pj]));
       }
-      __syncthreads();
-      {  // columns p, q of G (threads 0..127) and of R (threads 128..255)
-        const int pr = (tid >> 4) & 7, row = tid & 15;
-        if (pr < W2 / 2 && rf[pr]) {
-          double2(*X)[W2 + 1] = (tid >> 7) ? R : G;
-          const int pp = rp[pr], qq = rq[pr];
-          const double c = rc[pr], s = rs[pr];
-          const double2 x = X[row][pp], y = X[row][qq];
-          const double2 ey = cmul(rev[pr], y);
-          X[row][pp] = csub(cscale(x, c), cscale(ey, s));
-          X[row][qq] = cadd(cscale(x, s), cscale(ey, c));
+      if (any) swf[isw % 3] = 1;
+#pragma unroll
+      for (int q = 0; q < EPT; ++q)
+        if (ei[q] >= 0) {
+          Gb[cur ^ 1][ei[q]][ej[q]] = gn[q];
+          Rb[cur ^ 1][ei[q]][ej[q]] = rn[q];
         }
-      }
-      __syncthreads();
-      if (tid < 128) {  // rows p, q of G:  G <- J^H G
-        const int pr = tid >> 4, col = tid & 15;
-        if (pr < W2 / 2 && rf[pr]) {
-          const int pp = rp[pr], qq = rq[pr];
-          const double c = rc[pr], s = rs[pr];
-          const double2 x = G[pp][col], y = G[qq][col];
-          const double2 ey = cmul(cconj(rev[pr]), y);
-          double2 np_ = csub(cscale(x, c), cscale(ey, s));
-          double2 nq_ = cadd(cscale(x, s), cscale(ey, c));
-          if (col == qq) np_ = cmk(0.0, 0.0);
-          if (col == pp) { nq_ = cmk(0.0, 0.0); np_.y = 0.0; }
-          if (col == qq) nq_.y = 0.0;
-          G[pp][col] = np_;
-          G[qq][col] = nq_;
-        }
-      }
+      cur ^= 1;
       __syncthreads();
     }
-    if (!sweep_rot) break;
+    if (!swf[isw % 3]) break;
     if (tid == 0) any_rot = 1;
   }
   __syncthreads();
 
   // 3. apply R to the pair's columns of W and V
   if (any_rot) {
+    const double2(*R)[W2 + 1] = Rb[cur];
     double2* __restrict__ Aw = T.thw;
     double2* __restrict__ Vw = T.V;
     for (int pass = 0; pass < 2; ++pass) {
@@ -288,7 +294,7 @@ __global__ __launch_bounds__(256) void k_jacobi_step(Task2* tasks, int step, int
         double2 x[W2];
 #pragma unroll
         for (int l = 0; l < W2; ++l) x[l] = cols[l] >= 0 ? X[(long)cols[l] * rows + r] : cmk(0.0, 0.0);
-#pragma unroll
+#pragma unroll 4
         for (int pc = 0; pc < W2; ++pc) {
           double2 y = cmk(0.0, 0.0);
 #pragma unroll
@@ -299,7 +305,7 @@ __global__ __launch_bounds__(256) void k_jacobi_step(Task2* tasks, int step, int
     }
     if (tid == 0) flags[sweep % 3] = 1;
   }
-  if (tid < W2 && cols[tid] >= 0) T.sig2[cols[tid]] = G[tid][tid].x;
+  if (tid < W2 && cols[tid] >= 0) T.sig2[cols[tid]] = Gb[cur][tid][tid].x;
 }
 
 // ------------------------------------------------------------------ truncation
@@ -508,15 +514,17 @@ hipError_t launch_theta2(Task2* d_tasks, int ntask, int maxM, int maxN, hipStrea
   return hipSuccess;
 }
 
-int jacobi_block_width() { return 8; }
-
-hipError_t launch_jacobi_step(Task2* d_tasks, int ntask, int maxN, int step, int sweep, double tol_mult,
+hipError_t launch_jacobi_step(Task2* d_tasks, int ntask, int maxN, int bw, int step, int sweep, double tol_mult,
                               int maxin, hipStream_t st) {
-  constexpr int BW = 8;
-  const int nb = (maxN + BW - 1) / BW;
+  const int nb = (maxN + bw - 1) / bw;
   const int nbp = nb + (nb & 1);
-  hipLaunchKernelGGL(k_jacobi_step<BW>, dim3(nbp / 2, ntask), dim3(256), 0, st, d_tasks, step, sweep,
-                     tol_mult, maxin);
+  const dim3 grid(nbp / 2, ntask);
+  switch (bw) {
+    case 4: hipLaunchKernelGGL(k_jacobi_step<4>, grid, dim3(256), 0, st, d_tasks, step, sweep, tol_mult, maxin); break;
+    case 8: hipLaunchKernelGGL(k_jacobi_step<8>, grid, dim3(256), 0, st, d_tasks, step, sweep, tol_mult, maxin); break;
+    case 16: hipLaunchKernelGGL(k_jacobi_step<16>, grid, dim3(256), 0, st, d_tasks, step, sweep, tol_mult, maxin); break;
+    default: return hipErrorInvalidValue;
+  }
   MPS_LAUNCH_CHECK();
   return hipSuccess;
 }

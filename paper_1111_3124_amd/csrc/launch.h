@@ -15,8 +15,7 @@ struct AmpArgs {
 
 hipError_t launch_prep2(Task2* d_tasks, int ntask, int maxN, hipStream_t st);
 hipError_t launch_theta2(Task2* d_tasks, int ntask, int maxM, int maxN, hipStream_t st);
-int jacobi_block_width();
-hipError_t launch_jacobi_step(Task2* d_tasks, int ntask, int maxN, int step, int sweep, double tol_mult,
+hipError_t launch_jacobi_step(Task2* d_tasks, int ntask, int maxN, int bw, int step, int sweep, double tol_mult,
                               int maxin, hipStream_t st);
 hipError_t launch_truncate(Task2* d_tasks, int ntask, int chi, double eps, double floor_rel, hipStream_t st);
 hipError_t launch_split(Task2* d_tasks, int ntask, int maxM, int maxN, int maxK, hipStream_t st);

@@ -28,6 +28,7 @@ thread_local std::string g_create_error;
 struct EvPair {
   hipEvent_t a, b;
   int cls;
+  int n;
 };
 
 }  // namespace
@@ -46,11 +47,12 @@ struct mps_state {
   double* d_lam_lo = nullptr;
   // options
   int max_sweeps = 40;
-  int max_sweeps_dd = 8;
+  int max_sweeps_dd = 16;
   int max_inner = 12;
+  int block_width = 8;
   double tol_mult = 1.0;
-  double rank_floor = 0x1p-47;
-  double rank_floor_dd = 0x1p-100;
+  double rank_floor = 0x1p-44;
+  double rank_floor_dd = 0x1p-96;
   bool timing = false;
   // workspace
   char* ws = nullptr;
@@ -110,11 +112,13 @@ struct Timed {
   mps_state* h;
   EvPair p{};
   bool on;
-  Timed(mps_state* hh, int cls) : h(hh), on(hh->timing) {
+  // `launches` kernels are enqueued between the two events
+  Timed(mps_state* hh, int cls, int launches = 1) : h(hh), on(hh->timing) {
     if (on) {
       p.a = ev_get(h);
       p.b = ev_get(h);
       p.cls = cls;
+      p.n = launches;
       (void)hipEventRecord(p.a, h->stream);
     }
   }
@@ -132,7 +136,7 @@ void harvest_timing(mps_state* h) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
       h->tms[p.cls] += ms;
-      h->tcount[p.cls] += 1;
+      h->tcount[p.cls] += p.n;
     }
     h->evpool.push_back(p.a);
     h->evpool.push_back(p.b);
@@ -246,7 +250,7 @@ int run_wave2(mps_state* h, const std::vector<GateRef>& g2) {
     maxN = std::max(maxN, N);
     size_t cplx = (size_t)2 * M * N + (size_t)N * N;
     size_t bytes = align_up(cplx * sizeof(double2)) * (dd ? 2 : 1) + align_up(N * sizeof(double)) * (dd ? 2 : 1) +
-                   align_up(N * sizeof(int));
+                   align_up(N * sizeof(int)) + (dd ? 2 * align_up((size_t)N * N * sizeof(double2)) : 0);
     off[i + 1] = off[i] + bytes;
   }
   int rc = ensure_ws(h, off[nt]);
@@ -299,6 +303,10 @@ int run_wave2(mps_state* h, const std::vector<GateRef>& g2) {
       t.thw_lo = t.thu_lo + MN;
       t.V_lo = t.thw_lo + MN;
       w += align_up((2 * MN + NN) * sizeof(double2));
+      t.aux1 = (double2*)w;
+      w += align_up(NN * sizeof(double2));
+      t.aux2 = (double2*)w;
+      w += align_up(NN * sizeof(double2));
     }
     t.sig2 = (double*)w;
     w += align_up(t.N * sizeof(double));
@@ -323,7 +331,7 @@ int run_wave2(mps_state* h, const std::vector<GateRef>& g2) {
     if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("theta: ") + hipGetErrorString(e));
   }
   // Jacobi sweeps on the FP64 (hi) part of theta_w
-  const int bw = mpsk::jacobi_block_width();
+  const int bw = h->block_width;
   const int nb = (maxN + bw - 1) / bw;
   const int nsteps = nb + (nb & 1) - 1;
   int* hflags = (int*)(h->h_stage + o_flags);
@@ -331,9 +339,9 @@ int run_wave2(mps_state* h, const std::vector<GateRef>& g2) {
   bool converged = false;
   for (int sw = 0; sw < h->max_sweeps; ++sw) {
     {
-      Timed tm(h, 1);
+      Timed tm(h, 1, nsteps);
       for (int st = 0; st < nsteps; ++st) {
-        e = mpsk::launch_jacobi_step(dt, nt, maxN, st, sw, h->tol_mult, h->max_inner, h->stream);
+        e = mpsk::launch_jacobi_step(dt, nt, maxN, bw, st, sw, h->tol_mult, h->max_inner, h->stream);
         if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("jacobi: ") + hipGetErrorString(e));
       }
     }
@@ -384,9 +392,11 @@ int run_wave2(mps_state* h, const std::vector<GateRef>& g2) {
   h->last.epsdist = st[3];
   h->last.k = (int)st[4];
   h->last.rank = (int)st[5];
-  h->last.sweeps = sweeps + dd_sweeps;
+  h->last.sweeps = sweeps;
+  h->last.dd_sweeps = dd_sweeps;
   h->last.splits = 1;
-  if (!converged || !dd_conv) return fail(h, MPS_ENOCONV, "Jacobi sweep limit reached");
+  // a dd handle's result is the dd polish: its convergence is what counts
+  if (dd ? !dd_conv : !converged) return fail(h, MPS_ENOCONV, "Jacobi sweep limit reached");
   return MPS_OK;
 }
 
@@ -727,6 +737,14 @@ int mps_set_option(mps_handle h, int key, double value) {
       return MPS_OK;
     case MPS_OPT_KERNEL_TIMING:
       h->timing = value != 0;
+      return MPS_OK;
+    case MPS_OPT_BLOCK_WIDTH:
+      if (!(value == 4 || value == 8 || value == 16)) return fail(h, MPS_EINVAL, "block width must be 4, 8 or 16");
+      h->block_width = (int)value;
+      return MPS_OK;
+    case MPS_OPT_MAX_INNER:
+      if (!(value >= 1 && value <= 64)) return fail(h, MPS_EINVAL, "inner sweep limit out of range");
+      h->max_inner = (int)value;
       return MPS_OK;
     case MPS_OPT_RANK_FLOOR:
       if (!(value >= 0 && value < 1)) return fail(h, MPS_EINVAL, "rank floor out of range");
