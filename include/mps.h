@@ -68,7 +68,7 @@ enum mps_option {
   MPS_OPT_KERNEL_TIMING = 3,  /* 1: time every kernel class with HIP events (see below)  */
   MPS_OPT_RANK_FLOOR = 4,     /* relative rank floor (default 2^-44 FP64, 2^-96 dd)       */
   MPS_OPT_BLOCK_WIDTH = 5,    /* Jacobi column block width: 4, 8 (default) or 16          */
-  MPS_OPT_MAX_INNER = 6       /* inner Jacobi sweeps per block pair (default 12)          */
+  MPS_OPT_MAX_INNER = 6       /* inner sweeps per block pair, tasks with >= 16 blocks (1)  */
 };
 
 /* Diagnostics of the most recent split (the last one of a three-qubit gate). */

@@ -659,7 +659,8 @@ hipError_t launch_theta2_dd(Task2* d_tasks, int ntask, int maxM, int maxN, hipSt
   return hipSuccess;
 }
 
-int run_dd_refine(Task2* d_tasks, int ntask, int maxM, int maxN, int max_sweeps, int maxin, double tol_mult,
+int run_dd_refine(Task2* d_tasks, int ntask, int maxM, int maxN, int max_sweeps, int /*maxin: the polish always
+                  diagonalises each pair's nearly diagonal Gram fully (it exits early)*/, double tol_mult,
                   int* h_flags, int* d_flags, hipStream_t st, int* sweeps, bool* converged) {
   const long nn = (long)maxN * maxN;
   hipLaunchKernelGGL(k_promote, dim3(grid_for(nn), ntask), dim3(256), 0, st, d_tasks);
@@ -678,7 +679,7 @@ int run_dd_refine(Task2* d_tasks, int ntask, int maxM, int maxN, int max_sweeps,
   *sweeps = 0;
   for (int sw = 0; sw < max_sweeps; ++sw) {
     for (int stp = 0; stp < nbp - 1; ++stp)
-      hipLaunchKernelGGL(k_jacobi_step_dd, dim3(nbp / 2, ntask), dim3(256), 0, st, d_tasks, stp, sw, tol_mult, maxin);
+      hipLaunchKernelGGL(k_jacobi_step_dd, dim3(nbp / 2, ntask), dim3(256), 0, st, d_tasks, stp, sw, tol_mult, 12);
     if (hipGetLastError() != hipSuccess) return -1;
     if (hipMemcpyAsync(h_flags, d_flags, sizeof(int) * 3 * ntask, hipMemcpyDeviceToHost, st) != hipSuccess) return -1;
     if (hipStreamSynchronize(st) != hipSuccess) return -1;

@@ -234,9 +234,12 @@ __global__ __launch_bounds__(256) void k_jacobi_step(Task2* tasks, int step, int
   const double ztol = *T.fro2 * 0x1p-88;  // columns below 2^-44 ||theta|| are rounding noise
   __syncthreads();
 
-  // 2. two-sided Jacobi on G, one barrier per round
+  // 2. two-sided Jacobi on G, one barrier per round.  With many column blocks a
+  // single inner sweep per step is enough (the next steps revisit every column);
+  // with few blocks each pair must be diagonalised fully.
+  const int inner = nbp >= 16 ? maxin : 12;
   int cur = 0;
-  for (int isw = 0; isw < maxin; ++isw) {
+  for (int isw = 0; isw < inner; ++isw) {
     // slot isw%3 is written this sweep and read after its last barrier; slot
     // (isw+1)%3 was last read two sweeps ago (many barriers back): clear it now
     if (tid == 0) swf[(isw + 1) % 3] = 0;

@@ -48,7 +48,7 @@ struct mps_state {
   // options
   int max_sweeps = 40;
   int max_sweeps_dd = 16;
-  int max_inner = 12;
+  int max_inner = 1;
   int block_width = 8;
   double tol_mult = 1.0;
   double rank_floor = 0x1p-44;
