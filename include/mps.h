@@ -168,7 +168,10 @@ int mps_sync(mps_handle h);
 /* With MPS_OPT_KERNEL_TIMING on, accumulated device time (ms, from HIP events
  * recorded on the handle's stream around each launch) and launch count of kernel
  * class `cls` (0 theta, 1 jacobi step, 2 truncate, 3 split, 4 single-site gate,
- * 5 amplitude, 6 dd refinement); reset = 1 clears the counters after reading. */
+ * 5 amplitude, 6 dd refinement); reset = 1 clears the counters after reading.
+ * cls 8 / 9 are counters (always on): *launches receives the number of
+ * update-sweeps executed by the FP64 Jacobi / the dd polish (one update taking
+ * one sweep counts 1), *ms receives 0. */
 int mps_kernel_time(mps_handle h, int cls, double* ms, long* launches, int reset);
 
 /* Message for the last error on h (h may be NULL: the last error of mps_create*). */

@@ -79,6 +79,13 @@ struct Task2 {
   int* flags;           // 2 ints: rotation flags of the current / previous sweep
 };
 
+// One entry of a launch list: the task slot a block row works on and, for the
+// Jacobi steps, the slot's current sweep index.
+struct Ent {
+  int slot;
+  int sweep;
+};
+
 // One single-site gate.
 struct Task1 {
   double2* B;

@@ -7,12 +7,13 @@ namespace mpsk {
 
 bool dd_available();
 hipError_t launch_gate1_dd(Task1* d_tasks, int ntask, long maxel, hipStream_t st);
-hipError_t launch_theta2_dd(Task2* d_tasks, int ntask, int maxM, int maxN, hipStream_t st);
-// Refine the FP64 Jacobi result in double-double: returns 0 on success.
-int run_dd_refine(Task2* d_tasks, int ntask, int maxM, int maxN, int max_sweeps, int maxin, double tol_mult,
-                  int* h_flags, int* d_flags, hipStream_t st, int* sweeps, bool* converged);
-hipError_t launch_truncate_dd(Task2* d_tasks, int ntask, int chi, double eps, double floor_rel, hipStream_t st);
-hipError_t launch_split_dd(Task2* d_tasks, int ntask, int maxM, int maxN, int maxK, hipStream_t st);
+hipError_t launch_theta2_dd(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, int maxN, hipStream_t st);
+hipError_t launch_dd_enter(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, int maxN, hipStream_t st);
+hipError_t launch_jacobi_step_dd(Task2* d_tasks, const Ent* d_ents, int nent, int maxN, int step, double tol_mult,
+                                 int maxin, hipStream_t st);
+hipError_t launch_truncate_dd(Task2* d_tasks, const Ent* d_ents, int nent, int chi, double eps, double floor_rel,
+                              hipStream_t st);
+hipError_t launch_split_dd(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, int maxN, int maxK, hipStream_t st);
 hipError_t launch_amplitude_dd(const AmpArgs& args, const double2* const* B_lo, int count, hipStream_t st);
 
 }  // namespace mpsk

@@ -158,8 +158,8 @@ struct ThetaOpDD {
   }
 };
 
-__global__ __launch_bounds__(256) void k_theta2_dd(Task2* tasks) {
-  const Task2* t = &tasks[blockIdx.z];
+__global__ __launch_bounds__(256) void k_theta2_dd(Task2* tasks, const Ent* ents) {
+  const Task2* t = &tasks[ents[blockIdx.z].slot];
   const int tm = blockIdx.x * 32, tn = blockIdx.y * 32;
   if (tm >= t->M || tn >= t->N) return;
   ThetaOpDD op{t};
@@ -190,8 +190,8 @@ struct GramOpDD {
   }
 };
 
-__global__ __launch_bounds__(256) void k_gram_dd(Task2* tasks) {
-  const Task2* t = &tasks[blockIdx.z];
+__global__ __launch_bounds__(256) void k_gram_dd(Task2* tasks, const Ent* ents) {
+  const Task2* t = &tasks[ents[blockIdx.z].slot];
   const int tm = blockIdx.x * 32, tn = blockIdx.y * 32;
   if (tm >= t->N || tn >= t->N) return;
   GramOpDD op{t};
@@ -217,8 +217,8 @@ struct NsOp {
   }
 };
 
-__global__ __launch_bounds__(256) void k_ns_mul(Task2* tasks) {
-  const Task2* t = &tasks[blockIdx.z];
+__global__ __launch_bounds__(256) void k_ns_mul(Task2* tasks, const Ent* ents) {
+  const Task2* t = &tasks[ents[blockIdx.z].slot];
   const int tm = blockIdx.x * 64, tn = blockIdx.y * 64;
   if (tm >= t->N || tn >= t->N) return;
   NsOp op{t};
@@ -226,8 +226,8 @@ __global__ __launch_bounds__(256) void k_ns_mul(Task2* tasks) {
 }
 
 // V <- V - C / 2 (dd minus binary64)
-__global__ __launch_bounds__(256) void k_ns_fix(Task2* tasks) {
-  const Task2& T = tasks[blockIdx.y];
+__global__ __launch_bounds__(256) void k_ns_fix(Task2* tasks, const Ent* ents) {
+  const Task2& T = tasks[ents[blockIdx.y].slot];
   const long nn = (long)T.N * T.N;
   for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < nn; e += (long)gridDim.x * 256) {
     cdd v = ldc(T.V, T.V_lo, e);
@@ -239,8 +239,8 @@ __global__ __launch_bounds__(256) void k_ns_fix(Task2* tasks) {
 }
 
 // promote V (binary64 from the FP64 Jacobi) to dd, clear the rotation flags
-__global__ __launch_bounds__(256) void k_promote(Task2* tasks) {
-  const Task2& T = tasks[blockIdx.y];
+__global__ __launch_bounds__(256) void k_promote(Task2* tasks, const Ent* ents) {
+  const Task2& T = tasks[ents[blockIdx.y].slot];
   const long nn = (long)T.N * T.N;
   for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < nn; e += (long)gridDim.x * 256)
     T.V_lo[e] = make_double2(0.0, 0.0);
@@ -269,8 +269,8 @@ struct WOpDD {
   }
 };
 
-__global__ __launch_bounds__(256) void k_wmul_dd(Task2* tasks) {
-  const Task2* t = &tasks[blockIdx.z];
+__global__ __launch_bounds__(256) void k_wmul_dd(Task2* tasks, const Ent* ents) {
+  const Task2* t = &tasks[ents[blockIdx.z].slot];
   const int tm = blockIdx.x * 32, tn = blockIdx.y * 32;
   if (tm >= t->M || tn >= t->N) return;
   WOpDD op{t};
@@ -279,17 +279,59 @@ __global__ __launch_bounds__(256) void k_wmul_dd(Task2* tasks) {
 
 // ------------------------------------------------------------------ dd Jacobi step
 // The block one-sided Jacobi step of kernels.hip in double-double: dd Gram of the
-// pair, dd two-sided Jacobi on it (rotation coefficients computed once per pair in
-// dd, so every rotation is unitary to dd precision), dd update of W and V.
+// pair, dd two-sided Jacobi on it, dd update of W and V.  The rotation angle is
+// formed in binary64 from the dd Gram entries (an angle error of 2^-53 relative only
+// leaves an off-diagonal residual 2^-53 times the one being removed, which the
+// polish then removes), while c, s and the phase e are completed in dd so that
+// every applied rotation is unitary to dd precision.
 __device__ __forceinline__ int rrp(int i, int r, int np) { return i == 0 ? 0 : 1 + (i - 1 + r) % (np - 1); }
-__device__ __forceinline__ int rr_pos(int x, int r, int np) {
-  return x == 0 ? 0 : 1 + ((x - 1 - r) % (np - 1) + (np - 1)) % (np - 1);
+
+__device__ __forceinline__ double rcp_nr_dd(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ __forceinline__ double rsq_nr_dd(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
 }
 
-__global__ __launch_bounds__(256) void k_jacobi_step_dd(Task2* tasks, int step, int sweep, double tol_mult,
+// coefficients of index p (ap, bp) and q (aq, bq): (X J)[:, x] = a_x X_x + b_x X_partner
+__device__ __forceinline__ bool dd_pair_rot(ddr al, ddr be, cdd g, double tol, double ztol, cdd& ap, cdd& bp,
+                                            cdd& aq, cdd& bq) {
+  const double gr = g.re.hi, gi = g.im.hi;
+  const double g2 = gr * gr + gi * gi;
+  if (!(al.hi > ztol && be.hi > ztol && g2 > tol * tol * al.hi * be.hi)) return false;
+  const double ig = rsq_nr_dd(g2);
+  const double zeta = 0.5 * dd::sub(be, al).hi * ig;
+  double t = rcp_nr_dd(fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
+  t = zeta < 0.0 ? -t : t;
+  // c = 1 / sqrt(1 + t^2), s = t c, in dd
+  const ddr one_t2 = dd::add_d(dd::two_prod(t, t), 1.0);
+  const ddr c = dd::div(dd::from(1.0), dd::sqrt(one_t2));
+  const ddr sn = dd::mul_d(c, t);
+  // unit phase e = conj(g) / |g|: binary64 estimate, normalised in dd
+  const double er = gr * ig, ei = -gi * ig;
+  const ddr n2 = dd::add(dd::two_prod(er, er), dd::two_prod(ei, ei));
+  const ddr inv = dd::div(dd::from(1.0), dd::sqrt(n2));
+  const cdd e = {dd::mul_d(inv, er), dd::mul_d(inv, ei)};
+  ap = {c, {0.0, 0.0}};
+  bp = dd::cscale(e, dd::neg(sn));
+  aq = dd::cscale(e, c);
+  bq = {sn, {0.0, 0.0}};
+  return true;
+}
+
+__global__ __launch_bounds__(256) void k_jacobi_step_dd(Task2* tasks, const Ent* ents, int step, double tol_mult,
                                                          int maxin) {
-  constexpr int BW = 8, W2 = 16, TB = 2;
-  const Task2& T = tasks[blockIdx.y];
+  constexpr int BW = 8, W2 = 16, TB = 2, LPT = 64 * W2 / 256;
+  const Task2& T = tasks[ents[blockIdx.y].slot];
+  const int sweep = ents[blockIdx.y].sweep;
   const int N = T.N, M = T.M;
   const int nb = (N + BW - 1) / BW;
   const int nbp = nb + (nb & 1);
@@ -304,8 +346,9 @@ __global__ __launch_bounds__(256) void k_jacobi_step_dd(Task2* tasks, int step, 
   __shared__ double2 Chh[64][W2 + 1], Chl[64][W2 + 1];
   __shared__ cdd Gb[2][W2][W2 + 1];
   __shared__ cdd Rb[2][W2][W2 + 1];
-  __shared__ cdd cal[W2], cbe[W2];  // per index: (X J)[:, x] = cal X[:, x] + cbe X[:, partner]
-  __shared__ int crot[W2];
+  __shared__ cdd ca[W2], cb[W2];
+  __shared__ int cpart[W2], crot[W2];
+  __shared__ int rnd_rot[2];
   __shared__ int swf[3];
   __shared__ int any_rot;
 
@@ -316,9 +359,11 @@ __global__ __launch_bounds__(256) void k_jacobi_step_dd(Task2* tasks, int step, 
     cols[tid] = (blk < nb && c < N) ? c : -1;
   }
   if (tid < 3) swf[tid] = 0;
+  if (tid < 2) rnd_rot[tid] = 0;
   if (tid == 0) any_rot = 0;
   __syncthreads();
 
+  // 1. dd Gram; the next chunk's loads are issued before the current chunk is reduced
   const int wave = tid >> 6, lane = tid & 63;
   const int bi = lane >> 3, bj = lane & 7;
   cacc acc[TB][TB];
@@ -326,35 +371,51 @@ __global__ __launch_bounds__(256) void k_jacobi_step_dd(Task2* tasks, int step, 
   for (int i = 0; i < TB; ++i)
 #pragma unroll
     for (int j = 0; j < TB; ++j) acc[i][j] = cacc0();
-  for (int r0 = 0; r0 < M; r0 += 64) {
-    for (int e = tid; e < 64 * W2; e += 256) {
+  auto load = [&](int r0, double2 (&vh)[LPT], double2 (&vl)[LPT]) {
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+      const int e = tid + 256 * q;
       const int rr = e & 63, l = e >> 6;
       const int c = cols[l], r = r0 + rr;
       const bool ok = c >= 0 && r < M;
-      Chh[rr][l] = ok ? T.thw[(long)c * M + r] : make_double2(0.0, 0.0);
-      Chl[rr][l] = ok ? T.thw_lo[(long)c * M + r] : make_double2(0.0, 0.0);
+      vh[q] = ok ? T.thw[(long)c * M + r] : make_double2(0.0, 0.0);
+      vl[q] = ok ? T.thw_lo[(long)c * M + r] : make_double2(0.0, 0.0);
     }
-    __syncthreads();
-    for (int rr = wave; rr < 64; rr += 4) {
-      cdd x[TB], y[TB];
+  };
+  {
+    double2 vh[LPT], vl[LPT];
+    load(0, vh, vl);
+    for (int r0 = 0; r0 < M; r0 += 64) {
+      __syncthreads();  // the previous chunk has been reduced
 #pragma unroll
-      for (int i = 0; i < TB; ++i) {
-        const double2 h = Chh[rr][bi * TB + i], l = Chl[rr][bi * TB + i];
-        x[i] = {{h.x, l.x}, {h.y, l.y}};
+      for (int q = 0; q < LPT; ++q) {
+        const int e = tid + 256 * q;
+        Chh[e & 63][e >> 6] = vh[q];
+        Chl[e & 63][e >> 6] = vl[q];
       }
+      if (r0 + 64 < M) load(r0 + 64, vh, vl);
+      __syncthreads();
+      for (int rr = wave; rr < 64; rr += 4) {
+        cdd x[TB], y[TB];
 #pragma unroll
-      for (int j = 0; j < TB; ++j) {
-        const double2 h = Chh[rr][bj * TB + j], l = Chl[rr][bj * TB + j];
-        y[j] = {{h.x, l.x}, {h.y, l.y}};
+        for (int i = 0; i < TB; ++i) {
+          const double2 h = Chh[rr][bi * TB + i], l = Chl[rr][bi * TB + i];
+          x[i] = {{h.x, l.x}, {h.y, l.y}};
+        }
+#pragma unroll
+        for (int j = 0; j < TB; ++j) {
+          const double2 h = Chh[rr][bj * TB + j], l = Chl[rr][bj * TB + j];
+          y[j] = {{h.x, l.x}, {h.y, l.y}};
+        }
+#pragma unroll
+        for (int i = 0; i < TB; ++i)
+#pragma unroll
+          for (int j = 0; j < TB; ++j) dd::cacc_fmac(acc[i][j], x[i], y[j]);
       }
-#pragma unroll
-      for (int i = 0; i < TB; ++i)
-#pragma unroll
-        for (int j = 0; j < TB; ++j) dd::cacc_fmac(acc[i][j], x[i], y[j]);
     }
-    __syncthreads();
   }
   for (int w = 0; w < 4; ++w) {
+    __syncthreads();
     if (wave == w) {
 #pragma unroll
       for (int i = 0; i < TB; ++i)
@@ -365,7 +426,6 @@ __global__ __launch_bounds__(256) void k_jacobi_step_dd(Task2* tasks, int step, 
           Gb[0][gi][gj] = (w == 0) ? v : dd::cadd(Gb[0][gi][gj], v);
         }
     }
-    __syncthreads();
   }
   for (int e = tid; e < W2 * W2; e += 256) {
     const int i = e / W2, j = e % W2;
@@ -375,45 +435,42 @@ __global__ __launch_bounds__(256) void k_jacobi_step_dd(Task2* tasks, int step, 
   const double ztol = *T.fro2 * 0x1p-192;  // columns below 2^-96 ||theta|| are rounding noise
   __syncthreads();
 
+  // 2. two-sided Jacobi on G in dd: one thread per pair forms the rotation, then every
+  //    thread forms its element of J^H G J and R J (double-buffered)
+  // the polish diagonalises each pair's nearly diagonal Gram fully (rounds without
+  // a rotation cost only the coefficient check)
+  const int inner = maxin > 12 ? maxin : 12;
   int cur = 0;
-  for (int isw = 0; isw < maxin; ++isw) {
+  for (int isw = 0; isw < inner; ++isw) {
     if (tid == 0) swf[(isw + 1) % 3] = 0;
     for (int rnd = 0; rnd < W2 - 1; ++rnd) {
-      // coefficients, one thread per pair
       if (tid < W2 / 2) {
         const int pa = rrp(tid, rnd, W2), pb = rrp(W2 - 1 - tid, rnd, W2);
         const int p = pa < pb ? pa : pb, q = pa < pb ? pb : pa;
-        const cdd gpq = Gb[cur][p][q];
-        const ddr a = Gb[cur][p][p].re, b = Gb[cur][q][q].re;
-        const double gah = hypot(gpq.re.hi, gpq.im.hi);
-        const bool rot = cols[p] >= 0 && cols[q] >= 0 && a.hi > ztol && b.hi > ztol &&
-                         gah > tol * sqrt(a.hi * b.hi);
-        cdd alp = {{1.0, 0.0}, {0.0, 0.0}}, bep = czero(), alq = alp, beq = czero();
-        if (rot) {
-          const ddr ga = dd::sqrt(dd::add(dd::mul(gpq.re, gpq.re), dd::mul(gpq.im, gpq.im)));
-          const ddr zeta = dd::div(dd::sub(b, a), dd::mul_d(ga, 2.0));
-          const ddr az = zeta.hi < 0 ? dd::neg(zeta) : zeta;
-          const ddr root = dd::sqrt(dd::add_d(dd::mul(zeta, zeta), 1.0));
-          ddr t = dd::div(dd::from(1.0), dd::add(az, root));
-          if (zeta.hi < 0) t = dd::neg(t);
-          const ddr c = dd::div(dd::from(1.0), dd::sqrt(dd::add_d(dd::mul(t, t), 1.0)));
-          const ddr sn = dd::mul(t, c);
-          const cdd e = {dd::div(gpq.re, ga), dd::neg(dd::div(gpq.im, ga))};  // e^{-i phi}
-          alp = {c, {0.0, 0.0}};
-          bep = dd::cscale(e, dd::neg(sn));
-          alq = dd::cscale(e, c);
-          beq = {sn, {0.0, 0.0}};
+        cdd ap, bp, aq, bq;
+        const bool rot = cols[p] >= 0 && cols[q] >= 0 &&
+                         dd_pair_rot(Gb[cur][p][p].re, Gb[cur][q][q].re, Gb[cur][p][q], tol, ztol, ap, bp, aq, bq);
+        if (!rot) {
+          ap = aq = {{1.0, 0.0}, {0.0, 0.0}};
+          bp = bq = czero();
+        } else {
           swf[isw % 3] = 1;
+          rnd_rot[rnd & 1] = 1;
         }
-        cal[p] = alp; cbe[p] = bep; cal[q] = alq; cbe[q] = beq;
+        ca[p] = ap; cb[p] = bp; ca[q] = aq; cb[q] = bq;
+        cpart[p] = q; cpart[q] = p;
         crot[p] = rot; crot[q] = rot;
       }
       __syncthreads();
+      if (tid == 0) rnd_rot[(rnd + 1) & 1] = 0;
+      if (!rnd_rot[rnd & 1]) {
+        __syncthreads();
+        continue;
+      }
       {
         const int i = tid / W2, j = tid % W2;
-        const int pi_ = rrp(W2 - 1 - rr_pos(i, rnd, W2), rnd, W2);
-        const int pj = rrp(W2 - 1 - rr_pos(j, rnd, W2), rnd, W2);
-        const cdd ai = cal[i], bi_ = cbe[i], aj = cal[j], bj_ = cbe[j];
+        const int pi_ = cpart[i], pj = cpart[j];
+        const cdd ai = ca[i], bi_ = cb[i], aj = ca[j], bj_ = cb[j];
         const cdd (*G)[W2 + 1] = Gb[cur];
         const cdd colj = dd::cadd(dd::cmul(aj, G[i][j]), dd::cmul(bj_, G[i][pj]));
         const cdd colpj = dd::cadd(dd::cmul(aj, G[pi_][j]), dd::cmul(bj_, G[pi_][pj]));
@@ -432,21 +489,25 @@ __global__ __launch_bounds__(256) void k_jacobi_step_dd(Task2* tasks, int step, 
   }
   __syncthreads();
 
+  // 3. dd update of the pair's columns of W and V (M + N rows, a row per thread at a
+  //    time, all its loads issued before the products)
   if (any_rot) {
-    for (int pass = 0; pass < 2; ++pass) {
-      double2* Xh = pass ? T.V : T.thw;
-      double2* Xl = pass ? T.V_lo : T.thw_lo;
-      const int rows = pass ? N : M;
-      for (int r = tid; r < rows; r += 256) {
-        cdd x[W2];
+    const int total = M + N;
+    for (int rr = tid; rr < total; rr += 256) {
+      const bool inA = rr < M;
+      double2* Xh = inA ? T.thw : T.V;
+      double2* Xl = inA ? T.thw_lo : T.V_lo;
+      const int rows = inA ? M : N;
+      const int r = inA ? rr : rr - M;
+      cdd x[W2];
 #pragma unroll
-        for (int l = 0; l < W2; ++l) x[l] = cols[l] >= 0 ? ldc(Xh, Xl, (long)cols[l] * rows + r) : czero();
-        for (int pc = 0; pc < W2; ++pc) {
-          cacc y = cacc0();
-#pragma unroll
-          for (int l = 0; l < W2; ++l) dd::cacc_fma(y, x[l], Rb[cur][l][pc]);
-          if (cols[pc] >= 0) stc(Xh, Xl, (long)cols[pc] * rows + r, dd::cnorm(y));
-        }
+      for (int l = 0; l < W2; ++l) x[l] = cols[l] >= 0 ? ldc(Xh, Xl, (long)cols[l] * rows + r) : czero();
+#pragma unroll 1
+      for (int pc = 0; pc < W2; ++pc) {
+        cacc y = cacc0();
+#pragma unroll 4
+        for (int l = 0; l < W2; ++l) dd::cacc_fma(y, x[l], Rb[cur][l][pc]);
+        if (cols[pc] >= 0) stc(Xh, Xl, (long)cols[pc] * rows + r, dd::cnorm(y));
       }
     }
     if (tid == 0) flags[sweep % 3] = 1;
@@ -462,8 +523,8 @@ __device__ __forceinline__ bool dd_before(ddr a, int ia, ddr b, int ib) {
   return dd::lt(b, a) || (a.hi == b.hi && a.lo == b.lo && ia < ib);
 }
 
-__global__ __launch_bounds__(1024) void k_truncate_dd(Task2* tasks, int chi, double eps, double floor_rel) {
-  Task2& T = tasks[blockIdx.x];
+__global__ __launch_bounds__(1024) void k_truncate_dd(Task2* tasks, const Ent* ents, int chi, double eps, double floor_rel) {
+  Task2& T = tasks[ents[blockIdx.x].slot];
   const int N = T.N, M = T.M;
   int P = 1;
   while (P < N) P <<= 1;
@@ -563,8 +624,8 @@ __global__ __launch_bounds__(1024) void k_truncate_dd(Task2* tasks, int chi, dou
 }
 
 // ------------------------------------------------------------------ split (dd)
-__global__ __launch_bounds__(256) void k_split_right_dd(Task2* tasks) {
-  const Task2& T = tasks[blockIdx.z];
+__global__ __launch_bounds__(256) void k_split_right_dd(Task2* tasks, const Ent* ents) {
+  const Task2& T = tasks[ents[blockIdx.z].slot];
   const int k = *T.dim_out, N = T.N, c = T.c;
   const int nu = blockIdx.y;
   if (nu >= k) return;
@@ -595,8 +656,8 @@ struct SplitLeftOpDD {
   }
 };
 
-__global__ __launch_bounds__(256) void k_split_left_dd(Task2* tasks) {
-  const Task2* t = &tasks[blockIdx.z];
+__global__ __launch_bounds__(256) void k_split_left_dd(Task2* tasks, const Ent* ents) {
+  const Task2* t = &tasks[ents[blockIdx.z].slot];
   const int k = *t->dim_out;
   const int tm = blockIdx.x * 32, tn = blockIdx.y * 32;
   if (tm >= t->M || tn >= k) return;
@@ -653,57 +714,50 @@ hipError_t launch_gate1_dd(Task1* d_tasks, int ntask, long maxel, hipStream_t st
   return hipSuccess;
 }
 
-hipError_t launch_theta2_dd(Task2* d_tasks, int ntask, int maxM, int maxN, hipStream_t st) {
-  hipLaunchKernelGGL(k_theta2_dd, dim3((maxM + 31) / 32, (maxN + 31) / 32, ntask), dim3(256), 0, st, d_tasks);
+hipError_t launch_theta2_dd(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, int maxN, hipStream_t st) {
+  hipLaunchKernelGGL(k_theta2_dd, dim3((maxM + 31) / 32, (maxN + 31) / 32, nent), dim3(256), 0, st, d_tasks, d_ents);
   MPS_LAUNCH_CHECK();
   return hipSuccess;
 }
 
-int run_dd_refine(Task2* d_tasks, int ntask, int maxM, int maxN, int max_sweeps, int /*maxin: the polish always
-                  diagonalises each pair's nearly diagonal Gram fully (it exits early)*/, double tol_mult,
-                  int* h_flags, int* d_flags, hipStream_t st, int* sweeps, bool* converged) {
+// Enter the dd polish: V0 (binary64) -> dd, two Newton-Schulz steps, W = theta_w V in dd.
+hipError_t launch_dd_enter(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, int maxN, hipStream_t st) {
   const long nn = (long)maxN * maxN;
-  hipLaunchKernelGGL(k_promote, dim3(grid_for(nn), ntask), dim3(256), 0, st, d_tasks);
-  if (hipGetLastError() != hipSuccess) return -1;
+  hipLaunchKernelGGL(k_promote, dim3(grid_for(nn), nent), dim3(256), 0, st, d_tasks, d_ents);
+  MPS_LAUNCH_CHECK();
   for (int it = 0; it < 2; ++it) {
-    hipLaunchKernelGGL(k_gram_dd, dim3((maxN + 31) / 32, (maxN + 31) / 32, ntask), dim3(256), 0, st, d_tasks);
-    hipLaunchKernelGGL(k_ns_mul, dim3((maxN + 63) / 64, (maxN + 63) / 64, ntask), dim3(256), 0, st, d_tasks);
-    hipLaunchKernelGGL(k_ns_fix, dim3(grid_for(nn), ntask), dim3(256), 0, st, d_tasks);
-    if (hipGetLastError() != hipSuccess) return -1;
+    hipLaunchKernelGGL(k_gram_dd, dim3((maxN + 31) / 32, (maxN + 31) / 32, nent), dim3(256), 0, st, d_tasks, d_ents);
+    hipLaunchKernelGGL(k_ns_mul, dim3((maxN + 63) / 64, (maxN + 63) / 64, nent), dim3(256), 0, st, d_tasks, d_ents);
+    hipLaunchKernelGGL(k_ns_fix, dim3(grid_for(nn), nent), dim3(256), 0, st, d_tasks, d_ents);
+    MPS_LAUNCH_CHECK();
   }
-  hipLaunchKernelGGL(k_wmul_dd, dim3((maxM + 31) / 32, (maxN + 31) / 32, ntask), dim3(256), 0, st, d_tasks);
-  if (hipGetLastError() != hipSuccess) return -1;
+  hipLaunchKernelGGL(k_wmul_dd, dim3((maxM + 31) / 32, (maxN + 31) / 32, nent), dim3(256), 0, st, d_tasks, d_ents);
+  MPS_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+// One dd polish step (inner sweeps per block pair as in the FP64 step).
+hipError_t launch_jacobi_step_dd(Task2* d_tasks, const Ent* d_ents, int nent, int maxN, int step, double tol_mult,
+                                 int maxin, hipStream_t st) {
   const int nb = (maxN + 7) / 8;
   const int nbp = nb + (nb & 1);
-  *converged = false;
-  *sweeps = 0;
-  for (int sw = 0; sw < max_sweeps; ++sw) {
-    for (int stp = 0; stp < nbp - 1; ++stp)
-      hipLaunchKernelGGL(k_jacobi_step_dd, dim3(nbp / 2, ntask), dim3(256), 0, st, d_tasks, stp, sw, tol_mult, 12);
-    if (hipGetLastError() != hipSuccess) return -1;
-    if (hipMemcpyAsync(h_flags, d_flags, sizeof(int) * 3 * ntask, hipMemcpyDeviceToHost, st) != hipSuccess) return -1;
-    if (hipStreamSynchronize(st) != hipSuccess) return -1;
-    *sweeps = sw + 1;
-    bool any = false;
-    for (int i = 0; i < ntask; ++i) any |= h_flags[3 * i + sw % 3] != 0;
-    if (!any) {
-      *converged = true;
-      break;
-    }
-  }
-  return 0;
-}
-
-hipError_t launch_truncate_dd(Task2* d_tasks, int ntask, int chi, double eps, double floor_rel, hipStream_t st) {
-  hipLaunchKernelGGL(k_truncate_dd, dim3(ntask), dim3(1024), 0, st, d_tasks, chi, eps, floor_rel);
+  hipLaunchKernelGGL(k_jacobi_step_dd, dim3(nbp / 2, nent), dim3(256), 0, st, d_tasks, d_ents, step, tol_mult, maxin);
   MPS_LAUNCH_CHECK();
   return hipSuccess;
 }
 
-hipError_t launch_split_dd(Task2* d_tasks, int ntask, int maxM, int maxN, int maxK, hipStream_t st) {
-  hipLaunchKernelGGL(k_split_right_dd, dim3((maxN + 255) / 256, maxK, ntask), dim3(256), 0, st, d_tasks);
+hipError_t launch_truncate_dd(Task2* d_tasks, const Ent* d_ents, int nent, int chi, double eps, double floor_rel,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_truncate_dd, dim3(nent), dim3(1024), 0, st, d_tasks, d_ents, chi, eps, floor_rel);
   MPS_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_split_left_dd, dim3((maxM + 31) / 32, (maxK + 31) / 32, ntask), dim3(256), 0, st, d_tasks);
+  return hipSuccess;
+}
+
+hipError_t launch_split_dd(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, int maxN, int maxK, hipStream_t st) {
+  hipLaunchKernelGGL(k_split_right_dd, dim3((maxN + 255) / 256, maxK, nent), dim3(256), 0, st, d_tasks, d_ents);
+  MPS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_split_left_dd, dim3((maxM + 31) / 32, (maxK + 31) / 32, nent), dim3(256), 0, st, d_tasks,
+                     d_ents);
   MPS_LAUNCH_CHECK();
   return hipSuccess;
 }

@@ -18,8 +18,8 @@ namespace mpsk {
 
 // ------------------------------------------------------------------ prep
 // V = I_N, zero the Frobenius accumulator and the rotation flags.
-__global__ __launch_bounds__(256) void k_prep2(Task2* tasks) {
-  const Task2& T = tasks[blockIdx.y];
+__global__ __launch_bounds__(256) void k_prep2(Task2* tasks, const Ent* ents) {
+  const Task2& T = tasks[ents[blockIdx.y].slot];
   const int N = T.N;
   const long nn = (long)N * N;
   for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < nn; e += (long)gridDim.x * 256) {
@@ -88,8 +88,8 @@ struct ThetaOp {
   }
 };
 
-__global__ __launch_bounds__(256) void k_theta2(Task2* tasks) {
-  const Task2* t = &tasks[blockIdx.z];
+__global__ __launch_bounds__(256) void k_theta2(Task2* tasks, const Ent* ents) {
+  const Task2* t = &tasks[ents[blockIdx.z].slot];
   const int tm = blockIdx.x * 64, tn = blockIdx.y * 64;
   if (tm >= t->M || tn >= t->N) return;
   ThetaOp op{t};
@@ -113,50 +113,57 @@ __global__ __launch_bounds__(256) void k_theta2(Task2* tasks) {
 // A pair whose off-diagonal entries are all below tol * sqrt(G_pp G_qq) is left
 // alone; a task whose previous sweep rotated nothing is converged and skipped.
 __device__ __forceinline__ int rr_player(int i, int r, int np) { return i == 0 ? 0 : 1 + (i - 1 + r) % (np - 1); }
-// partner of index x in round r of the circle schedule on np players
-__device__ __forceinline__ int rr_partner(int x, int r, int np) {
-  const int pos = x == 0 ? 0 : 1 + ((x - 1 - r) % (np - 1) + (np - 1)) % (np - 1);
-  return rr_player(np - 1 - pos, r, np);
+// Newton-refined reciprocal and reciprocal square root (the hardware estimates
+// v_rcp_f64 / v_rsq_f64 are not correctly rounded; two Newton steps bring them to
+// binary64 accuracy, with a much shorter dependency chain than div / sqrt).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
 }
 
-struct RotCoef {
-  double2 al, be;  // (X J)[:, x] = al X[:, x] + be X[:, partner(x)]
-  bool rot;
+// Rotation of one column pair (p < q) from the Gram entries al = G_pp, be = G_qq,
+// g = G_pq: the complex form of the symmetric Schur 2x2 (Golub & Van Loan 8.4):
+// with e = conj(g)/|g|, zeta = (be - al) / (2|g|), t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+// c = 1 / sqrt(1 + t^2), s = t c:  (X J)[:, p] = c X_p - s e X_q,  (X J)[:, q] = s X_p + c e X_q.
+struct PairRot {
+  double c, s;
+  double2 e;  // e^{-i phi}
 };
 
-// rotation coefficients of index x (partner px) from the current Gram buffer
-template <int LD>
-__device__ __forceinline__ RotCoef rot_coef(const double2 (*G)[LD], const int* cols, int x, int px, double tol,
-                                            double ztol) {
-  RotCoef r;
-  r.al = cmk(1.0, 0.0);
-  r.be = cmk(0.0, 0.0);
-  r.rot = false;
-  const int p = x < px ? x : px, q = x < px ? px : x;
-  if (cols[p] < 0 || cols[q] < 0) return r;
-  const double a = G[p][p].x, b = G[q][q].x;
-  const double2 g = G[p][q];
-  const double ga = hypot(g.x, g.y);
-  if (!(a > ztol && b > ztol && ga > tol * sqrt(a * b))) return r;
-  const double zeta = (b - a) / (2.0 * ga);
-  const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  const double c = 1.0 / sqrt(1.0 + t * t);
-  const double sn = t * c;
-  const double2 e = cmk(g.x / ga, -g.y / ga);  // e^{-i phi}
-  r.rot = true;
-  if (x == p) { r.al = cmk(c, 0.0); r.be = cscale(e, -sn); }
-  else        { r.al = cscale(e, c); r.be = cmk(sn, 0.0); }
-  return r;
+__device__ __forceinline__ bool pair_rot(double al, double be, double2 g, double tol, double ztol, PairRot& r) {
+  const double g2 = g.x * g.x + g.y * g.y;
+  if (!(al > ztol && be > ztol && g2 > tol * tol * al * be)) return false;
+  const double ig = rsq_nr(g2);            // 1 / |g|
+  const double zeta = 0.5 * (be - al) * ig;
+  const double root = sqrt(fma(zeta, zeta, 1.0));
+  double t = rcp_nr(fabs(zeta) + root);
+  t = zeta < 0.0 ? -t : t;
+  r.c = rsq_nr(fma(t, t, 1.0));
+  r.s = t * r.c;
+  r.e = cmk(g.x * ig, -g.y * ig);
+  return true;
 }
 
 template <int BW>
-__global__ __launch_bounds__(256) void k_jacobi_step(Task2* tasks, int step, int sweep, double tol_mult,
-                                                      int maxin) {
+__global__ __launch_bounds__(256) void k_jacobi_step(Task2* tasks, const Ent* ents, int step, double tol_mult,
+                                                      int maxin, long long* phase_clock) {
   constexpr int W2 = 2 * BW;
-  constexpr int TB = W2 / 8;          // register block edge of the Gram phase
-  constexpr int EPT = (W2 * W2 + 255) / 256;  // inner-phase elements per thread
+  constexpr int TB = W2 / 8;                   // register block edge of the Gram phase
+  constexpr int CR = W2 <= 8 ? 128 : 64;        // rows per Gram chunk
+  constexpr int LPT = CR * W2 / 256;           // chunk elements loaded per thread
   static_assert(W2 == 8 || W2 == 16 || W2 == 32, "block width");
-  const Task2& T = tasks[blockIdx.y];
+  const Task2& T = tasks[ents[blockIdx.y].slot];
+  const int sweep = ents[blockIdx.y].sweep;
   const int N = T.N, M = T.M;
   const int nb = (N + BW - 1) / BW;
   const int nbp = nb + (nb & 1);
@@ -170,12 +177,18 @@ __global__ __launch_bounds__(256) void k_jacobi_step(Task2* tasks, int step, int
   if (sweep > 0 && flags[(sweep + 2) % 3] == 0) return;
 
   __shared__ int cols[W2];
-  __shared__ double2 Ch[64][W2 + 1];
+  __shared__ double2 Ch[2][CR][W2 + 1];
   __shared__ double2 Gb[2][W2][W2 + 1];
   __shared__ double2 Rb[2][W2][W2 + 1];
+  __shared__ double rc_[W2], rs_[W2];       // per index x: coefficient of X_x and of X_partner
+  __shared__ double2 ra_[W2], rb_[W2];      // (X J)[:, x] = ra_[x] X_x + rb_[x] X_partner(x)
+  __shared__ int rpart[W2], rrot[W2];
+  __shared__ int rnd_rot[2];  // did any pair of the round rotate (alternating slots)
   __shared__ int swf[3];
   __shared__ int any_rot;
 
+  const bool clk = phase_clock && pi == 0 && blockIdx.y == 0 && tid == 0;
+  if (clk) phase_clock[0] = wall_clock64();
   const int I = rr_player(pi, step, nbp), J = rr_player(nbp - 1 - pi, step, nbp);
   if (tid < W2) {
     const int blk = tid < BW ? I : J;
@@ -183,10 +196,30 @@ __global__ __launch_bounds__(256) void k_jacobi_step(Task2* tasks, int step, int
     cols[tid] = (blk < nb && c < N) ? c : -1;
   }
   if (tid < 3) swf[tid] = 0;
+  if (tid < 2) rnd_rot[tid] = 0;
   if (tid == 0) any_rot = 0;
   __syncthreads();
 
-  // 1. Gram: wave g takes rows g, g+4, ... of each 64-row chunk; lane (bi, bj) a TB x TB block
+  // chunk loader: element e = tid + 256 q -> row e % CR, pair column e / CR
+  auto load_chunk = [&](const double2* X, int rows, int r0, double2 (&v)[LPT]) {
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+      const int e = tid + 256 * q;
+      const int rr = e % CR, l = e / CR;
+      const int c = cols[l], r = r0 + rr;
+      v[q] = (c >= 0 && r < rows) ? X[(long)c * rows + r] : cmk(0.0, 0.0);
+    }
+  };
+  auto store_chunk = [&](int buf, const double2 (&v)[LPT]) {
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+      const int e = tid + 256 * q;
+      Ch[buf][e % CR][e / CR] = v[q];
+    }
+  };
+
+  // 1. Gram, row chunks double-buffered: the loads of chunk i+1 are in flight while
+  //    chunk i is reduced.  Wave w takes rows w, w+4, ...; lane (bi, bj) a TB x TB block.
   const double2* __restrict__ A = T.thw;
   const int wave = tid >> 6, lane = tid & 63;
   const int bi = lane >> 3, bj = lane & 7;
@@ -195,48 +228,54 @@ __global__ __launch_bounds__(256) void k_jacobi_step(Task2* tasks, int step, int
   for (int i = 0; i < TB; ++i)
 #pragma unroll
     for (int j = 0; j < TB; ++j) acc[i][j] = cmk(0.0, 0.0);
-  for (int r0 = 0; r0 < M; r0 += 64) {
-    for (int e = tid; e < 64 * W2; e += 256) {
-      const int rr = e & 63, l = e >> 6;
-      const int c = cols[l], r = r0 + rr;
-      Ch[rr][l] = (c >= 0 && r < M) ? A[(long)c * M + r] : cmk(0.0, 0.0);
-    }
-    __syncthreads();
+  const int nch = (M + CR - 1) / CR;
+  {
+    double2 v[LPT];
+    load_chunk(A, M, 0, v);
+    store_chunk(0, v);
+    for (int ch = 0; ch < nch; ++ch) {
+      const bool more = ch + 1 < nch;
+      if (more) load_chunk(A, M, (ch + 1) * CR, v);
+      __syncthreads();
+      const int b = ch & 1;
 #pragma unroll 4
-    for (int rr = wave; rr < 64; rr += 4) {
-      double2 x[TB], y[TB];
+      for (int rr = wave; rr < CR; rr += 4) {
+        double2 x[TB], y[TB];
 #pragma unroll
-      for (int i = 0; i < TB; ++i) x[i] = Ch[rr][bi * TB + i];
+        for (int i = 0; i < TB; ++i) x[i] = Ch[b][rr][bi * TB + i];
 #pragma unroll
-      for (int j = 0; j < TB; ++j) y[j] = Ch[rr][bj * TB + j];
+        for (int j = 0; j < TB; ++j) y[j] = Ch[b][rr][bj * TB + j];
 #pragma unroll
-      for (int i = 0; i < TB; ++i)
+        for (int i = 0; i < TB; ++i)
 #pragma unroll
-        for (int j = 0; j < TB; ++j) acc[i][j] = cfmac(x[i], y[j], acc[i][j]);
+          for (int j = 0; j < TB; ++j) acc[i][j] = cfmac(x[i], y[j], acc[i][j]);
+      }
+      if (more) store_chunk(b ^ 1, v);  // buffer b^1 was last read before this chunk's barrier
     }
-    __syncthreads();
   }
   // reduce the four waves' partial Grams into Gb[0] (one wave at a time: deterministic)
   for (int w = 0; w < 4; ++w) {
+    __syncthreads();
     if (wave == w) {
 #pragma unroll
       for (int i = 0; i < TB; ++i)
 #pragma unroll
         for (int j = 0; j < TB; ++j) {
           const int gi = bi * TB + i, gj = bj * TB + j;
-          if (gi < W2 && gj < W2) Gb[0][gi][gj] = (w == 0) ? acc[i][j] : cadd(Gb[0][gi][gj], acc[i][j]);
+          Gb[0][gi][gj] = (w == 0) ? acc[i][j] : cadd(Gb[0][gi][gj], acc[i][j]);
         }
     }
-    __syncthreads();
   }
   for (int e = tid; e < W2 * W2; e += 256) Rb[0][e / W2][e % W2] = cmk(e / W2 == e % W2 ? 1.0 : 0.0, 0.0);
   const double tol = tol_mult * (double)(M > 16 ? M : 16) * 0x1p-53;
   const double ztol = *T.fro2 * 0x1p-88;  // columns below 2^-44 ||theta|| are rounding noise
   __syncthreads();
+  if (clk) phase_clock[1] = wall_clock64();
 
-  // 2. two-sided Jacobi on G, one barrier per round.  With many column blocks a
-  // single inner sweep per step is enough (the next steps revisit every column);
-  // with few blocks each pair must be diagonalised fully.
+  // 2. two-sided Jacobi on G: per round, one thread per pair forms the rotation, then
+  //    every thread forms its elements of J^H G J and R J (double-buffered).  With
+  //    many column blocks a single inner sweep per step is enough (the next steps
+  //    revisit every column); with few blocks each pair is diagonalised fully.
   const int inner = nbp >= 16 ? maxin : 12;
   int cur = 0;
   for (int isw = 0; isw < inner; ++isw) {
@@ -244,39 +283,44 @@ __global__ __launch_bounds__(256) void k_jacobi_step(Task2* tasks, int step, int
     // (isw+1)%3 was last read two sweeps ago (many barriers back): clear it now
     if (tid == 0) swf[(isw + 1) % 3] = 0;
     for (int rnd = 0; rnd < W2 - 1; ++rnd) {
-      const double2(*G)[W2 + 1] = Gb[cur];
-      const double2(*R)[W2 + 1] = Rb[cur];
-      double2 gn[EPT], rn[EPT];
-      int ei[EPT], ej[EPT];
-      bool any = false;
-#pragma unroll
-      for (int q = 0; q < EPT; ++q) {
-        const int e = tid + 256 * q;
-        ei[q] = -1;
-        if (e >= W2 * W2) continue;
-        const int i = e / W2, j = e % W2;
-        ei[q] = i; ej[q] = j;
-        const int pi_ = rr_partner(i, rnd, W2), pj = rr_partner(j, rnd, W2);
-        const RotCoef ci = rot_coef<W2 + 1>(G, cols, i, pi_, tol, ztol);
-        const RotCoef cj = (pj == pi_ && j == i) ? ci : rot_coef<W2 + 1>(G, cols, j, pj, tol, ztol);
-        any |= ci.rot;
-        // (J^H G J)_{ij} and (R J)_{ij}
-        const double2 gij = G[i][j], gipj = G[i][pj], gpij = G[pi_][j], gpipj = G[pi_][pj];
-        const double2 colj = cadd(cmul(cj.al, gij), cmul(cj.be, gipj));
-        const double2 colpj = cadd(cmul(cj.al, gpij), cmul(cj.be, gpipj));
-        double2 v = cadd(cmul(cconj(ci.al), colj), cmul(cconj(ci.be), colpj));
-        if (ci.rot && j == pi_) v = cmk(0.0, 0.0);  // the rotated pair's off-diagonal is zero
-        if (i == j) v.y = 0.0;
-        gn[q] = v;
-        rn[q] = cadd(cmul(cj.al, R[i][j]), cmul(cj.be, R[i][pj]));
-      }
-      if (any) swf[isw % 3] = 1;
-#pragma unroll
-      for (int q = 0; q < EPT; ++q)
-        if (ei[q] >= 0) {
-          Gb[cur ^ 1][ei[q]][ej[q]] = gn[q];
-          Rb[cur ^ 1][ei[q]][ej[q]] = rn[q];
+      if (tid < W2 / 2) {
+        const int pa = rr_player(tid, rnd, W2), pb = rr_player(W2 - 1 - tid, rnd, W2);
+        const int p = pa < pb ? pa : pb, q = pa < pb ? pb : pa;
+        PairRot r;
+        const bool rot = cols[p] >= 0 && cols[q] >= 0 &&
+                         pair_rot(Gb[cur][p][p].x, Gb[cur][q][q].x, Gb[cur][p][q], tol, ztol, r);
+        rpart[p] = q; rpart[q] = p;
+        rrot[p] = rot; rrot[q] = rot;
+        if (rot) {
+          ra_[p] = cmk(r.c, 0.0);          rb_[p] = cscale(r.e, -r.s);
+          ra_[q] = cscale(r.e, r.c);       rb_[q] = cmk(r.s, 0.0);
+          swf[isw % 3] = 1;
+          rnd_rot[rnd & 1] = 1;
+        } else {
+          ra_[p] = ra_[q] = cmk(1.0, 0.0);
+          rb_[p] = rb_[q] = cmk(0.0, 0.0);
         }
+      }
+      __syncthreads();
+      // slot (rnd+1)&1 was last read in the previous round, before its closing barrier
+      if (tid == 0) rnd_rot[(rnd + 1) & 1] = 0;
+      if (!rnd_rot[rnd & 1]) {  // nothing rotated: G and R are unchanged
+        __syncthreads();
+        continue;
+      }
+      for (int e = tid; e < W2 * W2; e += 256) {
+        const int i = e / W2, j = e % W2;
+        const int pi_ = rpart[i], pj = rpart[j];
+        const double2 ai = ra_[i], bi_ = rb_[i], aj = ra_[j], bj_ = rb_[j];
+        const double2(*G)[W2 + 1] = Gb[cur];
+        const double2 colj = cadd(cmul(aj, G[i][j]), cmul(bj_, G[i][pj]));
+        const double2 colpj = cadd(cmul(aj, G[pi_][j]), cmul(bj_, G[pi_][pj]));
+        double2 v = cadd(cmul(cconj(ai), colj), cmul(cconj(bi_), colpj));
+        if (rrot[i] && j == pi_) v = cmk(0.0, 0.0);  // the rotated pair's off-diagonal is zero
+        if (i == j) v.y = 0.0;
+        Gb[cur ^ 1][i][j] = v;
+        Rb[cur ^ 1][i][j] = cadd(cmul(aj, Rb[cur][i][j]), cmul(bj_, Rb[cur][i][pj]));
+      }
       cur ^= 1;
       __syncthreads();
     }
@@ -284,24 +328,41 @@ __global__ __launch_bounds__(256) void k_jacobi_step(Task2* tasks, int step, int
     if (tid == 0) any_rot = 1;
   }
   __syncthreads();
+  if (clk) phase_clock[2] = wall_clock64();
 
-  // 3. apply R to the pair's columns of W and V
+  // 3. apply R to the pair's columns of W (M rows) and V (N rows), treated as one
+  //    list of M + N rows: each thread takes RPT rows at a time and issues all their
+  //    loads before computing, so that RPT * W2 loads per thread are in flight.
   if (any_rot) {
     const double2(*R)[W2 + 1] = Rb[cur];
-    double2* __restrict__ Aw = T.thw;
-    double2* __restrict__ Vw = T.V;
-    for (int pass = 0; pass < 2; ++pass) {
-      double2* X = pass ? Vw : Aw;
-      const int rows = pass ? N : M;
-      for (int r = tid; r < rows; r += 256) {
-        double2 x[W2];
+    constexpr int RPT = W2 <= 8 ? 4 : (W2 <= 16 ? 2 : 1);  // rows per thread in flight
+    const int total = M + N;
+    for (int r0 = 0; r0 < total; r0 += 256 * RPT) {
+      double2 x[RPT][W2];
 #pragma unroll
-        for (int l = 0; l < W2; ++l) x[l] = cols[l] >= 0 ? X[(long)cols[l] * rows + r] : cmk(0.0, 0.0);
+      for (int k = 0; k < RPT; ++k) {
+        const int rr = r0 + tid + 256 * k;
+        const bool inA = rr < M;
+        const double2* X = inA ? T.thw : T.V;
+        const int rows = inA ? M : N;
+        const int r = inA ? rr : rr - M;
+#pragma unroll
+        for (int l = 0; l < W2; ++l)
+          x[k][l] = (rr < total && cols[l] >= 0) ? X[(long)cols[l] * rows + r] : cmk(0.0, 0.0);
+      }
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int rr = r0 + tid + 256 * k;
+        if (rr >= total) continue;
+        const bool inA = rr < M;
+        double2* X = inA ? T.thw : T.V;
+        const int rows = inA ? M : N;
+        const int r = inA ? rr : rr - M;
 #pragma unroll 4
         for (int pc = 0; pc < W2; ++pc) {
           double2 y = cmk(0.0, 0.0);
 #pragma unroll
-          for (int l = 0; l < W2; ++l) y = cfma(x[l], R[l][pc], y);
+          for (int l = 0; l < W2; ++l) y = cfma(x[k][l], R[l][pc], y);
           if (cols[pc] >= 0) X[(long)cols[pc] * rows + r] = y;
         }
       }
@@ -309,14 +370,19 @@ __global__ __launch_bounds__(256) void k_jacobi_step(Task2* tasks, int step, int
     if (tid == 0) flags[sweep % 3] = 1;
   }
   if (tid < W2 && cols[tid] >= 0) T.sig2[cols[tid]] = Gb[cur][tid][tid].x;
+  if (clk) {
+    __threadfence();
+    phase_clock[3] = wall_clock64();
+    phase_clock[4] = any_rot;
+  }
 }
 
 // ------------------------------------------------------------------ truncation
 // Sort sigma^2 descending (bitonic, ties by column index), suffix sums for the
 // discarded weight, the kept count k = min(chi, k_eps, rank, min(M, N)), the new
 // Schmidt values sigma_j / nu and the column order for the split.
-__global__ __launch_bounds__(1024) void k_truncate(Task2* tasks, int chi, double eps, double floor_rel) {
-  Task2& T = tasks[blockIdx.x];
+__global__ __launch_bounds__(1024) void k_truncate(Task2* tasks, const Ent* ents, int chi, double eps, double floor_rel) {
+  Task2& T = tasks[ents[blockIdx.x].slot];
   const int N = T.N, M = T.M;
   int P = 1;
   while (P < N) P <<= 1;
@@ -413,8 +479,8 @@ __global__ __launch_bounds__(1024) void k_truncate(Task2* tasks, int chi, double
 
 // ------------------------------------------------------------------ split
 // B_{s+1}'[nu][j][gamma] = conj(V[(j c + gamma), perm[nu]])  (rows of Z_k^H)
-__global__ __launch_bounds__(256) void k_split_right(Task2* tasks) {
-  const Task2& T = tasks[blockIdx.z];
+__global__ __launch_bounds__(256) void k_split_right(Task2* tasks, const Ent* ents) {
+  const Task2& T = tasks[ents[blockIdx.z].slot];
   const int k = *T.dim_out, N = T.N, c = T.c;
   const int nu = blockIdx.y;
   if (nu >= k) return;
@@ -448,8 +514,8 @@ struct SplitLeftOp {
   }
 };
 
-__global__ __launch_bounds__(256) void k_split_left(Task2* tasks) {
-  const Task2* t = &tasks[blockIdx.z];
+__global__ __launch_bounds__(256) void k_split_left(Task2* tasks, const Ent* ents) {
+  const Task2* t = &tasks[ents[blockIdx.z].slot];
   const int k = *t->dim_out;
   const int tm = blockIdx.x * 64, tn = blockIdx.y * 64;
   if (tm >= t->M || tn >= k) return;
@@ -501,48 +567,49 @@ __global__ __launch_bounds__(256) void k_amplitude(const AmpArgs args) {
 #define MPS_LAUNCH_CHECK() \
   do { hipError_t e_ = hipGetLastError(); if (e_ != hipSuccess) return e_; } while (0)
 
-hipError_t launch_prep2(Task2* d_tasks, int ntask, int maxN, hipStream_t st) {
+hipError_t launch_prep2(Task2* d_tasks, const Ent* d_ents, int nent, int maxN, hipStream_t st) {
   long nn = (long)maxN * maxN;
   int gx = (int)((nn + 255) / 256);
   if (gx > 4096) gx = 4096;
   if (gx < 1) gx = 1;
-  hipLaunchKernelGGL(k_prep2, dim3(gx, ntask), dim3(256), 0, st, d_tasks);
+  hipLaunchKernelGGL(k_prep2, dim3(gx, nent), dim3(256), 0, st, d_tasks, d_ents);
   MPS_LAUNCH_CHECK();
   return hipSuccess;
 }
 
-hipError_t launch_theta2(Task2* d_tasks, int ntask, int maxM, int maxN, hipStream_t st) {
-  hipLaunchKernelGGL(k_theta2, dim3((maxM + 63) / 64, (maxN + 63) / 64, ntask), dim3(256), 0, st, d_tasks);
+hipError_t launch_theta2(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, int maxN, hipStream_t st) {
+  hipLaunchKernelGGL(k_theta2, dim3((maxM + 63) / 64, (maxN + 63) / 64, nent), dim3(256), 0, st, d_tasks, d_ents);
   MPS_LAUNCH_CHECK();
   return hipSuccess;
 }
 
-hipError_t launch_jacobi_step(Task2* d_tasks, int ntask, int maxN, int bw, int step, int sweep, double tol_mult,
-                              int maxin, hipStream_t st) {
+hipError_t launch_jacobi_step(Task2* d_tasks, const Ent* d_ents, int nent, int maxN, int bw, int step, double tol_mult,
+                              int maxin, hipStream_t st, long long* phase_clock) {
   const int nb = (maxN + bw - 1) / bw;
   const int nbp = nb + (nb & 1);
-  const dim3 grid(nbp / 2, ntask);
+  const dim3 grid(nbp / 2, nent);
   switch (bw) {
-    case 4: hipLaunchKernelGGL(k_jacobi_step<4>, grid, dim3(256), 0, st, d_tasks, step, sweep, tol_mult, maxin); break;
-    case 8: hipLaunchKernelGGL(k_jacobi_step<8>, grid, dim3(256), 0, st, d_tasks, step, sweep, tol_mult, maxin); break;
-    case 16: hipLaunchKernelGGL(k_jacobi_step<16>, grid, dim3(256), 0, st, d_tasks, step, sweep, tol_mult, maxin); break;
+    case 4: hipLaunchKernelGGL(k_jacobi_step<4>, grid, dim3(256), 0, st, d_tasks, d_ents, step, tol_mult, maxin, phase_clock); break;
+    case 8: hipLaunchKernelGGL(k_jacobi_step<8>, grid, dim3(256), 0, st, d_tasks, d_ents, step, tol_mult, maxin, phase_clock); break;
+    case 16: hipLaunchKernelGGL(k_jacobi_step<16>, grid, dim3(256), 0, st, d_tasks, d_ents, step, tol_mult, maxin, phase_clock); break;
     default: return hipErrorInvalidValue;
   }
   MPS_LAUNCH_CHECK();
   return hipSuccess;
 }
 
-hipError_t launch_truncate(Task2* d_tasks, int ntask, int chi, double eps, double floor_rel, hipStream_t st) {
-  hipLaunchKernelGGL(k_truncate, dim3(ntask), dim3(1024), 0, st, d_tasks, chi, eps, floor_rel);
+hipError_t launch_truncate(Task2* d_tasks, const Ent* d_ents, int nent, int chi, double eps, double floor_rel,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_truncate, dim3(nent), dim3(1024), 0, st, d_tasks, d_ents, chi, eps, floor_rel);
   MPS_LAUNCH_CHECK();
   return hipSuccess;
 }
 
-hipError_t launch_split(Task2* d_tasks, int ntask, int maxM, int maxN, int maxK, hipStream_t st) {
-  hipLaunchKernelGGL(k_split_right, dim3((maxN + 255) / 256, maxK, ntask), dim3(256), 0, st, d_tasks);
+hipError_t launch_split(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, int maxN, int maxK, hipStream_t st) {
+  hipLaunchKernelGGL(k_split_right, dim3((maxN + 255) / 256, maxK, nent), dim3(256), 0, st, d_tasks, d_ents);
   MPS_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_split_left, dim3((maxM + 63) / 64, (maxK + 63) / 64, ntask), dim3(256), 0, st,
-                     d_tasks);
+  hipLaunchKernelGGL(k_split_left, dim3((maxM + 63) / 64, (maxK + 63) / 64, nent), dim3(256), 0, st, d_tasks,
+                     d_ents);
   MPS_LAUNCH_CHECK();
   return hipSuccess;
 }

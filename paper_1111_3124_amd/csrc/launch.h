@@ -13,12 +13,15 @@ struct AmpArgs {
   double2* out;               // count
 };
 
-hipError_t launch_prep2(Task2* d_tasks, int ntask, int maxN, hipStream_t st);
-hipError_t launch_theta2(Task2* d_tasks, int ntask, int maxM, int maxN, hipStream_t st);
-hipError_t launch_jacobi_step(Task2* d_tasks, int ntask, int maxN, int bw, int step, int sweep, double tol_mult,
-                              int maxin, hipStream_t st);
-hipError_t launch_truncate(Task2* d_tasks, int ntask, int chi, double eps, double floor_rel, hipStream_t st);
-hipError_t launch_split(Task2* d_tasks, int ntask, int maxM, int maxN, int maxK, hipStream_t st);
+hipError_t launch_prep2(Task2* d_tasks, const Ent* d_ents, int nent, int maxN, hipStream_t st);
+hipError_t launch_theta2(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, int maxN, hipStream_t st);
+// phase_clock: NULL, or 5 long longs receiving wall_clock64() stamps of block (0, 0)
+// (start, after Gram, after inner Jacobi, end, rotated?) for phase profiling
+hipError_t launch_jacobi_step(Task2* d_tasks, const Ent* d_ents, int nent, int maxN, int bw, int step, double tol_mult,
+                              int maxin, hipStream_t st, long long* phase_clock = nullptr);
+hipError_t launch_truncate(Task2* d_tasks, const Ent* d_ents, int nent, int chi, double eps, double floor_rel,
+                           hipStream_t st);
+hipError_t launch_split(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, int maxN, int maxK, hipStream_t st);
 hipError_t launch_gate1(Task1* d_tasks, int ntask, long maxel, hipStream_t st);
 hipError_t launch_amplitude(const AmpArgs& args, int count, hipStream_t st);
 

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -50,10 +51,12 @@ struct mps_state {
   int max_sweeps_dd = 16;
   int max_inner = 1;
   int block_width = 8;
+  int max_slots = 32;
   double tol_mult = 1.0;
   double rank_floor = 0x1p-44;
   double rank_floor_dd = 0x1p-96;
   bool timing = false;
+  bool debug_sweeps = false;  // MPS_DEBUG_SWEEPS=1: print per-update sweep counts
   // workspace
   char* ws = nullptr;
   size_t ws_size = 0;
@@ -69,6 +72,8 @@ struct mps_state {
   std::vector<hipEvent_t> evpool;
   double tms[8] = {0};
   long tcount[8] = {0};
+  long slot_sweeps = 0, slot_sweeps_dd = 0;  // update-sweeps executed (FP64, dd polish)
+  long long* d_phase = nullptr;               // MPS_DEBUG_PHASES=1: step phase stamps
 };
 
 namespace {
@@ -197,234 +202,391 @@ struct GateRef {
   const double* Ulo;
 };
 
-// ------------------------------------------------------------------ single-site wave
-int run_wave1(mps_state* h, const std::vector<GateRef>& g1) {
-  if (g1.empty()) return MPS_OK;
-  const int nt = (int)g1.size();
-  int rc = ensure_small(h, align_up(sizeof(Task1) * nt));
-  if (rc) return rc;
-  Task1* ht = (Task1*)h->h_stage;
-  long maxel = 0;
-  for (int i = 0; i < nt; ++i) {
-    const int s = g1[i].first;
-    Task1 t{};
-    t.B = h->B[s];
-    t.B_lo = h->Blo.empty() ? nullptr : h->Blo[s];
-    t.ld = h->capx[s + 1];
-    t.a = h->dimx[s];
-    t.b = h->dimx[s + 1];
-    for (int e = 0; e < 4; ++e) {
-      t.U[e] = make_double2(g1[i].U[2 * e], g1[i].U[2 * e + 1]);
-      t.U_lo[e] = g1[i].Ulo ? make_double2(g1[i].Ulo[2 * e], g1[i].Ulo[2 * e + 1]) : make_double2(0, 0);
-    }
-    ht[i] = t;
-    maxel = std::max(maxel, (long)t.a * t.b);
-  }
-  Task1* dt = (Task1*)h->d_small;
-  HIPCHK(h, hipMemcpyAsync(dt, ht, sizeof(Task1) * nt, hipMemcpyHostToDevice, h->stream));
-  {
-    Timed tm(h, 4);
-    hipError_t e = (h->prec == MPS_PREC_DD) ? mpsk::launch_gate1_dd(dt, nt, maxel, h->stream)
-                                            : mpsk::launch_gate1(dt, nt, maxel, h->stream);
-    if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("gate1: ") + hipGetErrorString(e));
-  }
-  // the staging buffer is reused by the next wave: wait for the copy
-  HIPCHK(h, hipStreamSynchronize(h->stream));
-  harvest_timing(h);
-  h->last.splits = 0;
-  return MPS_OK;
+// ------------------------------------------------------------------ two-site scheduler
+// Continuous batching of two-site updates.  Each update occupies a slot (task
+// descriptor + workspace).  One scheduler tick:
+//   1. admit queued gates whose sites are free and not claimed by an earlier queued
+//      gate (gates on disjoint sites commute, so queue order is kept where it
+//      matters); a single-site gate runs at once, a two-site gate takes a slot and
+//      gets its prep + theta launch;
+//   2. one Jacobi sweep for every slot still iterating (FP64 sweeps, or dd polish
+//      sweeps after the FP64 iteration of a dd handle has converged);
+//   3. read the rotation flags; converged slots are truncated and split at once and
+//      their new bond dimensions read back, which frees their sites.
+// A slow update therefore never holds back updates that do not depend on it.
+struct Slot {
+  int state = 0;  // 0 free, 1 FP64 Jacobi, 2 dd polish, 3 ready to finalise
+  int gate = -1;
+  int sweep = 0;
+  int fp64_sweeps = 0, dd_sweeps = 0;
+  bool fp64_conv = false, conv = false;
+  int M = 0, N = 0;
+};
+
+struct SchedBufs {
+  int S = 0;
+  size_t slot_bytes = 0;
+  // offsets in the small device / pinned areas
+  size_t o_tasks = 0, o_flags = 0, o_stats = 0, o_fro = 0, o_dims = 0, o_ents = 0, o_end = 0;
+  static constexpr int kLists = 6;  // new, jacobi, dd, dd-enter, final, gate1 tasks
+};
+
+size_t slot_workspace_bytes(const mps_state* h, int Mcap, int Ncap) {
+  const bool dd = h->prec == MPS_PREC_DD;
+  const size_t MN = (size_t)Mcap * Ncap, NN = (size_t)Ncap * Ncap;
+  size_t b = align_up((2 * MN + NN) * sizeof(double2)) * (dd ? 2 : 1);
+  if (dd) b += 2 * align_up(NN * sizeof(double2));
+  b += align_up(Ncap * sizeof(double)) * (dd ? 2 : 1) + align_up(Ncap * sizeof(int));
+  return b;
 }
 
-// ------------------------------------------------------------------ two-site wave
-int run_wave2(mps_state* h, const std::vector<GateRef>& g2) {
-  if (g2.empty()) return MPS_OK;
-  const int nt = (int)g2.size();
+void fill_task(mps_state* h, Task2& t, const GateRef& g, char* w, int* d_flags, double* d_stats, double* d_fro,
+               int slot) {
   const bool dd = h->prec == MPS_PREC_DD;
-  // workspace layout per task
-  std::vector<size_t> off(nt + 1, 0);
-  int maxM = 0, maxN = 0;
-  for (int i = 0; i < nt; ++i) {
-    const int s = g2[i].first;
-    const int M = 2 * h->dimx[s], N = 2 * h->dimx[s + 2];
-    maxM = std::max(maxM, M);
-    maxN = std::max(maxN, N);
-    size_t cplx = (size_t)2 * M * N + (size_t)N * N;
-    size_t bytes = align_up(cplx * sizeof(double2)) * (dd ? 2 : 1) + align_up(N * sizeof(double)) * (dd ? 2 : 1) +
-                   align_up(N * sizeof(int)) + (dd ? 2 * align_up((size_t)N * N * sizeof(double2)) : 0);
-    off[i + 1] = off[i] + bytes;
+  const int s = g.first;
+  t = Task2{};
+  t.Bl = h->B[s];
+  t.Br = h->B[s + 1];
+  t.Bl_lo = dd ? h->Blo[s] : nullptr;
+  t.Br_lo = dd ? h->Blo[s + 1] : nullptr;
+  t.ldl = h->capx[s + 1];
+  t.ldr = h->capx[s + 2];
+  t.a = h->dimx[s];
+  t.b = h->dimx[s + 1];
+  t.c = h->dimx[s + 2];
+  t.M = 2 * t.a;
+  t.N = 2 * t.c;
+  t.lamL = h->d_lam + (size_t)s * h->chi;
+  t.lamL_lo = dd ? h->d_lam_lo + (size_t)s * h->chi : nullptr;
+  t.lamS = h->d_lam + (size_t)(s + 1) * h->chi;
+  t.lamS_lo = dd ? h->d_lam_lo + (size_t)(s + 1) * h->chi : nullptr;
+  t.dim_out = h->d_dimx + s + 1;
+  for (int e = 0; e < 16; ++e) {
+    t.U[e] = make_double2(g.U[2 * e], g.U[2 * e + 1]);
+    t.U_lo[e] = (dd && g.Ulo) ? make_double2(g.Ulo[2 * e], g.Ulo[2 * e + 1]) : make_double2(0, 0);
   }
-  int rc = ensure_ws(h, off[nt]);
-  if (rc) return rc;
-  // small device area: tasks | flags (3/task) | stats (8/task) | fro2 (1/task) | dimx copy
-  const size_t o_tasks = 0;
-  const size_t o_flags = align_up(sizeof(Task2) * nt);
-  const size_t o_stats = o_flags + align_up(sizeof(int) * 3 * nt);
-  const size_t o_fro = o_stats + align_up(sizeof(double) * 8 * nt);
-  const size_t o_dims = o_fro + align_up(sizeof(double) * nt);
-  const size_t o_end = o_dims + align_up(sizeof(int) * (h->n + 1));
-  rc = ensure_small(h, o_end);
-  if (rc) return rc;
-  Task2* ht = (Task2*)(h->h_stage + o_tasks);
-  Task2* dt = (Task2*)(h->d_small + o_tasks);
-  int* d_flags = (int*)(h->d_small + o_flags);
-  double* d_stats = (double*)(h->d_small + o_stats);
-  double* d_fro = (double*)(h->d_small + o_fro);
-  for (int i = 0; i < nt; ++i) {
-    const int s = g2[i].first;
-    Task2 t{};
-    t.Bl = h->B[s];
-    t.Br = h->B[s + 1];
-    t.Bl_lo = dd ? h->Blo[s] : nullptr;
-    t.Br_lo = dd ? h->Blo[s + 1] : nullptr;
-    t.ldl = h->capx[s + 1];
-    t.ldr = h->capx[s + 2];
-    t.a = h->dimx[s];
-    t.b = h->dimx[s + 1];
-    t.c = h->dimx[s + 2];
-    t.M = 2 * t.a;
-    t.N = 2 * t.c;
-    t.lamL = h->d_lam + (size_t)s * h->chi;
-    t.lamL_lo = dd ? h->d_lam_lo + (size_t)s * h->chi : nullptr;
-    t.lamS = h->d_lam + (size_t)(s + 1) * h->chi;
-    t.lamS_lo = dd ? h->d_lam_lo + (size_t)(s + 1) * h->chi : nullptr;
-    t.dim_out = h->d_dimx + s + 1;
-    for (int e = 0; e < 16; ++e) {
-      t.U[e] = make_double2(g2[i].U[2 * e], g2[i].U[2 * e + 1]);
-      t.U_lo[e] = (dd && g2[i].Ulo) ? make_double2(g2[i].Ulo[2 * e], g2[i].Ulo[2 * e + 1]) : make_double2(0, 0);
-    }
-    char* w = h->ws + off[i];
-    const size_t MN = (size_t)t.M * t.N, NN = (size_t)t.N * t.N;
-    t.thu = (double2*)w;
-    t.thw = t.thu + MN;
-    t.V = t.thw + MN;
+  const size_t MN = (size_t)t.M * t.N, NN = (size_t)t.N * t.N;
+  t.thu = (double2*)w;
+  t.thw = t.thu + MN;
+  t.V = t.thw + MN;
+  w += align_up((2 * MN + NN) * sizeof(double2));
+  if (dd) {
+    t.thu_lo = (double2*)w;
+    t.thw_lo = t.thu_lo + MN;
+    t.V_lo = t.thw_lo + MN;
     w += align_up((2 * MN + NN) * sizeof(double2));
-    if (dd) {
-      t.thu_lo = (double2*)w;
-      t.thw_lo = t.thu_lo + MN;
-      t.V_lo = t.thw_lo + MN;
-      w += align_up((2 * MN + NN) * sizeof(double2));
-      t.aux1 = (double2*)w;
-      w += align_up(NN * sizeof(double2));
-      t.aux2 = (double2*)w;
-      w += align_up(NN * sizeof(double2));
-    }
-    t.sig2 = (double*)w;
+    t.aux1 = (double2*)w;
+    w += align_up(NN * sizeof(double2));
+    t.aux2 = (double2*)w;
+    w += align_up(NN * sizeof(double2));
+  }
+  t.sig2 = (double*)w;
+  w += align_up(t.N * sizeof(double));
+  if (dd) {
+    t.sig2_lo = (double*)w;
     w += align_up(t.N * sizeof(double));
-    if (dd) {
-      t.sig2_lo = (double*)w;
-      w += align_up(t.N * sizeof(double));
-    }
-    t.perm = (int*)w;
-    t.flags = d_flags + 3 * i;
-    t.stats = d_stats + 8 * i;
-    t.fro2 = d_fro + i;
-    ht[i] = t;
   }
-  HIPCHK(h, hipMemcpyAsync(dt, ht, sizeof(Task2) * nt, hipMemcpyHostToDevice, h->stream));
-  hipError_t e;
-  {
-    Timed tm(h, 0);
-    e = mpsk::launch_prep2(dt, nt, maxN, h->stream);
-    if (e == hipSuccess)
-      e = dd ? mpsk::launch_theta2_dd(dt, nt, maxM, maxN, h->stream)
-             : mpsk::launch_theta2(dt, nt, maxM, maxN, h->stream);
-    if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("theta: ") + hipGetErrorString(e));
-  }
-  // Jacobi sweeps on the FP64 (hi) part of theta_w
+  t.perm = (int*)w;
+  t.flags = d_flags + 3 * slot;
+  t.stats = d_stats + 8 * slot;
+  t.fro2 = d_fro + slot;
+}
+
+int run_gates(mps_state* h, const std::vector<GateRef>& gates) {
+  if (gates.empty()) return MPS_OK;
+  for (const auto& g : gates)
+    if (g.k == 3) return fail(h, MPS_ESTATE, "three-site gates are not available in this build");
+  const bool dd = h->prec == MPS_PREC_DD;
+  // slots and workspace (capacity-sized per slot)
+  int capmax = 1;
+  for (int b = 0; b <= h->n; ++b) capmax = std::max(capmax, h->capx[b]);
+  const int Mcap = 2 * capmax, Ncap = 2 * capmax;
+  int n2 = 0;
+  for (const auto& g : gates) n2 += g.k == 2;
+  const int S = std::max(1, std::min(std::min(h->max_slots, std::max(1, h->n / 2 + 1)), std::max(1, n2)));
+  SchedBufs L;
+  L.S = S;
+  L.slot_bytes = slot_workspace_bytes(h, Mcap, Ncap);
+  int rc = ensure_ws(h, L.slot_bytes * S);
+  if (rc) return rc;
+  L.o_tasks = 0;
+  L.o_flags = align_up(sizeof(Task2) * S);
+  L.o_stats = L.o_flags + align_up(sizeof(int) * 3 * S);
+  L.o_fro = L.o_stats + align_up(sizeof(double) * 8 * S);
+  L.o_dims = L.o_fro + align_up(sizeof(double) * S);
+  L.o_ents = L.o_dims + align_up(sizeof(int) * (h->n + 1));
+  const size_t list_bytes = align_up(std::max(sizeof(mpsk::Ent) * S, sizeof(Task1) * (size_t)h->n));
+  L.o_end = L.o_ents + SchedBufs::kLists * list_bytes;
+  rc = ensure_small(h, L.o_end);
+  if (rc) return rc;
+  Task2* ht = (Task2*)(h->h_stage + L.o_tasks);
+  Task2* dt = (Task2*)(h->d_small + L.o_tasks);
+  int* d_flags = (int*)(h->d_small + L.o_flags);
+  int* hflags = (int*)(h->h_stage + L.o_flags);
+  double* d_stats = (double*)(h->d_small + L.o_stats);
+  double* hstats = (double*)(h->h_stage + L.o_stats);
+  double* d_fro = (double*)(h->d_small + L.o_fro);
+  auto hlist = [&](int i) { return h->h_stage + L.o_ents + i * list_bytes; };
+  auto dlist = [&](int i) { return h->d_small + L.o_ents + i * list_bytes; };
+
+  std::vector<Slot> slot(S);
+  std::vector<char> done(gates.size(), 0), busy(h->n, 0);
+  std::vector<double> gstats(8 * gates.size(), 0.0);
+  std::vector<int> gsweeps(gates.size(), 0), gdd(gates.size(), 0);
+  size_t first_pending = 0;
+  int status = MPS_OK;
   const int bw = h->block_width;
-  const int nb = (maxN + bw - 1) / bw;
-  const int nsteps = nb + (nb & 1) - 1;
-  int* hflags = (int*)(h->h_stage + o_flags);
-  int sweeps = 0;
-  bool converged = false;
-  for (int sw = 0; sw < h->max_sweeps; ++sw) {
-    {
+  const size_t window = (size_t)4 * S + 16;
+  hipError_t e;
+
+  auto upload_list = [&](int li, const std::vector<int>& sl) -> mpsk::Ent* {
+    mpsk::Ent* hl = (mpsk::Ent*)hlist(li);
+    for (size_t i = 0; i < sl.size(); ++i) hl[i] = mpsk::Ent{sl[i], slot[sl[i]].sweep};
+    hipError_t ee = hipMemcpyAsync(dlist(li), hl, sizeof(mpsk::Ent) * sl.size(), hipMemcpyHostToDevice, h->stream);
+    return ee == hipSuccess ? (mpsk::Ent*)dlist(li) : nullptr;
+  };
+
+  bool unsynced = false;  // async copies from the pinned staging may still be pending
+  while (true) {
+    // the staging buffers are rewritten below: wait for copies a previous tick left
+    if (unsynced) {
+      HIPCHK(h, hipStreamSynchronize(h->stream));
+      unsynced = false;
+    }
+    // ---- 1. admission
+    std::vector<int> newl;
+    std::vector<GateRef> g1;
+    std::vector<char> claimed(h->n, 0);
+    int free_slots = 0;
+    for (auto& sl : slot) free_slots += sl.state == 0;
+    while (first_pending < gates.size() && done[first_pending]) ++first_pending;
+    for (size_t gi = first_pending; gi < gates.size() && gi < first_pending + window; ++gi) {
+      if (done[gi]) continue;
+      const GateRef& g = gates[gi];
+      bool free_ = true;
+      for (int q = g.first; q < g.first + g.k; ++q) free_ &= !busy[q] && !claimed[q];
+      if (free_ && g.k == 1) {
+        g1.push_back(g);
+        done[gi] = 1;
+        claimed[g.first] = 1;  // later gates on this site wait for the next pass
+        continue;
+      }
+      if (free_ && g.k == 2 && free_slots > 0) {
+        int si = 0;
+        while (slot[si].state != 0) ++si;
+        Slot& sl = slot[si];
+        sl = Slot{};
+        sl.state = 1;
+        sl.gate = (int)gi;
+        fill_task(h, ht[si], g, h->ws + L.slot_bytes * si, d_flags, d_stats, d_fro, si);
+        sl.M = ht[si].M;
+        sl.N = ht[si].N;
+        for (int q = g.first; q < g.first + g.k; ++q) busy[q] = 1;
+        done[gi] = 1;
+        --free_slots;
+        newl.push_back(si);
+        continue;
+      }
+      for (int q = g.first; q < g.first + g.k; ++q) claimed[q] = 1;
+    }
+    if (!g1.empty()) {
+      Task1* h1 = (Task1*)hlist(5);
+      long maxel = 0;
+      for (size_t i = 0; i < g1.size(); ++i) {
+        const int s0 = g1[i].first;
+        Task1 t{};
+        t.B = h->B[s0];
+        t.B_lo = dd ? h->Blo[s0] : nullptr;
+        t.ld = h->capx[s0 + 1];
+        t.a = h->dimx[s0];
+        t.b = h->dimx[s0 + 1];
+        for (int q = 0; q < 4; ++q) {
+          t.U[q] = make_double2(g1[i].U[2 * q], g1[i].U[2 * q + 1]);
+          t.U_lo[q] = (dd && g1[i].Ulo) ? make_double2(g1[i].Ulo[2 * q], g1[i].Ulo[2 * q + 1]) : make_double2(0, 0);
+        }
+        h1[i] = t;
+        maxel = std::max(maxel, (long)t.a * t.b);
+      }
+      HIPCHK(h, hipMemcpyAsync(dlist(5), h1, sizeof(Task1) * g1.size(), hipMemcpyHostToDevice, h->stream));
+      unsynced = true;
+      Timed tm(h, 4);
+      e = dd ? mpsk::launch_gate1_dd((Task1*)dlist(5), (int)g1.size(), maxel, h->stream)
+             : mpsk::launch_gate1((Task1*)dlist(5), (int)g1.size(), maxel, h->stream);
+      if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("gate1: ") + hipGetErrorString(e));
+    }
+    if (!newl.empty()) {
+      HIPCHK(h, hipMemcpyAsync(dt, ht, sizeof(Task2) * S, hipMemcpyHostToDevice, h->stream));
+      unsynced = true;
+      mpsk::Ent* el = upload_list(0, newl);
+      if (!el) return fail(h, MPS_EDEVICE, "list upload failed");
+      int mM = 0, mN = 0;
+      for (int si : newl) { mM = std::max(mM, slot[si].M); mN = std::max(mN, slot[si].N); }
+      Timed tm(h, 0);
+      e = mpsk::launch_prep2(dt, el, (int)newl.size(), mN, h->stream);
+      if (e == hipSuccess)
+        e = dd ? mpsk::launch_theta2_dd(dt, el, (int)newl.size(), mM, mN, h->stream)
+               : mpsk::launch_theta2(dt, el, (int)newl.size(), mM, mN, h->stream);
+      if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("theta: ") + hipGetErrorString(e));
+    }
+    // ---- 2. one sweep for every iterating slot
+    std::vector<int> jl, dl;
+    for (int si = 0; si < S; ++si) {
+      if (slot[si].state == 1) jl.push_back(si);
+      if (slot[si].state == 2) dl.push_back(si);
+    }
+    if (jl.empty() && dl.empty()) {
+      bool any_active = false;
+      for (auto& sl : slot) any_active |= sl.state != 0;
+      if (!any_active) {
+        while (first_pending < gates.size() && done[first_pending]) ++first_pending;
+        if (first_pending >= gates.size()) break;
+        continue;  // only single-site gates were pending; admit the rest
+      }
+    }
+    if (!jl.empty()) {
+      mpsk::Ent* el = upload_list(1, jl);
+      if (!el) return fail(h, MPS_EDEVICE, "list upload failed");
+      int mN = 0;
+      for (int si : jl) mN = std::max(mN, slot[si].N);
+      const int nb = (mN + bw - 1) / bw;
+      const int nsteps = nb + (nb & 1) - 1;
       Timed tm(h, 1, nsteps);
-      for (int st = 0; st < nsteps; ++st) {
-        e = mpsk::launch_jacobi_step(dt, nt, maxN, bw, st, sw, h->tol_mult, h->max_inner, h->stream);
+      h->slot_sweeps += (long)jl.size();
+      for (int stp = 0; stp < nsteps; ++stp) {
+        long long* pc = (h->d_phase && stp == nsteps / 2) ? h->d_phase : nullptr;
+        e = mpsk::launch_jacobi_step(dt, el, (int)jl.size(), mN, bw, stp, h->tol_mult, h->max_inner, h->stream, pc);
         if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("jacobi: ") + hipGetErrorString(e));
       }
     }
-    HIPCHK(h, hipMemcpyAsync(hflags, d_flags, sizeof(int) * 3 * nt, hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
-    sweeps = sw + 1;
-    bool any = false;
-    for (int i = 0; i < nt; ++i) any |= hflags[3 * i + sw % 3] != 0;
-    if (!any) {
-      converged = true;
-      break;
+    if (!dl.empty()) {
+      mpsk::Ent* el = upload_list(2, dl);
+      if (!el) return fail(h, MPS_EDEVICE, "list upload failed");
+      int mN = 0;
+      for (int si : dl) mN = std::max(mN, slot[si].N);
+      const int nb = (mN + 7) / 8;
+      const int nsteps = nb + (nb & 1) - 1;
+      Timed tm(h, 6, nsteps);
+      h->slot_sweeps_dd += (long)dl.size();
+      for (int stp = 0; stp < nsteps; ++stp) {
+        e = mpsk::launch_jacobi_step_dd(dt, el, (int)dl.size(), mN, stp, h->tol_mult, h->max_inner, h->stream);
+        if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("dd jacobi: ") + hipGetErrorString(e));
+      }
+    }
+    // ---- 3. convergence
+    if (!jl.empty() || !dl.empty()) {
+      HIPCHK(h, hipMemcpyAsync(hflags, d_flags, sizeof(int) * 3 * S, hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(h, hipStreamSynchronize(h->stream));
+      unsynced = false;
+      if (h->d_phase && !jl.empty()) {
+        long long pc[5];
+        HIPCHK(h, hipMemcpy(pc, h->d_phase, sizeof(pc), hipMemcpyDeviceToHost));
+        // wall_clock64 runs at 100 MHz on gfx950
+        std::fprintf(stderr, "[mps] step phases (us, %zu updates, N %d): gram %.1f inner %.1f update %.1f rot %lld\n",
+                     jl.size(), slot[jl[0]].N, (pc[1] - pc[0]) * 0.01, (pc[2] - pc[1]) * 0.01, (pc[3] - pc[2]) * 0.01,
+                     pc[4]);
+      }
+    }
+    std::vector<int> enter;
+    for (int si : jl) {
+      Slot& sl = slot[si];
+      const bool rot = hflags[3 * si + sl.sweep % 3] != 0;
+      ++sl.sweep;
+      if (!rot || sl.sweep >= h->max_sweeps) {
+        sl.fp64_sweeps = sl.sweep;
+        sl.fp64_conv = !rot;
+        if (dd) {
+          enter.push_back(si);
+          sl.state = 2;
+          sl.sweep = 0;
+        } else {
+          sl.conv = sl.fp64_conv;
+          sl.state = 3;
+        }
+      }
+    }
+    for (int si : dl) {
+      Slot& sl = slot[si];
+      const bool rot = hflags[3 * si + sl.sweep % 3] != 0;
+      ++sl.sweep;
+      if (!rot || sl.sweep >= h->max_sweeps_dd) {
+        sl.dd_sweeps = sl.sweep;
+        sl.conv = !rot;
+        sl.state = 3;
+      }
+    }
+    if (!enter.empty()) {
+      unsynced = true;
+      mpsk::Ent* el = upload_list(3, enter);
+      if (!el) return fail(h, MPS_EDEVICE, "list upload failed");
+      int mM = 0, mN = 0;
+      for (int si : enter) { mM = std::max(mM, slot[si].M); mN = std::max(mN, slot[si].N); }
+      Timed tm(h, 6);
+      e = mpsk::launch_dd_enter(dt, el, (int)enter.size(), mM, mN, h->stream);
+      if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("dd enter: ") + hipGetErrorString(e));
+    }
+    // ---- 4. finalise converged slots
+    std::vector<int> fl;
+    for (int si = 0; si < S; ++si)
+      if (slot[si].state == 3) fl.push_back(si);
+    if (!fl.empty()) {
+      mpsk::Ent* el = upload_list(4, fl);
+      if (!el) return fail(h, MPS_EDEVICE, "list upload failed");
+      int mM = 0, mN = 0;
+      for (int si : fl) { mM = std::max(mM, slot[si].M); mN = std::max(mN, slot[si].N); }
+      const int maxK = std::min(h->chi, std::min(mM, mN));
+      {
+        Timed tm(h, 2);
+        e = dd ? mpsk::launch_truncate_dd(dt, el, (int)fl.size(), h->chi, h->eps, h->rank_floor_dd, h->stream)
+               : mpsk::launch_truncate(dt, el, (int)fl.size(), h->chi, h->eps, h->rank_floor, h->stream);
+        if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("truncate: ") + hipGetErrorString(e));
+      }
+      {
+        Timed tm(h, 3);
+        e = dd ? mpsk::launch_split_dd(dt, el, (int)fl.size(), mM, mN, maxK, h->stream)
+               : mpsk::launch_split(dt, el, (int)fl.size(), mM, mN, maxK, h->stream);
+        if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("split: ") + hipGetErrorString(e));
+      }
+      HIPCHK(h, hipMemcpyAsync(hstats, d_stats, sizeof(double) * 8 * S, hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(h, hipMemcpyAsync(h->h_stage + L.o_dims, h->d_dimx, sizeof(int) * (h->n + 1), hipMemcpyDeviceToHost,
+                               h->stream));
+      HIPCHK(h, hipStreamSynchronize(h->stream));
+      unsynced = false;
+      std::memcpy(h->dimx.data(), h->h_stage + L.o_dims, sizeof(int) * (h->n + 1));
+      for (int si : fl) {
+        Slot& sl = slot[si];
+        const GateRef& g = gates[sl.gate];
+        std::memcpy(&gstats[8 * sl.gate], hstats + 8 * si, sizeof(double) * 8);
+        gsweeps[sl.gate] = sl.fp64_sweeps;
+        gdd[sl.gate] = sl.dd_sweeps;
+        if (!sl.conv) status = MPS_ENOCONV;
+        if (h->debug_sweeps)
+          std::fprintf(stderr, "[mps] update at site %d (M %d, N %d): %d FP64 sweeps, %d dd sweeps\n", g.first,
+                       sl.M, sl.N, sl.fp64_sweeps, sl.dd_sweeps);
+        for (int q = g.first; q < g.first + g.k; ++q) busy[q] = 0;
+        sl = Slot{};
+      }
     }
   }
-  int dd_sweeps = 0;
-  bool dd_conv = true;
-  if (dd) {
-    Timed tm(h, 6);
-    int r2 = mpsk::run_dd_refine(dt, nt, maxM, maxN, h->max_sweeps_dd, h->max_inner, h->tol_mult, hflags, d_flags,
-                                 h->stream, &dd_sweeps, &dd_conv);
-    if (r2 != 0) return fail(h, MPS_EDEVICE, "dd refinement failed");
-  }
-  {
-    Timed tm(h, 2);
-    e = dd ? mpsk::launch_truncate_dd(dt, nt, h->chi, h->eps, h->rank_floor_dd, h->stream)
-           : mpsk::launch_truncate(dt, nt, h->chi, h->eps, h->rank_floor, h->stream);
-    if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("truncate: ") + hipGetErrorString(e));
-  }
-  {
-    Timed tm(h, 3);
-    const int maxK = std::min(h->chi, std::min(maxM, maxN));
-    e = dd ? mpsk::launch_split_dd(dt, nt, maxM, maxN, maxK, h->stream)
-           : mpsk::launch_split(dt, nt, maxM, maxN, maxK, h->stream);
-    if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("split: ") + hipGetErrorString(e));
-  }
-  double* hstats = (double*)(h->h_stage + o_stats);
-  HIPCHK(h, hipMemcpyAsync(hstats, d_stats, sizeof(double) * 8 * nt, hipMemcpyDeviceToHost, h->stream));
-  std::vector<int> nd(h->n + 1);
-  HIPCHK(h, hipMemcpyAsync(h->h_stage + o_dims, h->d_dimx, sizeof(int) * (h->n + 1), hipMemcpyDeviceToHost,
-                           h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  std::memcpy(nd.data(), h->h_stage + o_dims, sizeof(int) * (h->n + 1));
-  h->dimx = nd;
   harvest_timing(h);
-  const double* st = hstats + 8 * (nt - 1);
-  h->last.W = st[0];
-  h->last.w = st[1];
-  h->last.gap = st[2];
-  h->last.epsdist = st[3];
-  h->last.k = (int)st[4];
-  h->last.rank = (int)st[5];
-  h->last.sweeps = sweeps;
-  h->last.dd_sweeps = dd_sweeps;
-  h->last.splits = 1;
-  // a dd handle's result is the dd polish: its convergence is what counts
-  if (dd ? !dd_conv : !converged) return fail(h, MPS_ENOCONV, "Jacobi sweep limit reached");
-  return MPS_OK;
-}
-
-// Split a gate list into waves of gates on disjoint sites and run them.
-int run_gates(mps_state* h, const std::vector<GateRef>& gates) {
-  size_t i = 0;
-  int status = MPS_OK;
-  while (i < gates.size()) {
-    std::vector<char> busy(h->n, 0);
-    std::vector<GateRef> w1, w2, w3;
-    size_t j = i;
-    for (; j < gates.size(); ++j) {
-      const GateRef& g = gates[j];
-      bool clash = false;
-      for (int q = g.first; q < g.first + g.k; ++q) clash |= busy[q] != 0;
-      if (clash) break;
-      for (int q = g.first; q < g.first + g.k; ++q) busy[q] = 1;
-      (g.k == 1 ? w1 : g.k == 2 ? w2 : w3).push_back(g);
-    }
-    int rc = run_wave1(h, w1);
-    if (rc) return rc;
-    rc = run_wave2(h, w2);
-    if (rc == MPS_ENOCONV) status = rc;
-    else if (rc) return rc;
-    if (!w3.empty()) return fail(h, MPS_ESTATE, "three-site gates are not available in this build");
-    i = j;
+  // diagnostics of the last two-site gate in queue order
+  for (size_t gi = gates.size(); gi-- > 0;) {
+    if (gates[gi].k != 2) continue;
+    const double* st = &gstats[8 * gi];
+    h->last.W = st[0];
+    h->last.w = st[1];
+    h->last.gap = st[2];
+    h->last.epsdist = st[3];
+    h->last.k = (int)st[4];
+    h->last.rank = (int)st[5];
+    h->last.sweeps = *std::max_element(gsweeps.begin(), gsweeps.end());
+    h->last.dd_sweeps = *std::max_element(gdd.begin(), gdd.end());
+    h->last.splits = 1;
+    break;
   }
-  return status;
+  if (n2 == 0) h->last.splits = 0;
+  if (status) return fail(h, status, "Jacobi sweep limit reached");
+  return MPS_OK;
 }
 
 }  // namespace
@@ -455,6 +617,9 @@ mps_handle mps_create_ex(int n, int chi_max, double eps, int prec, void* hip_str
   h->chi = chi_max;
   h->eps = eps;
   h->prec = prec;
+  if (const char* dbg = std::getenv("MPS_DEBUG_SWEEPS")) h->debug_sweeps = dbg[0] == '1';
+  if (const char* dbg = std::getenv("MPS_DEBUG_PHASES"))
+    if (dbg[0] == '1' && hipMalloc((void**)&h->d_phase, 8 * sizeof(long long)) != hipSuccess) h->d_phase = nullptr;
   auto bail = [&](const char* what, hipError_t e) {
     g_create_error = std::string(what) + ": " + hipGetErrorString(e);
     mps_destroy(h);
@@ -530,6 +695,7 @@ int mps_destroy(mps_handle h) {
   if (h->d_lam) (void)hipFree(h->d_lam);
   if (h->d_lam_lo) (void)hipFree(h->d_lam_lo);
   if (h->d_dimx) (void)hipFree(h->d_dimx);
+  if (h->d_phase) (void)hipFree(h->d_phase);
   if (h->ws) (void)hipFree(h->ws);
   if (h->d_small) (void)hipFree(h->d_small);
   if (h->h_stage) (void)hipHostFree(h->h_stage);
@@ -763,9 +929,16 @@ int mps_sync(mps_handle h) {
 }
 
 int mps_kernel_time(mps_handle h, int cls, double* ms, long* launches, int reset) {
-  if (!h || cls < 0 || cls >= 8) return MPS_EINVAL;
+  if (!h || cls < 0 || cls >= 10) return MPS_EINVAL;
   HIPCHK(h, hipStreamSynchronize(h->stream));
   harvest_timing(h);
+  if (cls >= 8) {  // counters: update-sweeps of the FP64 Jacobi (8) and of the dd polish (9)
+    long& c = cls == 8 ? h->slot_sweeps : h->slot_sweeps_dd;
+    if (ms) *ms = 0.0;
+    if (launches) *launches = c;
+    if (reset) c = 0;
+    return MPS_OK;
+  }
   if (ms) *ms = h->tms[cls];
   if (launches) *launches = h->tcount[cls];
   if (reset) { h->tms[cls] = 0; h->tcount[cls] = 0; }
