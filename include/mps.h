@@ -31,10 +31,11 @@
  *     code; mps_last_error() gives a message.  No exception crosses the ABI.
  *   - Ownership: the caller owns every host buffer passed in or out; the library
  *     copies inputs before returning.  The handle owns all device memory.
- *   - Synchronisation: gate application is queued on the handle's HIP stream and
- *     returns without waiting for the device, except that the library waits for
- *     the new bond dimensions at the end of each gate (or each wave of gates,
- *     see mps_apply_gates).  Every call that returns host data synchronises.
+ *   - Synchronisation: gate application is queued on the handle's HIP stream.
+ *     The library reads back each new bond dimension once its update has
+ *     converged (it sizes later launches), so a gate call returns after the
+ *     device has finished all but the final writes of its last update; every
+ *     call that returns host data synchronises.
  *   - Threads: one thread at a time per handle.
  */
 #ifndef MPS_H_
@@ -104,7 +105,11 @@ int mps_destroy(mps_handle h);
  * k = 1: B_first <- (U (x) 1) B_first; no SVD, Schmidt values unchanged.
  * k = 2: theta = B_s B_{s+1} mixed by U, SVD of diag(V_{s-1}) theta, truncation,
  *        split into B_s, V_s, B_{s+1} (Section 3.1; Vidal's update).
- * k = 3: the same on three sites with two splits.
+ * k = 3: theta = B_s B_{s+1} B_{s+2} mixed by U (8 x 8), SVD of the
+ *        (2 m_{s-1}) x (4 m_{s+2}) matrix diag(V_{s-1}) theta, truncation, split
+ *        into B_s, V_s and the right factor; the right factor weighted by V_s
+ *        is reshaped to (2 m_s) x (2 m_{s+2}) and split again into B_{s+1},
+ *        V_{s+1}, B_{s+2}.  mps_stats then describes the second split.
  * Errors: MPS_EINVAL (first < 0, first + k > n, k not 1..3, U NULL),
  * MPS_ENONFINITE, MPS_ENOCONV, MPS_EDEVICE, MPS_ENOMEM. */
 int mps_apply_gate(mps_handle h, int first, int k, const double* U);
@@ -113,10 +118,17 @@ int mps_apply_gate(mps_handle h, int first, int k, const double* U);
  * handle U_lo is ignored. */
 int mps_apply_gate_dd(mps_handle h, int first, int k, const double* U_hi, const double* U_lo);
 
-/* Apply `count` gates in order.  Consecutive gates acting on disjoint sites form a
- * wave that runs as one batched launch per kernel (gates on disjoint sites
- * commute, so the result equals applying them one by one).  first[i], k[i];
- * U packed back to back (2 * 4^k[i] doubles each); U_lo NULL or same packing. */
+/* Apply `count` gates in order.  The library's scheduler admits a gate as soon as
+ * none of its sites is held by an unfinished update and no earlier, still
+ * waiting gate touches them; admitted updates iterate together, one batched
+ * launch per kernel and Jacobi step for all of them, and each finishes as soon
+ * as its own SVD has converged.  Only gates on disjoint sites ever run at the
+ * same time and gates on shared sites keep their order, so the result equals
+ * applying the gates one by one.  first[i], k[i]; U packed back to back
+ * (2 * 4^k[i] doubles each); U_lo NULL or same packing.  Every gate is checked
+ * before any runs: an invalid one (MPS_EINVAL, MPS_ENONFINITE) applies none of
+ * the list.  MPS_ENOCONV (some update hit the sweep limit; its result is still
+ * used) is reported after all gates ran; MPS_EDEVICE leaves the state undefined. */
 int mps_apply_gates(mps_handle h, int count, const int* first, const int* k,
                     const double* U, const double* U_lo);
 

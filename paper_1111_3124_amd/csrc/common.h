@@ -75,8 +75,16 @@ struct Task2 {
   double* sig2_lo;
   int* perm;            // N: column order, sigma descending
   double* fro2;         // ||thw||_F^2 (zero-column threshold)
-  double* stats;        // 8 doubles: W, w, gap, epsdist, k, rank, nu, W_lo
-  int* flags;           // 2 ints: rotation flags of the current / previous sweep
+  double* stats;        // 8 doubles: W, w, gap, epsdist, k, rank, nu (hi, lo)
+  int* flags;           // 3 ints: rotation flags of the current / next / previous sweep
+  // three-site gates (first split): theta is 2a x 4d, columns (j*2 + k)*d + delta
+  const double2* B3;    // site s+2 (null for a two-site update)
+  const double2* B3_lo;
+  int ld3, d;           // row length of B3, m_{s+2}
+  const double2* U8;    // 8 x 8 gate, row-major (device copy)
+  const double2* U8_lo;
+  double2* T1;          // scratch: B_s B_{s+1} as (4a x c), column-major
+  double2* T1_lo;
 };
 
 // One entry of a launch list: the task slot a block row works on and, for the

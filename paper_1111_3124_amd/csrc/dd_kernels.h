@@ -13,7 +13,8 @@ hipError_t launch_jacobi_step_dd(Task2* d_tasks, const Ent* d_ents, int nent, in
                                  int maxin, hipStream_t st);
 hipError_t launch_truncate_dd(Task2* d_tasks, const Ent* d_ents, int nent, int chi, double eps, double floor_rel,
                               hipStream_t st);
-hipError_t launch_split_dd(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, int maxN, int maxK, hipStream_t st);
+hipError_t launch_split_dd(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, int maxN, int maxK, hipStream_t st,
+                           bool right = true);
 hipError_t launch_amplitude_dd(const AmpArgs& args, const double2* const* B_lo, int count, hipStream_t st);
 
 }  // namespace mpsk

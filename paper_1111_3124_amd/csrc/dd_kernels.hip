@@ -13,89 +13,13 @@
 #include "dd.h"
 #include "dd_kernels.h"
 #include "gemm.h"
+#include "ddgemm.h"
 
 namespace mpsk {
 
 using dd::cacc;
 using dd::cdd;
 using dd::ddr;
-
-__device__ __forceinline__ cdd ldc(const double2* hi, const double2* lo, long i) {
-  const double2 h = hi[i];
-  const double2 l = lo ? lo[i] : make_double2(0.0, 0.0);
-  return {{h.x, l.x}, {h.y, l.y}};
-}
-__device__ __forceinline__ void stc(double2* hi, double2* lo, long i, cdd v) {
-  hi[i] = make_double2(v.re.hi, v.im.hi);
-  lo[i] = make_double2(v.re.lo, v.im.lo);
-}
-__device__ __forceinline__ cdd czero() { return {{0.0, 0.0}, {0.0, 0.0}}; }
-__device__ __forceinline__ cacc cacc0() { return {{0.0, 0.0}, {0.0, 0.0}}; }
-__device__ __forceinline__ cdd ld_gate(const double2* U, const double2* Ul, int e) {
-  return {{U[e].x, Ul[e].x}, {U[e].y, Ul[e].y}};
-}
-
-// ------------------------------------------------------------------ dd GEMM tile
-// C (m x n) = A B with dd operands: 32 x 32 output tile per 256-thread block, a
-// 2 x 2 register block per thread, K slices of 16 staged through LDS as hi/lo planes.
-template <class Op>
-__device__ __forceinline__ void ddgemm_tile(const Op& op, int m, int n, int kd, int tm, int tn) {
-  __shared__ double2 Ah[16][33], Al[16][33], Bh[16][33], Bl[16][33];
-  const int tid = threadIdx.x;
-  const int tr = tid >> 4, tc = tid & 15;
-  cacc acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = cacc0();
-  for (int k0 = 0; k0 < kd; k0 += 16) {
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int e = tid + 256 * q;
-      int row, kk;
-      if (Op::kARowFast) { row = e & 31; kk = e >> 5; } else { kk = e & 15; row = e >> 4; }
-      const int gr = tm + row, gk = k0 + kk;
-      const cdd v = (gr < m && gk < kd) ? op.a(gr, gk) : czero();
-      Ah[kk][row] = make_double2(v.re.hi, v.im.hi);
-      Al[kk][row] = make_double2(v.re.lo, v.im.lo);
-    }
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int e = tid + 256 * q;
-      int col, kk;
-      if (Op::kBColFast) { col = e & 31; kk = e >> 5; } else { kk = e & 15; col = e >> 4; }
-      const int gc = tn + col, gk = k0 + kk;
-      const cdd v = (gc < n && gk < kd) ? op.b(gk, gc) : czero();
-      Bh[kk][col] = make_double2(v.re.hi, v.im.hi);
-      Bl[kk][col] = make_double2(v.re.lo, v.im.lo);
-    }
-    __syncthreads();
-    for (int kk = 0; kk < 16; ++kk) {
-      cdd av[2], bv[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const double2 h = Ah[kk][tr * 2 + i], l = Al[kk][tr * 2 + i];
-        av[i] = {{h.x, l.x}, {h.y, l.y}};
-      }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const double2 h = Bh[kk][tc * 2 + j], l = Bl[kk][tc * 2 + j];
-        bv[j] = {{h.x, l.x}, {h.y, l.y}};
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) dd::cacc_fma(acc[i][j], av[i], bv[j]);
-    }
-    __syncthreads();
-  }
-  cdd out[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) out[i][j] = dd::cnorm(acc[i][j]);
-  op.epilogue(tm + tr * 2, tn + tc * 2, out);
-}
 
 // ------------------------------------------------------------------ single-site gate
 __global__ __launch_bounds__(256) void k_gate1_dd(Task1* tasks) {
@@ -753,9 +677,12 @@ hipError_t launch_truncate_dd(Task2* d_tasks, const Ent* d_ents, int nent, int c
   return hipSuccess;
 }
 
-hipError_t launch_split_dd(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, int maxN, int maxK, hipStream_t st) {
-  hipLaunchKernelGGL(k_split_right_dd, dim3((maxN + 255) / 256, maxK, nent), dim3(256), 0, st, d_tasks, d_ents);
-  MPS_LAUNCH_CHECK();
+hipError_t launch_split_dd(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, int maxN, int maxK, hipStream_t st,
+                           bool right) {
+  if (right) {
+    hipLaunchKernelGGL(k_split_right_dd, dim3((maxN + 255) / 256, maxK, nent), dim3(256), 0, st, d_tasks, d_ents);
+    MPS_LAUNCH_CHECK();
+  }
   hipLaunchKernelGGL(k_split_left_dd, dim3((maxM + 31) / 32, (maxK + 31) / 32, nent), dim3(256), 0, st, d_tasks,
                      d_ents);
   MPS_LAUNCH_CHECK();

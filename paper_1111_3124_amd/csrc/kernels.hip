@@ -605,9 +605,12 @@ hipError_t launch_truncate(Task2* d_tasks, const Ent* d_ents, int nent, int chi,
   return hipSuccess;
 }
 
-hipError_t launch_split(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, int maxN, int maxK, hipStream_t st) {
-  hipLaunchKernelGGL(k_split_right, dim3((maxN + 255) / 256, maxK, nent), dim3(256), 0, st, d_tasks, d_ents);
-  MPS_LAUNCH_CHECK();
+hipError_t launch_split(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, int maxN, int maxK, hipStream_t st,
+                        bool right) {
+  if (right) {
+    hipLaunchKernelGGL(k_split_right, dim3((maxN + 255) / 256, maxK, nent), dim3(256), 0, st, d_tasks, d_ents);
+    MPS_LAUNCH_CHECK();
+  }
   hipLaunchKernelGGL(k_split_left, dim3((maxM + 63) / 64, (maxK + 63) / 64, nent), dim3(256), 0, st, d_tasks,
                      d_ents);
   MPS_LAUNCH_CHECK();

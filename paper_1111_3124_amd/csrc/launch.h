@@ -21,7 +21,9 @@ hipError_t launch_jacobi_step(Task2* d_tasks, const Ent* d_ents, int nent, int m
                               int maxin, hipStream_t st, long long* phase_clock = nullptr);
 hipError_t launch_truncate(Task2* d_tasks, const Ent* d_ents, int nent, int chi, double eps, double floor_rel,
                            hipStream_t st);
-hipError_t launch_split(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, int maxN, int maxK, hipStream_t st);
+// right = false: only B_s' (the first split of a three-site gate)
+hipError_t launch_split(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, int maxN, int maxK, hipStream_t st,
+                        bool right = true);
 hipError_t launch_gate1(Task1* d_tasks, int ntask, long maxel, hipStream_t st);
 hipError_t launch_amplitude(const AmpArgs& args, int count, hipStream_t st);
 

@@ -17,6 +17,7 @@
 #include "../../include/mps.h"
 #include "common.h"
 #include "dd_kernels.h"
+#include "kernels3.h"
 #include "launch.h"
 
 using mpsk::Task1;
@@ -202,21 +203,26 @@ struct GateRef {
   const double* Ulo;
 };
 
-// ------------------------------------------------------------------ two-site scheduler
-// Continuous batching of two-site updates.  Each update occupies a slot (task
+// ------------------------------------------------------------------ update scheduler
+// Continuous batching of gate updates.  Each two-site split occupies a slot (task
 // descriptor + workspace).  One scheduler tick:
 //   1. admit queued gates whose sites are free and not claimed by an earlier queued
 //      gate (gates on disjoint sites commute, so queue order is kept where it
-//      matters); a single-site gate runs at once, a two-site gate takes a slot and
-//      gets its prep + theta launch;
+//      matters): a single-site gate runs at once; a two-site gate takes a slot and
+//      gets its prep + theta launch; a three-site gate takes a slot for its first
+//      split (s | s+1 s+2) and reserves a second one for its second split;
 //   2. one Jacobi sweep for every slot still iterating (FP64 sweeps, or dd polish
 //      sweeps after the FP64 iteration of a dd handle has converged);
 //   3. read the rotation flags; converged slots are truncated and split at once and
-//      their new bond dimensions read back, which frees their sites.
-// A slow update therefore never holds back updates that do not depend on it.
+//      their new bond dimensions read back.  A finished first split of a three-site
+//      gate hands Z1_k^H, weighted by its new Schmidt values, to the reserved slot as
+//      the theta of the second split; any other finished slot frees its sites.
+// A slow update never holds back updates that do not depend on it.
 struct Slot {
-  int state = 0;  // 0 free, 1 FP64 Jacobi, 2 dd polish, 3 ready to finalise
+  int state = 0;  // 0 free, 1 FP64 Jacobi, 2 dd polish, 3 ready to finalise, 5 reserved
+  int kind = 0;   // 0 two-site, 1 three-site first split, 2 three-site second split
   int gate = -1;
+  int partner = -1;  // kind 1: the reserved slot of the second split
   int sweep = 0;
   int fp64_sweeps = 0, dd_sweeps = 0;
   bool fp64_conv = false, conv = false;
@@ -227,44 +233,23 @@ struct SchedBufs {
   int S = 0;
   size_t slot_bytes = 0;
   // offsets in the small device / pinned areas
-  size_t o_tasks = 0, o_flags = 0, o_stats = 0, o_fro = 0, o_dims = 0, o_ents = 0, o_end = 0;
-  static constexpr int kLists = 6;  // new, jacobi, dd, dd-enter, final, gate1 tasks
+  size_t o_tasks = 0, o_flags = 0, o_stats = 0, o_fro = 0, o_dims = 0, o_u8 = 0, o_ents = 0, o_end = 0;
+  static constexpr int kLists = 9;  // new2, new3, jacobi, dd, dd-enter, final, final3, mid, gate1
 };
 
-size_t slot_workspace_bytes(const mps_state* h, int Mcap, int Ncap) {
+size_t slot_workspace_bytes(const mps_state* h, int Mcap, int Ncap, int t1cap) {
   const bool dd = h->prec == MPS_PREC_DD;
   const size_t MN = (size_t)Mcap * Ncap, NN = (size_t)Ncap * Ncap;
   size_t b = align_up((2 * MN + NN) * sizeof(double2)) * (dd ? 2 : 1);
   if (dd) b += 2 * align_up(NN * sizeof(double2));
   b += align_up(Ncap * sizeof(double)) * (dd ? 2 : 1) + align_up(Ncap * sizeof(int));
+  b += align_up((size_t)t1cap * sizeof(double2)) * (dd ? 2 : 1);
   return b;
 }
 
-void fill_task(mps_state* h, Task2& t, const GateRef& g, char* w, int* d_flags, double* d_stats, double* d_fro,
-               int slot) {
+// workspace pointers of a task whose theta is M x N, carved from the slot region w
+void carve(mps_state* h, Task2& t, char* w, int* d_flags, double* d_stats, double* d_fro, int slot) {
   const bool dd = h->prec == MPS_PREC_DD;
-  const int s = g.first;
-  t = Task2{};
-  t.Bl = h->B[s];
-  t.Br = h->B[s + 1];
-  t.Bl_lo = dd ? h->Blo[s] : nullptr;
-  t.Br_lo = dd ? h->Blo[s + 1] : nullptr;
-  t.ldl = h->capx[s + 1];
-  t.ldr = h->capx[s + 2];
-  t.a = h->dimx[s];
-  t.b = h->dimx[s + 1];
-  t.c = h->dimx[s + 2];
-  t.M = 2 * t.a;
-  t.N = 2 * t.c;
-  t.lamL = h->d_lam + (size_t)s * h->chi;
-  t.lamL_lo = dd ? h->d_lam_lo + (size_t)s * h->chi : nullptr;
-  t.lamS = h->d_lam + (size_t)(s + 1) * h->chi;
-  t.lamS_lo = dd ? h->d_lam_lo + (size_t)(s + 1) * h->chi : nullptr;
-  t.dim_out = h->d_dimx + s + 1;
-  for (int e = 0; e < 16; ++e) {
-    t.U[e] = make_double2(g.U[2 * e], g.U[2 * e + 1]);
-    t.U_lo[e] = (dd && g.Ulo) ? make_double2(g.Ulo[2 * e], g.Ulo[2 * e + 1]) : make_double2(0, 0);
-  }
   const size_t MN = (size_t)t.M * t.N, NN = (size_t)t.N * t.N;
   t.thu = (double2*)w;
   t.thw = t.thu + MN;
@@ -287,26 +272,57 @@ void fill_task(mps_state* h, Task2& t, const GateRef& g, char* w, int* d_flags, 
     w += align_up(t.N * sizeof(double));
   }
   t.perm = (int*)w;
+  w += align_up(t.N * sizeof(int));
+  if (t.B3) {
+    const size_t t1 = (size_t)4 * t.a * t.c;
+    t.T1 = (double2*)w;
+    w += align_up(t1 * sizeof(double2));
+    if (dd) t.T1_lo = (double2*)w;
+  }
   t.flags = d_flags + 3 * slot;
   t.stats = d_stats + 8 * slot;
   t.fro2 = d_fro + slot;
 }
 
+// the two-site split between sites s and s+1 with bond dims a | (b) | c
+void setup_split(mps_state* h, Task2& t, int s, int a, int b, int c) {
+  const bool dd = h->prec == MPS_PREC_DD;
+  t = Task2{};
+  t.Bl = h->B[s];
+  t.Br = h->B[s + 1];
+  t.Bl_lo = dd ? h->Blo[s] : nullptr;
+  t.Br_lo = dd ? h->Blo[s + 1] : nullptr;
+  t.ldl = h->capx[s + 1];
+  t.ldr = h->capx[s + 2];
+  t.a = a;
+  t.b = b;
+  t.c = c;
+  t.M = 2 * a;
+  t.N = 2 * c;
+  t.lamL = h->d_lam + (size_t)s * h->chi;
+  t.lamL_lo = dd ? h->d_lam_lo + (size_t)s * h->chi : nullptr;
+  t.lamS = h->d_lam + (size_t)(s + 1) * h->chi;
+  t.lamS_lo = dd ? h->d_lam_lo + (size_t)(s + 1) * h->chi : nullptr;
+  t.dim_out = h->d_dimx + s + 1;
+}
+
 int run_gates(mps_state* h, const std::vector<GateRef>& gates) {
   if (gates.empty()) return MPS_OK;
-  for (const auto& g : gates)
-    if (g.k == 3) return fail(h, MPS_ESTATE, "three-site gates are not available in this build");
   const bool dd = h->prec == MPS_PREC_DD;
-  // slots and workspace (capacity-sized per slot)
   int capmax = 1;
   for (int b = 0; b <= h->n; ++b) capmax = std::max(capmax, h->capx[b]);
-  const int Mcap = 2 * capmax, Ncap = 2 * capmax;
-  int n2 = 0;
-  for (const auto& g : gates) n2 += g.k == 2;
-  const int S = std::max(1, std::min(std::min(h->max_slots, std::max(1, h->n / 2 + 1)), std::max(1, n2)));
+  int n2 = 0, n3 = 0;
+  for (const auto& g : gates) {
+    n2 += g.k == 2;
+    n3 += g.k == 3;
+  }
+  const int Mcap = 2 * capmax, Ncap = (n3 ? 4 : 2) * capmax;
+  const int t1cap = n3 ? 4 * capmax * capmax : 0;
+  const int S = std::max(n3 ? 2 : 1,
+                         std::min(std::min(h->max_slots, std::max(2, h->n / 2 + 1)), std::max(1, n2 + 2 * n3)));
   SchedBufs L;
   L.S = S;
-  L.slot_bytes = slot_workspace_bytes(h, Mcap, Ncap);
+  L.slot_bytes = slot_workspace_bytes(h, Mcap, Ncap, t1cap);
   int rc = ensure_ws(h, L.slot_bytes * S);
   if (rc) return rc;
   L.o_tasks = 0;
@@ -314,7 +330,8 @@ int run_gates(mps_state* h, const std::vector<GateRef>& gates) {
   L.o_stats = L.o_flags + align_up(sizeof(int) * 3 * S);
   L.o_fro = L.o_stats + align_up(sizeof(double) * 8 * S);
   L.o_dims = L.o_fro + align_up(sizeof(double) * S);
-  L.o_ents = L.o_dims + align_up(sizeof(int) * (h->n + 1));
+  L.o_u8 = L.o_dims + align_up(sizeof(int) * (h->n + 1));
+  L.o_ents = L.o_u8 + align_up(sizeof(double2) * 128 * S);
   const size_t list_bytes = align_up(std::max(sizeof(mpsk::Ent) * S, sizeof(Task1) * (size_t)h->n));
   L.o_end = L.o_ents + SchedBufs::kLists * list_bytes;
   rc = ensure_small(h, L.o_end);
@@ -326,6 +343,9 @@ int run_gates(mps_state* h, const std::vector<GateRef>& gates) {
   double* d_stats = (double*)(h->d_small + L.o_stats);
   double* hstats = (double*)(h->h_stage + L.o_stats);
   double* d_fro = (double*)(h->d_small + L.o_fro);
+  double2* hu8 = (double2*)(h->h_stage + L.o_u8);
+  double2* du8 = (double2*)(h->d_small + L.o_u8);
+  enum { LN2 = 0, LN3, LJ, LD, LENTER, LFIN, LFIN3, LMID, LG1 };
   auto hlist = [&](int i) { return h->h_stage + L.o_ents + i * list_bytes; };
   auto dlist = [&](int i) { return h->d_small + L.o_ents + i * list_bytes; };
 
@@ -339,11 +359,21 @@ int run_gates(mps_state* h, const std::vector<GateRef>& gates) {
   const size_t window = (size_t)4 * S + 16;
   hipError_t e;
 
-  auto upload_list = [&](int li, const std::vector<int>& sl) -> mpsk::Ent* {
+  auto upload_list = [&](int li, const std::vector<mpsk::Ent>& ents) -> mpsk::Ent* {
     mpsk::Ent* hl = (mpsk::Ent*)hlist(li);
-    for (size_t i = 0; i < sl.size(); ++i) hl[i] = mpsk::Ent{sl[i], slot[sl[i]].sweep};
-    hipError_t ee = hipMemcpyAsync(dlist(li), hl, sizeof(mpsk::Ent) * sl.size(), hipMemcpyHostToDevice, h->stream);
+    for (size_t i = 0; i < ents.size(); ++i) hl[i] = ents[i];
+    hipError_t ee = hipMemcpyAsync(dlist(li), hl, sizeof(mpsk::Ent) * ents.size(), hipMemcpyHostToDevice, h->stream);
     return ee == hipSuccess ? (mpsk::Ent*)dlist(li) : nullptr;
+  };
+  auto ents_of = [&](const std::vector<int>& sl) {
+    std::vector<mpsk::Ent> v;
+    for (int si : sl) v.push_back(mpsk::Ent{si, slot[si].sweep});
+    return v;
+  };
+  auto free_slot = [&]() {
+    for (int si = 0; si < S; ++si)
+      if (slot[si].state == 0) return si;
+    return -1;
   };
 
   bool unsynced = false;  // async copies from the pinned staging may still be pending
@@ -354,7 +384,7 @@ int run_gates(mps_state* h, const std::vector<GateRef>& gates) {
       unsynced = false;
     }
     // ---- 1. admission
-    std::vector<int> newl;
+    std::vector<int> new2, new3;
     std::vector<GateRef> g1;
     std::vector<char> claimed(h->n, 0);
     int free_slots = 0;
@@ -371,26 +401,61 @@ int run_gates(mps_state* h, const std::vector<GateRef>& gates) {
         claimed[g.first] = 1;  // later gates on this site wait for the next pass
         continue;
       }
-      if (free_ && g.k == 2 && free_slots > 0) {
-        int si = 0;
-        while (slot[si].state != 0) ++si;
+      if (free_ && ((g.k == 2 && free_slots >= 1) || (g.k == 3 && free_slots >= 2))) {
+        const int si = free_slot();
         Slot& sl = slot[si];
         sl = Slot{};
         sl.state = 1;
         sl.gate = (int)gi;
-        fill_task(h, ht[si], g, h->ws + L.slot_bytes * si, d_flags, d_stats, d_fro, si);
-        sl.M = ht[si].M;
-        sl.N = ht[si].N;
+        const int s0 = g.first;
+        Task2& t = ht[si];
+        if (g.k == 2) {
+          setup_split(h, t, s0, h->dimx[s0], h->dimx[s0 + 1], h->dimx[s0 + 2]);
+          for (int q = 0; q < 16; ++q) {
+            t.U[q] = make_double2(g.U[2 * q], g.U[2 * q + 1]);
+            t.U_lo[q] = (dd && g.Ulo) ? make_double2(g.Ulo[2 * q], g.Ulo[2 * q + 1]) : make_double2(0, 0);
+          }
+          new2.push_back(si);
+        } else {
+          setup_split(h, t, s0, h->dimx[s0], h->dimx[s0 + 1], h->dimx[s0 + 2]);
+          t.B3 = h->B[s0 + 2];
+          t.B3_lo = dd ? h->Blo[s0 + 2] : nullptr;
+          t.ld3 = h->capx[s0 + 3];
+          t.d = h->dimx[s0 + 3];
+          t.N = 4 * t.d;
+          double2* u8h = hu8 + 128 * si;
+          for (int q = 0; q < 64; ++q) {
+            u8h[q] = make_double2(g.U[2 * q], g.U[2 * q + 1]);
+            u8h[64 + q] = (dd && g.Ulo) ? make_double2(g.Ulo[2 * q], g.Ulo[2 * q + 1]) : make_double2(0, 0);
+          }
+          t.U8 = du8 + 128 * si;
+          t.U8_lo = du8 + 128 * si + 64;
+          sl.kind = 1;
+          const int sb = [&] {
+            for (int j = 0; j < S; ++j)
+              if (j != si && slot[j].state == 0) return j;
+            return -1;
+          }();
+          slot[sb] = Slot{};
+          slot[sb].state = 5;
+          slot[sb].kind = 2;
+          slot[sb].gate = (int)gi;
+          sl.partner = sb;
+          --free_slots;
+          new3.push_back(si);
+        }
+        carve(h, t, h->ws + L.slot_bytes * si, d_flags, d_stats, d_fro, si);
+        sl.M = t.M;
+        sl.N = t.N;
         for (int q = g.first; q < g.first + g.k; ++q) busy[q] = 1;
         done[gi] = 1;
         --free_slots;
-        newl.push_back(si);
         continue;
       }
       for (int q = g.first; q < g.first + g.k; ++q) claimed[q] = 1;
     }
     if (!g1.empty()) {
-      Task1* h1 = (Task1*)hlist(5);
+      Task1* h1 = (Task1*)hlist(LG1);
       long maxel = 0;
       for (size_t i = 0; i < g1.size(); ++i) {
         const int s0 = g1[i].first;
@@ -407,26 +472,42 @@ int run_gates(mps_state* h, const std::vector<GateRef>& gates) {
         h1[i] = t;
         maxel = std::max(maxel, (long)t.a * t.b);
       }
-      HIPCHK(h, hipMemcpyAsync(dlist(5), h1, sizeof(Task1) * g1.size(), hipMemcpyHostToDevice, h->stream));
+      HIPCHK(h, hipMemcpyAsync(dlist(LG1), h1, sizeof(Task1) * g1.size(), hipMemcpyHostToDevice, h->stream));
       unsynced = true;
       Timed tm(h, 4);
-      e = dd ? mpsk::launch_gate1_dd((Task1*)dlist(5), (int)g1.size(), maxel, h->stream)
-             : mpsk::launch_gate1((Task1*)dlist(5), (int)g1.size(), maxel, h->stream);
+      e = dd ? mpsk::launch_gate1_dd((Task1*)dlist(LG1), (int)g1.size(), maxel, h->stream)
+             : mpsk::launch_gate1((Task1*)dlist(LG1), (int)g1.size(), maxel, h->stream);
       if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("gate1: ") + hipGetErrorString(e));
     }
-    if (!newl.empty()) {
+    if (!new2.empty() || !new3.empty()) {
       HIPCHK(h, hipMemcpyAsync(dt, ht, sizeof(Task2) * S, hipMemcpyHostToDevice, h->stream));
+      if (!new3.empty())
+        HIPCHK(h, hipMemcpyAsync(du8, hu8, sizeof(double2) * 128 * S, hipMemcpyHostToDevice, h->stream));
       unsynced = true;
-      mpsk::Ent* el = upload_list(0, newl);
-      if (!el) return fail(h, MPS_EDEVICE, "list upload failed");
-      int mM = 0, mN = 0;
-      for (int si : newl) { mM = std::max(mM, slot[si].M); mN = std::max(mN, slot[si].N); }
       Timed tm(h, 0);
-      e = mpsk::launch_prep2(dt, el, (int)newl.size(), mN, h->stream);
-      if (e == hipSuccess)
-        e = dd ? mpsk::launch_theta2_dd(dt, el, (int)newl.size(), mM, mN, h->stream)
-               : mpsk::launch_theta2(dt, el, (int)newl.size(), mM, mN, h->stream);
-      if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("theta: ") + hipGetErrorString(e));
+      for (int which = 0; which < 2; ++which) {
+        const std::vector<int>& nl = which ? new3 : new2;
+        if (nl.empty()) continue;
+        mpsk::Ent* el = upload_list(which ? LN3 : LN2, ents_of(nl));
+        if (!el) return fail(h, MPS_EDEVICE, "list upload failed");
+        int mM = 0, mN = 0, mA = 0, mC = 0, mD = 0;
+        for (int si : nl) {
+          mM = std::max(mM, slot[si].M);
+          mN = std::max(mN, slot[si].N);
+          mA = std::max(mA, ht[si].a);
+          mC = std::max(mC, ht[si].c);
+          mD = std::max(mD, ht[si].d);
+        }
+        e = mpsk::launch_prep2(dt, el, (int)nl.size(), mN, h->stream);
+        if (e == hipSuccess) {
+          if (which)
+            e = mpsk::launch_theta3(dt, el, (int)nl.size(), mA, mC, mD, dd, h->stream);
+          else
+            e = dd ? mpsk::launch_theta2_dd(dt, el, (int)nl.size(), mM, mN, h->stream)
+                   : mpsk::launch_theta2(dt, el, (int)nl.size(), mM, mN, h->stream);
+        }
+        if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("theta: ") + hipGetErrorString(e));
+      }
     }
     // ---- 2. one sweep for every iterating slot
     std::vector<int> jl, dl;
@@ -444,7 +525,7 @@ int run_gates(mps_state* h, const std::vector<GateRef>& gates) {
       }
     }
     if (!jl.empty()) {
-      mpsk::Ent* el = upload_list(1, jl);
+      mpsk::Ent* el = upload_list(LJ, ents_of(jl));
       if (!el) return fail(h, MPS_EDEVICE, "list upload failed");
       int mN = 0;
       for (int si : jl) mN = std::max(mN, slot[si].N);
@@ -459,7 +540,7 @@ int run_gates(mps_state* h, const std::vector<GateRef>& gates) {
       }
     }
     if (!dl.empty()) {
-      mpsk::Ent* el = upload_list(2, dl);
+      mpsk::Ent* el = upload_list(LD, ents_of(dl));
       if (!el) return fail(h, MPS_EDEVICE, "list upload failed");
       int mN = 0;
       for (int si : dl) mN = std::max(mN, slot[si].N);
@@ -516,7 +597,7 @@ int run_gates(mps_state* h, const std::vector<GateRef>& gates) {
     }
     if (!enter.empty()) {
       unsynced = true;
-      mpsk::Ent* el = upload_list(3, enter);
+      mpsk::Ent* el = upload_list(LENTER, ents_of(enter));
       if (!el) return fail(h, MPS_EDEVICE, "list upload failed");
       int mM = 0, mN = 0;
       for (int si : enter) { mM = std::max(mM, slot[si].M); mN = std::max(mN, slot[si].N); }
@@ -525,15 +606,17 @@ int run_gates(mps_state* h, const std::vector<GateRef>& gates) {
       if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("dd enter: ") + hipGetErrorString(e));
     }
     // ---- 4. finalise converged slots
-    std::vector<int> fl;
+    std::vector<int> fl, fl2, fl3;
     for (int si = 0; si < S; ++si)
-      if (slot[si].state == 3) fl.push_back(si);
+      if (slot[si].state == 3) {
+        fl.push_back(si);
+        (slot[si].kind == 1 ? fl3 : fl2).push_back(si);
+      }
     if (!fl.empty()) {
-      mpsk::Ent* el = upload_list(4, fl);
+      mpsk::Ent* el = upload_list(LFIN, ents_of(fl));
       if (!el) return fail(h, MPS_EDEVICE, "list upload failed");
       int mM = 0, mN = 0;
       for (int si : fl) { mM = std::max(mM, slot[si].M); mN = std::max(mN, slot[si].N); }
-      const int maxK = std::min(h->chi, std::min(mM, mN));
       {
         Timed tm(h, 2);
         e = dd ? mpsk::launch_truncate_dd(dt, el, (int)fl.size(), h->chi, h->eps, h->rank_floor_dd, h->stream)
@@ -542,9 +625,18 @@ int run_gates(mps_state* h, const std::vector<GateRef>& gates) {
       }
       {
         Timed tm(h, 3);
-        e = dd ? mpsk::launch_split_dd(dt, el, (int)fl.size(), mM, mN, maxK, h->stream)
-               : mpsk::launch_split(dt, el, (int)fl.size(), mM, mN, maxK, h->stream);
-        if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("split: ") + hipGetErrorString(e));
+        for (int which = 0; which < 2; ++which) {
+          const std::vector<int>& ll = which ? fl3 : fl2;
+          if (ll.empty()) continue;
+          mpsk::Ent* e2 = which ? upload_list(LFIN3, ents_of(ll)) : upload_list(LMID, ents_of(ll));
+          if (!e2) return fail(h, MPS_EDEVICE, "list upload failed");
+          int lM = 0, lN = 0;
+          for (int si : ll) { lM = std::max(lM, slot[si].M); lN = std::max(lN, slot[si].N); }
+          const int maxK = std::min(h->chi, std::min(lM, lN));
+          e = dd ? mpsk::launch_split_dd(dt, e2, (int)ll.size(), lM, lN, maxK, h->stream, which == 0)
+                 : mpsk::launch_split(dt, e2, (int)ll.size(), lM, lN, maxK, h->stream, which == 0);
+          if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("split: ") + hipGetErrorString(e));
+        }
       }
       HIPCHK(h, hipMemcpyAsync(hstats, d_stats, sizeof(double) * 8 * S, hipMemcpyDeviceToHost, h->stream));
       HIPCHK(h, hipMemcpyAsync(h->h_stage + L.o_dims, h->d_dimx, sizeof(int) * (h->n + 1), hipMemcpyDeviceToHost,
@@ -552,16 +644,53 @@ int run_gates(mps_state* h, const std::vector<GateRef>& gates) {
       HIPCHK(h, hipStreamSynchronize(h->stream));
       unsynced = false;
       std::memcpy(h->dimx.data(), h->h_stage + L.o_dims, sizeof(int) * (h->n + 1));
-      for (int si : fl) {
+      // first splits of three-site gates: the second split takes over in the reserved slot
+      std::vector<mpsk::Ent> mids;
+      std::vector<int> newB;
+      int mN1 = 0, mK1 = 0, mNB = 0;
+      for (int si : fl3) {
+        Slot& sa = slot[si];
+        const GateRef& g = gates[sa.gate];
+        const int s0 = g.first, sb = sa.partner;
+        Task2& tb = ht[sb];
+        setup_split(h, tb, s0 + 1, h->dimx[s0 + 1], 0, h->dimx[s0 + 3]);
+        carve(h, tb, h->ws + L.slot_bytes * sb, d_flags, d_stats, d_fro, sb);
+        Slot& sbl = slot[sb];
+        sbl.state = 1;
+        sbl.sweep = 0;
+        sbl.M = tb.M;
+        sbl.N = tb.N;
+        gsweeps[sa.gate] = sa.fp64_sweeps;
+        gdd[sa.gate] = sa.dd_sweeps;
+        if (!sa.conv) status = MPS_ENOCONV;
+        mids.push_back(mpsk::Ent{si, sb});
+        newB.push_back(sb);
+        mN1 = std::max(mN1, sa.N);
+        mK1 = std::max(mK1, std::min(h->chi, sa.M));
+        mNB = std::max(mNB, tb.N);
+      }
+      if (!mids.empty()) {
+        HIPCHK(h, hipMemcpyAsync(dt, ht, sizeof(Task2) * S, hipMemcpyHostToDevice, h->stream));
+        unsynced = true;
+        mpsk::Ent* eb = upload_list(LN2, ents_of(newB));
+        mpsk::Ent* em = upload_list(LN3, mids);
+        if (!eb || !em) return fail(h, MPS_EDEVICE, "list upload failed");
+        Timed tm(h, 0);
+        e = mpsk::launch_prep2(dt, eb, (int)newB.size(), mNB, h->stream);
+        if (e == hipSuccess) e = mpsk::launch_mid3(dt, em, (int)mids.size(), mN1, mK1, dd, h->stream);
+        if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("mid: ") + hipGetErrorString(e));
+        for (int si : fl3) slot[si] = Slot{};  // its V is read by the mid kernel, queued before any reuse
+      }
+      for (int si : fl2) {
         Slot& sl = slot[si];
         const GateRef& g = gates[sl.gate];
         std::memcpy(&gstats[8 * sl.gate], hstats + 8 * si, sizeof(double) * 8);
-        gsweeps[sl.gate] = sl.fp64_sweeps;
-        gdd[sl.gate] = sl.dd_sweeps;
+        gsweeps[sl.gate] = std::max(gsweeps[sl.gate], sl.fp64_sweeps);
+        gdd[sl.gate] = std::max(gdd[sl.gate], sl.dd_sweeps);
         if (!sl.conv) status = MPS_ENOCONV;
         if (h->debug_sweeps)
-          std::fprintf(stderr, "[mps] update at site %d (M %d, N %d): %d FP64 sweeps, %d dd sweeps\n", g.first,
-                       sl.M, sl.N, sl.fp64_sweeps, sl.dd_sweeps);
+          std::fprintf(stderr, "[mps] update at site %d (M %d, N %d, kind %d): %d FP64 sweeps, %d dd sweeps\n",
+                       g.first, sl.M, sl.N, sl.kind, sl.fp64_sweeps, sl.dd_sweeps);
         for (int q = g.first; q < g.first + g.k; ++q) busy[q] = 0;
         sl = Slot{};
       }
@@ -569,9 +698,10 @@ int run_gates(mps_state* h, const std::vector<GateRef>& gates) {
   }
   HIPCHK(h, hipStreamSynchronize(h->stream));
   harvest_timing(h);
-  // diagnostics of the last two-site gate in queue order
+  // diagnostics of the last multi-site gate in queue order
+  h->last.splits = 0;
   for (size_t gi = gates.size(); gi-- > 0;) {
-    if (gates[gi].k != 2) continue;
+    if (gates[gi].k == 1) continue;
     const double* st = &gstats[8 * gi];
     h->last.W = st[0];
     h->last.w = st[1];
@@ -581,10 +711,9 @@ int run_gates(mps_state* h, const std::vector<GateRef>& gates) {
     h->last.rank = (int)st[5];
     h->last.sweeps = *std::max_element(gsweeps.begin(), gsweeps.end());
     h->last.dd_sweeps = *std::max_element(gdd.begin(), gdd.end());
-    h->last.splits = 1;
+    h->last.splits = gates[gi].k - 1;
     break;
   }
-  if (n2 == 0) h->last.splits = 0;
   if (status) return fail(h, status, "Jacobi sweep limit reached");
   return MPS_OK;
 }

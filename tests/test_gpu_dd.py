@@ -183,3 +183,41 @@ def test_ghz_dd(B):
     for bits in ([0] * n, [1] * n):
         h, l = B.mps_amplitude_dd(d.h, bits)
         assert abs(mpmath.mpf(h.real) + mpmath.mpf(l.real) - s) < 1e-30
+
+
+def test_paper_sample_three_site_dd(B):
+    flush("dd paper sample (k=3)")
+    d = B.MPS(3, 8, 0.0, B.MPS_PREC_DD)
+    d.apply_gates(W.paper_sample_circuit())
+    gh, gl = d.amplitudes(all_bits(3), dd=True)
+    s = mpmath.mpf(1) / mpmath.sqrt(2)
+    for x in range(8):
+        want = s if x in (0, 5) else 0
+        got = mpmath.mpc(mpmath.mpf(gh[x].real) + mpmath.mpf(gl[x].real), mpmath.mpf(gh[x].imag) + mpmath.mpf(gl[x].imag))
+        assert abs(got - want) < 1e-30
+
+
+def test_three_site_dd_vs_oracle(B, oracle_mod):
+    flush("dd mixed k<=3: n=7 gates=40 seed=21")
+    n = 7
+    gates = W.random_circuit_dd(n, 40, 21)
+    om, _ = oracle_run(oracle_mod, n, 128, 0.0, gates)
+    d = dev_run(B, n, 128, 0.0, gates)
+    bits = all_bits(n)
+    gh, gl = d.amplitudes(bits, dd=True)
+    oh, ol = om.amplitudes(bits)
+    assert dd_diff(gh, gl, oh, ol) <= TOL
+
+
+def test_triples_truncated_dd_vs_oracle(B, oracle_mod):
+    flush("dd triples: n=10 count=30 chi=16 eps=1e-14 seed=3")
+    n = 10
+    gates = W.random_triples(n, 30, 3)
+    om, gaps = oracle_run(oracle_mod, n, 16, 1e-14, gates)
+    assert min(gaps) > 1e-20
+    d = dev_run(B, n, 16, 1e-14, gates)
+    assert d.bond_dims() == om.bond_dims()
+    bits = W.bitstrings(n, 300, 4)
+    gh, gl = d.amplitudes(bits, dd=True)
+    oh, ol = om.amplitudes(bits)
+    assert dd_diff(gh, gl, oh, ol) <= TOL

@@ -211,3 +211,62 @@ def test_sweep_limit_reports_noconv(B):
     with pytest.raises(B.MPSError) as e:
         h.apply(4, 2, W.haar_unitary(4, W.rng_for(12)))
     assert e.value.code == B.MPS_ENOCONV
+
+
+def _paper_rdo_check(amps, tol):
+    """RDOs of the paper's Section 3.2 example from the 8 amplitudes vs the printed
+    values in tests/golden/paper_sample.txt (initial stage checked separately)."""
+    import os
+    rows = [l.split() for l in open(os.path.join(os.path.dirname(__file__), "golden", "paper_sample.txt"))
+            if l.strip() and not l.startswith("#") and l.startswith("final")]
+    psi = np.asarray(amps).reshape(2, 2, 2)  # (q0, q1, q2)
+    rho = np.einsum("aib,cid->abcd", psi, psi.conj()).reshape(4, 4)  # (q0 q2) x (q0 q2)
+    want = np.zeros((4, 4))
+    for r in rows:
+        want[int(r[2], 2), int(r[3], 2)] = float(r[4])
+    assert np.max(np.abs(rho - want)) <= tol
+
+
+def test_paper_sample_three_site(B):
+    """Paper Section 3.2: |000>, H(0), CNOT(0 -> 2) applied as one U(8) on sites 0..2."""
+    flush("paper sample (k=3)")
+    d = B.MPS(3, 8, 0.0)
+    assert abs(d.amplitude([0, 0, 0]) - 1.0) < 1e-15
+    d.apply_gates(W.paper_sample_circuit())
+    assert d.bond_dims() == [2, 2]
+    amps = d.amplitudes(all_bits(3))
+    s = 2 ** -0.5
+    assert np.max(np.abs(amps - np.array([s, 0, 0, 0, 0, s, 0, 0]))) < 1e-15
+    _paper_rdo_check(amps, 1e-15)
+    for b in range(2):
+        assert np.allclose(d.schmidt(b), [s, s], atol=1e-15)
+    assert d.stats()["splits"] == 2
+
+
+def test_three_site_gates_vs_oracle(B, oracle_mod):
+    """Random U(2) / U(4) / U(8) gates (binary64 parts) on 7 qubits, no truncation."""
+    flush("mixed k<=3: n=7 gates=40 seed=21")
+    n = 7
+    gates = [W.Gate(g.first, g.k, g.u_hi) for g in W.random_circuit_dd(n, 40, 21)]
+    assert any(g.k == 3 for g in gates)
+    om, _ = oracle_run(oracle_mod, n, 128, 0.0, gates)
+    dev = B.MPS(n, 128, 0.0)
+    dev.apply_gates(gates)
+    assert dev.bond_dims() == om.bond_dims()
+    bits = all_bits(n)
+    assert np.max(np.abs(dev.amplitudes(bits) - oracle_amps(om, bits))) <= TOL
+
+
+def test_triples_truncated_vs_oracle(B, oracle_mod):
+    """Config-3 pattern at a size the oracle finishes quickly: 10 qubits, 30 Haar U(8)
+    on random contiguous triples, chi_max = 16, eps = 1e-14."""
+    flush("triples: n=10 count=30 chi=16 eps=1e-14 seed=3")
+    n = 10
+    gates = W.random_triples(n, 30, 3)
+    om, gaps = oracle_run(oracle_mod, n, 16, 1e-14, gates)
+    assert min(gaps) > 1e-10
+    dev = B.MPS(n, 16, 1e-14)
+    dev.apply_gates(gates)
+    assert dev.bond_dims() == om.bond_dims()
+    bits = W.bitstrings(n, 300, 4)
+    assert np.max(np.abs(dev.amplitudes(bits) - oracle_amps(om, bits))) <= TOL

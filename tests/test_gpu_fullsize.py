@@ -1,0 +1,56 @@
+"""Parity at the benchmark's size: one two-site update with a = b = c = 256 (theta
+512 x 512, truncation to chi_max = 256 binding) in the benchmark's launch path,
+against stored 256-bit oracle values (tests/golden/update_chi256.json, written by
+tests/golden/make_golden.py from the oracle only).  Checked: new bond dims, the 256
+Schmidt values of the updated bond, and 24 amplitudes."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLD = os.path.join(HERE, "golden", "update_chi256.json")
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1111_3124_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def fixture():
+    sys.path.insert(0, os.path.join(HERE, "golden"))
+    import make_golden
+    return json.load(open(GOLD)), make_golden.update_chi256_inputs()
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-26)])
+def test_update_chi256(B, fixture, prec, tol):
+    g, inp = fixture
+    print(f"full-size update: prec={prec} n={inp['n']} site={inp['first']}", flush=True)
+    assert g["split"]["gap"] > (1e-10 if prec == 0 else 1e-20)
+    d = B.MPS(inp["n"], inp["chi"], inp["eps"], prec)
+    d.load(inp["B"], inp["lam"])
+    d.apply(inp["first"], 2, inp["U"])
+    assert d.bond_dims() == g["dims_after"]
+    oh = np.array(g["schmidt_hi"]); ol = np.array(g["schmidt_lo"])
+    if prec:
+        lh, ll = d.schmidt_dd(inp["first"])
+        assert float(np.max(np.abs((lh - oh) + (ll - ol)))) <= tol
+    else:
+        assert float(np.max(np.abs(d.schmidt(inp["first"]) - (oh + ol)))) <= tol
+    ah = np.array(g["amp_re_hi"]) + 1j * np.array(g["amp_im_hi"])
+    al = np.array(g["amp_re_lo"]) + 1j * np.array(g["amp_im_lo"])
+    scale = max(1.0, float(np.max(np.abs(ah))))
+    if prec:
+        gh, gl = d.amplitudes(inp["bits"], dd=True)
+        err = float(np.max(np.abs((gh - ah) + (gl - al))))
+    else:
+        err = float(np.max(np.abs(d.amplitudes(inp["bits"]) - (ah + al))))
+    print(f"max |amplitude error| = {err:.3e} (scale {scale:.3e})", flush=True)
+    assert err <= tol * scale
