@@ -69,7 +69,9 @@ enum mps_option {
   MPS_OPT_KERNEL_TIMING = 3,  /* 1: time every kernel class with HIP events (see below)  */
   MPS_OPT_RANK_FLOOR = 4,     /* relative rank floor (default 2^-44 FP64, 2^-96 dd)       */
   MPS_OPT_BLOCK_WIDTH = 5,    /* Jacobi column block width: 4, 8 (default) or 16          */
-  MPS_OPT_MAX_INNER = 6       /* inner sweeps per block pair, tasks with >= 16 blocks (1)  */
+  MPS_OPT_MAX_INNER = 6,      /* inner sweeps per block pair, tasks with >= 16 blocks (1)  */
+  MPS_OPT_MAX_SLOTS = 7,      /* updates in flight at once (default 32; batches 1024)     */
+  MPS_OPT_WORKSPACE_MB = 8    /* batches: cap of the update workspace, MiB (16384)        */
 };
 
 /* Diagnostics of the most recent split (the last one of a three-qubit gate). */
@@ -80,9 +82,9 @@ struct mps_update_stats {
   double epsdist;  /* relative distance of the eps decision from its boundary, +inf if eps = 0 */
   int k;           /* kept count                                                      */
   int rank;        /* values above the rank floor                                     */
-  int sweeps;      /* FP64 Jacobi sweeps of the last gate's wave                       */
+  int sweeps;      /* most FP64 Jacobi sweeps any update of the last call took          */
   int splits;      /* number of splits in the last gate (0, 1 or 2)                    */
-  int dd_sweeps;   /* dd polish sweeps of the last gate's wave (dd handles)            */
+  int dd_sweeps;   /* most dd polish sweeps any update of the last call took (dd)       */
   int reserved;
 };
 
@@ -172,6 +174,8 @@ int mps_get_site(mps_handle h, int s, double* hi, double* lo, long cap_doubles);
 
 /* --- control --------------------------------------------------------------------- */
 
+/* Options (enum mps_option) apply to the handle's engine: for a member of a
+ * batch, to the whole batch. */
 int mps_set_option(mps_handle h, int key, double value);
 
 /* Wait for all work queued on the handle's stream. */
@@ -191,6 +195,35 @@ const char* mps_last_error(mps_handle h);
 
 /* Library version string. */
 const char* mps_version(void);
+
+/* --- batches of independent circuits ----------------------------------------------
+ * Many states evolved by independent circuits, updated together: the library's
+ * scheduler takes the gates of all circuits at once, so updates of different
+ * circuits share every launch (one Jacobi step launch serves all iterating
+ * updates of all circuits).  Each circuit's gates keep their order where they
+ * share sites, so each state ends exactly as if its circuit ran alone on a handle
+ * of the same precision, chi_max and eps. */
+typedef struct mps_batch* mps_batch_handle;
+
+/* `count` states |0...0>: circuit i has n[i] qubits, chi_max[i], eps[i]; all share
+ * one precision and one HIP stream.  All state memory is one device allocation.
+ * Returns NULL on error (see mps_batch_last_error(NULL)). */
+mps_batch_handle mps_batch_create(int count, const int* n, const int* chi_max, const double* eps, int prec);
+
+/* Apply `ngates` gates: gate g acts on circuit[g] at sites first[g]..first[g]+k[g]-1,
+ * U (and U_lo: NULL, or the lo parts on a dd batch) packed back to back as in
+ * mps_apply_gates.  Every gate is checked before any runs.  Errors as
+ * mps_apply_gates; messages via mps_batch_last_error. */
+int mps_batch_run(mps_batch_handle b, long ngates, const int* circuit, const int* first, const int* k,
+                  const double* U, const double* U_lo);
+
+/* The state of circuit i, for every readout call of this header (and for gates
+ * applied to it alone).  The batch owns it: do not pass it to mps_destroy. */
+mps_handle mps_batch_get(mps_batch_handle b, int circuit);
+
+int mps_batch_set_option(mps_batch_handle b, int key, double value);
+const char* mps_batch_last_error(mps_batch_handle b);
+int mps_batch_destroy(mps_batch_handle b);
 
 #ifdef __cplusplus
 }

@@ -24,7 +24,7 @@ MPS_OK, MPS_EINVAL, MPS_ERANGE, MPS_ENOMEM, MPS_EDEVICE, MPS_ENOCONV, MPS_ENONFI
     0, -1, -2, -3, -4, -5, -6, -7)
 MPS_PREC_FP64, MPS_PREC_DD = 0, 1
 MPS_OPT_MAX_SWEEPS, MPS_OPT_JACOBI_TOL, MPS_OPT_KERNEL_TIMING, MPS_OPT_RANK_FLOOR = 1, 2, 3, 4
-MPS_OPT_BLOCK_WIDTH, MPS_OPT_MAX_INNER = 5, 6
+MPS_OPT_BLOCK_WIDTH, MPS_OPT_MAX_INNER, MPS_OPT_MAX_SLOTS, MPS_OPT_WORKSPACE_MB = 5, 6, 7, 8
 KERNEL_CLASSES = ["theta", "jacobi", "truncate", "split", "gate1", "amplitude", "dd_refine"]
 COUNTER_SWEEPS, COUNTER_SWEEPS_DD = 8, 9
 
@@ -69,11 +69,24 @@ _lib.mps_kernel_time.argtypes = [_h, C.c_int, _dp, C.POINTER(C.c_long), C.c_int]
 _lib.mps_last_error.restype = C.c_char_p
 _lib.mps_last_error.argtypes = [_h]
 _lib.mps_version.restype = C.c_char_p
+_b = C.c_void_p
+_ip = C.POINTER(C.c_int)
+_lib.mps_batch_create.restype = _b
+_lib.mps_batch_create.argtypes = [C.c_int, _ip, _ip, _dp, C.c_int]
+_lib.mps_batch_run.argtypes = [_b, C.c_long, _ip, _ip, _ip, _dp, _dp]
+_lib.mps_batch_get.restype = _h
+_lib.mps_batch_get.argtypes = [_b, C.c_int]
+_lib.mps_batch_set_option.argtypes = [_b, C.c_int, C.c_double]
+_lib.mps_batch_last_error.restype = C.c_char_p
+_lib.mps_batch_last_error.argtypes = [_b]
+_lib.mps_batch_destroy.argtypes = [_b]
 
 EXPORTED = ["mps_create", "mps_create_ex", "mps_destroy", "mps_apply_gate", "mps_apply_gate_dd",
             "mps_apply_gates", "mps_bond_dim", "mps_schmidt", "mps_schmidt_dd", "mps_amplitude",
             "mps_amplitude_dd", "mps_amplitudes", "mps_stats", "mps_load", "mps_get_site",
-            "mps_set_option", "mps_sync", "mps_kernel_time", "mps_last_error", "mps_version"]
+            "mps_set_option", "mps_sync", "mps_kernel_time", "mps_last_error", "mps_version",
+            "mps_batch_create", "mps_batch_run", "mps_batch_get", "mps_batch_set_option",
+            "mps_batch_last_error", "mps_batch_destroy"]
 
 
 def _ptr(a):
@@ -130,18 +143,22 @@ def mps_apply_gate_dd(h, first: int, k: int, U_hi, U_lo) -> int:
     return _check(h, _lib.mps_apply_gate_dd(h, first, k, _ptr(uh), _ptr(ul)))
 
 
+def _pack(gates):
+    first = (C.c_int * len(gates))(*[g.first for g in gates])
+    ks = (C.c_int * len(gates))(*[g.k for g in gates])
+    uh = np.concatenate([_gate_doubles(g.u_hi, g.k) for g in gates])
+    ul = None
+    if any(getattr(g, "u_lo", None) is not None for g in gates):
+        ul = np.concatenate([_gate_doubles(g.u_lo, g.k) if getattr(g, "u_lo", None) is not None
+                             else np.zeros(2 << (2 * g.k)) for g in gates])
+    return first, ks, uh, ul
+
+
 def mps_apply_gates(h, gates, allow_noconv: bool = False) -> int:
     """gates: sequence of objects with .first, .k, .u_hi and optional .u_lo."""
     if not gates:
         return MPS_OK
-    first = (C.c_int * len(gates))(*[g.first for g in gates])
-    ks = (C.c_int * len(gates))(*[g.k for g in gates])
-    uh = np.concatenate([_gate_doubles(g.u_hi, g.k) for g in gates])
-    has_lo = any(getattr(g, "u_lo", None) is not None for g in gates)
-    ul = None
-    if has_lo:
-        ul = np.concatenate([_gate_doubles(g.u_lo, g.k) if g.u_lo is not None else np.zeros(2 << (2 * g.k))
-                             for g in gates])
+    first, ks, uh, ul = _pack(gates)
     rc = _lib.mps_apply_gates(h, len(gates), first, ks, _ptr(uh), _ptr(ul))
     if rc == MPS_ENOCONV and allow_noconv:
         return rc
@@ -251,18 +268,67 @@ def mps_kernel_time(h, cls: int, reset: bool = False):
     return ms.value, cnt.value
 
 
-# ---------------------------------------------------------------- convenience class
+def mps_batch_last_error(b=None) -> str:
+    return (_lib.mps_batch_last_error(b) or b"").decode()
+
+
+def _bcheck(b, rc):
+    if rc != MPS_OK:
+        raise MPSError(rc, mps_batch_last_error(b))
+    return rc
+
+
+def mps_batch_create(n, chi_max, eps, prec: int = MPS_PREC_FP64):
+    count = len(n)
+    ni = (C.c_int * count)(*[int(x) for x in n])
+    ci = (C.c_int * count)(*[int(x) for x in chi_max])
+    ep = np.ascontiguousarray(np.asarray(eps, dtype=np.float64))
+    b = _lib.mps_batch_create(count, ni, ci, _ptr(ep), prec)
+    if not b:
+        raise MPSError(MPS_EINVAL, mps_batch_last_error(None))
+    return b
+
+
+def mps_batch_run(b, circuit, gates, allow_noconv: bool = False) -> int:
+    """circuit[i]: the circuit gate i acts on; gates as for mps_apply_gates."""
+    if not len(gates):
+        return MPS_OK
+    first, ks, uh, ul = _pack(gates)
+    ci = (C.c_int * len(gates))(*[int(c) for c in circuit])
+    rc = _lib.mps_batch_run(b, len(gates), ci, first, ks, _ptr(uh), _ptr(ul))
+    if rc == MPS_ENOCONV and allow_noconv:
+        return rc
+    return _bcheck(b, rc)
+
+
+def mps_batch_get(b, circuit: int):
+    h = _lib.mps_batch_get(b, circuit)
+    if not h:
+        raise MPSError(MPS_EINVAL, f"no circuit {circuit} in the batch")
+    return h
+
+
+def mps_batch_set_option(b, key: int, value: float) -> int:
+    return _bcheck(b, _lib.mps_batch_set_option(b, key, float(value)))
+
+
+def mps_batch_destroy(b) -> int:
+    return _lib.mps_batch_destroy(b)
+
+
+# ---------------------------------------------------------------- convenience classes
 class MPS:
     """An n-qubit state on the device (Section 3.1 of the paper)."""
 
-    def __init__(self, n: int, chi_max: int, eps: float = 0.0, prec: int = MPS_PREC_FP64):
+    def __init__(self, n: int, chi_max: int, eps: float = 0.0, prec: int = MPS_PREC_FP64, _borrowed=None):
         self.n, self.chi_max, self.eps, self.prec = n, chi_max, eps, prec
-        self.h = mps_create_ex(n, chi_max, eps, prec, None)
+        self._owned = _borrowed is None
+        self.h = mps_create_ex(n, chi_max, eps, prec, None) if self._owned else _borrowed
 
     def close(self):
-        if self.h:
+        if self.h and self._owned:
             mps_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         try:
@@ -327,3 +393,44 @@ class MPS:
 
     def kernel_time(self, cls, reset=False):
         return mps_kernel_time(self.h, cls, reset)
+
+
+class Batch:
+    """Independent circuits evolved together (one scheduler, shared launches)."""
+
+    def __init__(self, n, chi_max, eps, prec: int = MPS_PREC_FP64):
+        self.prec = prec
+        self.b = mps_batch_create(n, chi_max, eps, prec)
+        self.states = [MPS(int(n[i]), int(chi_max[i]), float(eps[i]), prec, _borrowed=mps_batch_get(self.b, i))
+                       for i in range(len(n))]
+
+    def __len__(self):
+        return len(self.states)
+
+    def __getitem__(self, i) -> MPS:
+        return self.states[i]
+
+    def run(self, circuit, gates, allow_noconv=False):
+        return mps_batch_run(self.b, circuit, gates, allow_noconv)
+
+    def set_option(self, key, value):
+        return mps_batch_set_option(self.b, key, value)
+
+    def close(self):
+        if self.b:
+            for s in self.states:
+                s.h = None
+            mps_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

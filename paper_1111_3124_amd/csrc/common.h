@@ -59,6 +59,8 @@ struct Task2 {
   double* lamS;         // V_s output slot
   double* lamS_lo;
   int* dim_out;         // where the new m_s goes (device bond-dim table)
+  int chi;              // truncation: chi_max and eps of the state this task updates
+  double eps;
   // gate, row-major 4x4
   double2 U[16];
   double2 U_lo[16];

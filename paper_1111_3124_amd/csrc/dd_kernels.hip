@@ -447,8 +447,10 @@ __device__ __forceinline__ bool dd_before(ddr a, int ia, ddr b, int ib) {
   return dd::lt(b, a) || (a.hi == b.hi && a.lo == b.lo && ia < ib);
 }
 
-__global__ __launch_bounds__(1024) void k_truncate_dd(Task2* tasks, const Ent* ents, int chi, double eps, double floor_rel) {
+__global__ __launch_bounds__(1024) void k_truncate_dd(Task2* tasks, const Ent* ents, double floor_rel) {
   Task2& T = tasks[ents[blockIdx.x].slot];
+  const int chi = T.chi;
+  const double eps = T.eps;
   const int N = T.N, M = T.M;
   int P = 1;
   while (P < N) P <<= 1;
@@ -670,9 +672,8 @@ hipError_t launch_jacobi_step_dd(Task2* d_tasks, const Ent* d_ents, int nent, in
   return hipSuccess;
 }
 
-hipError_t launch_truncate_dd(Task2* d_tasks, const Ent* d_ents, int nent, int chi, double eps, double floor_rel,
-                              hipStream_t st) {
-  hipLaunchKernelGGL(k_truncate_dd, dim3(nent), dim3(1024), 0, st, d_tasks, d_ents, chi, eps, floor_rel);
+hipError_t launch_truncate_dd(Task2* d_tasks, const Ent* d_ents, int nent, double floor_rel, hipStream_t st) {
+  hipLaunchKernelGGL(k_truncate_dd, dim3(nent), dim3(1024), 0, st, d_tasks, d_ents, floor_rel);
   MPS_LAUNCH_CHECK();
   return hipSuccess;
 }

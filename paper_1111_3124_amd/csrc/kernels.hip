@@ -381,8 +381,10 @@ __global__ __launch_bounds__(256) void k_jacobi_step(Task2* tasks, const Ent* en
 // Sort sigma^2 descending (bitonic, ties by column index), suffix sums for the
 // discarded weight, the kept count k = min(chi, k_eps, rank, min(M, N)), the new
 // Schmidt values sigma_j / nu and the column order for the split.
-__global__ __launch_bounds__(1024) void k_truncate(Task2* tasks, const Ent* ents, int chi, double eps, double floor_rel) {
+__global__ __launch_bounds__(1024) void k_truncate(Task2* tasks, const Ent* ents, double floor_rel) {
   Task2& T = tasks[ents[blockIdx.x].slot];
+  const int chi = T.chi;
+  const double eps = T.eps;
   const int N = T.N, M = T.M;
   int P = 1;
   while (P < N) P <<= 1;
@@ -564,6 +566,16 @@ __global__ __launch_bounds__(256) void k_amplitude(const AmpArgs args) {
 }
 
 // ------------------------------------------------------------------ launchers
+// ------------------------------------------------------------------ state set-up
+// The product state |0...0> on zeroed memory: write 1.0 at each listed address
+// (B_s[0][0][0] and the first Schmidt value of every bond slot) and 1 into each
+// bond-dimension entry.
+__global__ __launch_bounds__(256) void k_set_product(double* const* ones, long n_ones, int* dims, long n_dims) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n_ones) *ones[i] = 1.0;
+  if (i < n_dims) dims[i] = 1;
+}
+
 #define MPS_LAUNCH_CHECK() \
   do { hipError_t e_ = hipGetLastError(); if (e_ != hipSuccess) return e_; } while (0)
 
@@ -598,9 +610,8 @@ hipError_t launch_jacobi_step(Task2* d_tasks, const Ent* d_ents, int nent, int m
   return hipSuccess;
 }
 
-hipError_t launch_truncate(Task2* d_tasks, const Ent* d_ents, int nent, int chi, double eps, double floor_rel,
-                           hipStream_t st) {
-  hipLaunchKernelGGL(k_truncate, dim3(nent), dim3(1024), 0, st, d_tasks, d_ents, chi, eps, floor_rel);
+hipError_t launch_truncate(Task2* d_tasks, const Ent* d_ents, int nent, double floor_rel, hipStream_t st) {
+  hipLaunchKernelGGL(k_truncate, dim3(nent), dim3(1024), 0, st, d_tasks, d_ents, floor_rel);
   MPS_LAUNCH_CHECK();
   return hipSuccess;
 }
@@ -622,6 +633,14 @@ hipError_t launch_gate1(Task1* d_tasks, int ntask, long maxel, hipStream_t st) {
   if (gx > 4096) gx = 4096;
   if (gx < 1) gx = 1;
   hipLaunchKernelGGL(k_gate1, dim3(gx, ntask), dim3(256), 0, st, d_tasks);
+  MPS_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_set_product(double* const* ones, long n_ones, int* dims, long n_dims, hipStream_t st) {
+  const long n = n_ones > n_dims ? n_ones : n_dims;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_set_product, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ones, n_ones, dims, n_dims);
   MPS_LAUNCH_CHECK();
   return hipSuccess;
 }

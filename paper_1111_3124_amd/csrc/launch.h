@@ -19,12 +19,14 @@ hipError_t launch_theta2(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, 
 // (start, after Gram, after inner Jacobi, end, rotated?) for phase profiling
 hipError_t launch_jacobi_step(Task2* d_tasks, const Ent* d_ents, int nent, int maxN, int bw, int step, double tol_mult,
                               int maxin, hipStream_t st, long long* phase_clock = nullptr);
-hipError_t launch_truncate(Task2* d_tasks, const Ent* d_ents, int nent, int chi, double eps, double floor_rel,
-                           hipStream_t st);
+// chi_max and eps are read from each task
+hipError_t launch_truncate(Task2* d_tasks, const Ent* d_ents, int nent, double floor_rel, hipStream_t st);
 // right = false: only B_s' (the first split of a three-site gate)
 hipError_t launch_split(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, int maxN, int maxK, hipStream_t st,
                         bool right = true);
 hipError_t launch_gate1(Task1* d_tasks, int ntask, long maxel, hipStream_t st);
 hipError_t launch_amplitude(const AmpArgs& args, int count, hipStream_t st);
+// *ones[i] = 1.0 for i < n_ones; dims[i] = 1 for i < n_dims (one launch for many states)
+hipError_t launch_set_product(double* const* ones, long n_ones, int* dims, long n_dims, hipStream_t st);
 
 }  // namespace mpsk

@@ -1,16 +1,21 @@
-// Host runtime of the MPS gate-update library: handle lifetime, device memory,
-// gate waves, the Jacobi sweep loop and the C ABI of include/mps.h.
+// Host runtime of the MPS gate-update library: engines (stream, workspace arena,
+// staging, timing), states, the update scheduler and the C ABI of include/mps.h.
 //
-// Bond dimensions live in a device table written by the truncation kernel; the
-// host mirrors it after each wave (one small device-to-host copy), so that every
-// launch is sized to the live shapes.
+// An engine owns everything a run of the scheduler needs besides the states: one
+// standalone handle owns one engine; a batch owns one engine shared by all its
+// states, so the updates of every circuit of the batch run in the same launches.
+// Bond dimensions live in device tables written by the truncation kernel; the
+// host mirrors them after each finalisation (one small device-to-host copy), so
+// that every launch is sized to the live shapes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -33,26 +38,57 @@ struct EvPair {
   int n;
 };
 
+// First-fit allocator of offsets in the workspace arena, with coalescing.
+struct Arena {
+  size_t size = 0;
+  std::map<size_t, size_t> fr;  // offset -> length of each free block
+  void reset(size_t s) {
+    size = s;
+    fr.clear();
+    if (s) fr[0] = s;
+  }
+  size_t alloc(size_t len) {
+    for (auto it = fr.begin(); it != fr.end(); ++it)
+      if (it->second >= len) {
+        const size_t off = it->first, rem = it->second - len;
+        fr.erase(it);
+        if (rem) fr[off + len] = rem;
+        return off;
+      }
+    return SIZE_MAX;
+  }
+  void release(size_t off, size_t len) {
+    auto it = fr.emplace(off, len).first;
+    auto nx = std::next(it);
+    if (nx != fr.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      fr.erase(nx);
+    }
+    if (it != fr.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        fr.erase(it);
+      }
+    }
+  }
+};
+
 }  // namespace
 
-struct mps_state {
-  int n = 0, chi = 0, prec = MPS_PREC_FP64;
-  double eps = 0.0;
+struct Engine {
+  int prec = MPS_PREC_FP64;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int device = 0;
-  std::vector<int> capx;  // capx[b+1] = capacity of bond b; capx[0] = capx[n] = 1
-  std::vector<int> dimx;  // host mirror of the bond dims, same indexing
-  int* d_dimx = nullptr;
-  std::vector<double2*> B, Blo;  // per site, capx[s] * 2 * capx[s+1]
-  double* d_lam = nullptr;       // (n+1) slots x chi; slot b+1 = bond b; slots 0, n = [1]
-  double* d_lam_lo = nullptr;
-  // options
+  bool batch = false;  // a batch engine sizes workspace per update, not per slot
+  // options (shared by every state of the engine)
   int max_sweeps = 40;
   int max_sweeps_dd = 16;
   int max_inner = 1;
   int block_width = 8;
   int max_slots = 32;
+  double ws_limit = 16.0 * (1ull << 30);  // batch engines: workspace arena cap, bytes
   double tol_mult = 1.0;
   double rank_floor = 0x1p-44;
   double rank_floor_dd = 0x1p-96;
@@ -61,13 +97,11 @@ struct mps_state {
   // workspace
   char* ws = nullptr;
   size_t ws_size = 0;
+  Arena arena;
   char* h_stage = nullptr;  // pinned host staging (task arrays, readbacks)
   size_t h_stage_size = 0;
   char* d_small = nullptr;  // device task arrays + flags + stats
   size_t d_small_size = 0;
-  // diagnostics
-  mps_update_stats last{};
-  std::string err;
   // timing
   std::vector<EvPair> pending;
   std::vector<hipEvent_t> evpool;
@@ -77,12 +111,40 @@ struct mps_state {
   long long* d_phase = nullptr;               // MPS_DEBUG_PHASES=1: step phase stamps
 };
 
+struct mps_state {
+  int n = 0, chi = 0, prec = MPS_PREC_FP64;
+  double eps = 0.0;
+  Engine* E = nullptr;
+  bool own_engine = false;
+  mps_batch* batch = nullptr;  // non-null: a member of a batch (which owns its memory)
+  char* mem = nullptr;         // device block holding B, B_lo, V, V_lo, dims (standalone)
+  std::vector<int> capx;  // capx[b+1] = capacity of bond b; capx[0] = capx[n] = 1
+  std::vector<int> dimx;  // host mirror of the bond dims, same indexing
+  int* d_dimx = nullptr;
+  std::vector<double2*> B, Blo;  // per site, capx[s] * 2 * capx[s+1]
+  double* d_lam = nullptr;       // (n+1) slots x chi; slot b+1 = bond b; slots 0, n = [1]
+  double* d_lam_lo = nullptr;
+  mps_update_stats last{};
+  std::string err;
+};
+
+struct mps_batch {
+  Engine* E = nullptr;
+  std::vector<mps_state*> units;
+  char* mem = nullptr;  // one device block for every state
+  int* d_dims = nullptr;  // all bond-dimension tables, back to back
+  int dims_total = 0;
+  std::string err;
+};
+
 namespace {
 
-int fail(mps_state* h, int code, const std::string& msg) {
-  if (h) h->err = msg;
+int fail(std::string* err, int code, const std::string& msg) {
+  if (err) *err = msg;
   return code;
 }
+int fail(mps_state* h, int code, const std::string& msg) { return fail(h ? &h->err : nullptr, code, msg); }
+int fail(mps_batch* b, int code, const std::string& msg) { return fail(b ? &b->err : nullptr, code, msg); }
 
 #define HIPCHK(h, call)                                                                        \
   do {                                                                                         \
@@ -103,10 +165,47 @@ int bond_capacity(int n, int chi, int b) {
 
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
-hipEvent_t ev_get(mps_state* h) {
-  if (!h->evpool.empty()) {
-    hipEvent_t e = h->evpool.back();
-    h->evpool.pop_back();
+// ------------------------------------------------------------------ engines
+Engine* engine_new(int prec, void* hip_stream, std::string* err) {
+  Engine* E = new Engine();
+  E->prec = prec;
+  if (const char* dbg = std::getenv("MPS_DEBUG_SWEEPS")) E->debug_sweeps = dbg[0] == '1';
+  hipError_t e = hipGetDevice(&E->device);
+  if (e == hipSuccess) {
+    if (hip_stream) {
+      E->stream = (hipStream_t)hip_stream;
+    } else {
+      e = hipStreamCreateWithFlags(&E->stream, hipStreamNonBlocking);
+      E->own_stream = e == hipSuccess;
+    }
+  }
+  if (e != hipSuccess) {
+    *err = std::string("engine: ") + hipGetErrorString(e);
+    delete E;
+    return nullptr;
+  }
+  if (const char* dbg = std::getenv("MPS_DEBUG_PHASES"))
+    if (dbg[0] == '1' && hipMalloc((void**)&E->d_phase, 8 * sizeof(long long)) != hipSuccess) E->d_phase = nullptr;
+  return E;
+}
+
+void engine_free(Engine* E) {
+  if (!E) return;
+  if (E->stream) (void)hipStreamSynchronize(E->stream);
+  if (E->d_phase) (void)hipFree(E->d_phase);
+  if (E->ws) (void)hipFree(E->ws);
+  if (E->d_small) (void)hipFree(E->d_small);
+  if (E->h_stage) (void)hipHostFree(E->h_stage);
+  for (auto& p : E->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+  for (auto e : E->evpool) (void)hipEventDestroy(e);
+  if (E->own_stream && E->stream) (void)hipStreamDestroy(E->stream);
+  delete E;
+}
+
+hipEvent_t ev_get(Engine* E) {
+  if (!E->evpool.empty()) {
+    hipEvent_t e = E->evpool.back();
+    E->evpool.pop_back();
     return e;
   }
   hipEvent_t e;
@@ -115,69 +214,136 @@ hipEvent_t ev_get(mps_state* h) {
 }
 
 struct Timed {
-  mps_state* h;
+  Engine* E;
   EvPair p{};
   bool on;
   // `launches` kernels are enqueued between the two events
-  Timed(mps_state* hh, int cls, int launches = 1) : h(hh), on(hh->timing) {
+  Timed(Engine* EE, int cls, int launches = 1) : E(EE), on(EE->timing) {
     if (on) {
-      p.a = ev_get(h);
-      p.b = ev_get(h);
+      p.a = ev_get(E);
+      p.b = ev_get(E);
       p.cls = cls;
       p.n = launches;
-      (void)hipEventRecord(p.a, h->stream);
+      (void)hipEventRecord(p.a, E->stream);
     }
   }
   ~Timed() {
     if (on) {
-      (void)hipEventRecord(p.b, h->stream);
-      h->pending.push_back(p);
+      (void)hipEventRecord(p.b, E->stream);
+      E->pending.push_back(p);
     }
   }
 };
 
 // after a synchronisation: fold finished event pairs into the per-class totals
-void harvest_timing(mps_state* h) {
-  for (auto& p : h->pending) {
+void harvest_timing(Engine* E) {
+  for (auto& p : E->pending) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
-      h->tms[p.cls] += ms;
-      h->tcount[p.cls] += p.n;
+      E->tms[p.cls] += ms;
+      E->tcount[p.cls] += p.n;
     }
-    h->evpool.push_back(p.a);
-    h->evpool.push_back(p.b);
+    E->evpool.push_back(p.a);
+    E->evpool.push_back(p.b);
   }
-  h->pending.clear();
+  E->pending.clear();
 }
 
-int ensure_ws(mps_state* h, size_t bytes) {
-  if (bytes <= h->ws_size) return MPS_OK;
-  HIPCHK(h, hipStreamSynchronize(h->stream));
-  if (h->ws) HIPCHK(h, hipFree(h->ws));
-  h->ws = nullptr;
-  h->ws_size = 0;
-  size_t want = std::max(bytes, h->ws_size * 3 / 2);
-  HIPCHK(h, hipMalloc((void**)&h->ws, want));
-  h->ws_size = want;
+// the arena must hold `bytes`; only called while no update holds workspace
+int ensure_ws(Engine* E, size_t bytes, std::string* err) {
+  if (bytes > E->ws_size) {
+    HIPCHK(err, hipStreamSynchronize(E->stream));
+    if (E->ws) HIPCHK(err, hipFree(E->ws));
+    E->ws = nullptr;
+    E->ws_size = 0;
+    HIPCHK(err, hipMalloc((void**)&E->ws, bytes));
+    E->ws_size = bytes;
+  }
+  E->arena.reset(E->ws_size);
   return MPS_OK;
 }
 
-int ensure_small(mps_state* h, size_t bytes) {
-  if (bytes <= h->d_small_size && bytes <= h->h_stage_size) return MPS_OK;
-  HIPCHK(h, hipStreamSynchronize(h->stream));
+int ensure_small(Engine* E, size_t bytes, std::string* err) {
+  if (bytes <= E->d_small_size && bytes <= E->h_stage_size) return MPS_OK;
+  HIPCHK(err, hipStreamSynchronize(E->stream));
   size_t want = std::max<size_t>(bytes, 1 << 16);
-  if (bytes > h->d_small_size) {
-    if (h->d_small) HIPCHK(h, hipFree(h->d_small));
-    h->d_small = nullptr;
-    HIPCHK(h, hipMalloc((void**)&h->d_small, want));
-    h->d_small_size = want;
+  if (bytes > E->d_small_size) {
+    if (E->d_small) HIPCHK(err, hipFree(E->d_small));
+    E->d_small = nullptr;
+    HIPCHK(err, hipMalloc((void**)&E->d_small, want));
+    E->d_small_size = want;
   }
-  if (bytes > h->h_stage_size) {
-    if (h->h_stage) HIPCHK(h, hipHostFree(h->h_stage));
-    h->h_stage = nullptr;
-    HIPCHK(h, hipHostMalloc((void**)&h->h_stage, want, hipHostMallocDefault));
-    h->h_stage_size = want;
+  if (bytes > E->h_stage_size) {
+    if (E->h_stage) HIPCHK(err, hipHostFree(E->h_stage));
+    E->h_stage = nullptr;
+    HIPCHK(err, hipHostMalloc((void**)&E->h_stage, want, hipHostMallocDefault));
+    E->h_stage_size = want;
   }
+  return MPS_OK;
+}
+
+// ------------------------------------------------------------------ state memory
+// One device block per state: site tensors (hi planes, then lo planes), Schmidt
+// value slots (hi, lo) and the bond-dimension table.
+void state_shape(mps_state* h, int n, int chi, double eps, int prec) {
+  h->n = n;
+  h->chi = chi;
+  h->eps = eps;
+  h->prec = prec;
+  h->capx.assign(n + 1, 1);
+  for (int b = 0; b + 1 < n; ++b) h->capx[b + 1] = bond_capacity(n, chi, b);
+  h->dimx.assign(n + 1, 1);
+}
+
+size_t state_bytes(const mps_state* h, bool with_dims) {
+  const bool dd = h->prec == MPS_PREC_DD;
+  size_t b = 0;
+  for (int s = 0; s < h->n; ++s) b += align_up((size_t)h->capx[s] * 2 * h->capx[s + 1] * sizeof(double2)) * (dd ? 2 : 1);
+  b += align_up((size_t)(h->n + 1) * h->chi * sizeof(double)) * (dd ? 2 : 1);
+  if (with_dims) b += align_up(sizeof(int) * (h->n + 1));
+  return b;
+}
+
+// carve the pointers of h from `base`; returns the end
+char* state_carve(mps_state* h, char* base, bool with_dims) {
+  const bool dd = h->prec == MPS_PREC_DD;
+  h->B.assign(h->n, nullptr);
+  h->Blo.assign(dd ? h->n : 0, nullptr);
+  for (int plane = 0; plane < (dd ? 2 : 1); ++plane)
+    for (int s = 0; s < h->n; ++s) {
+      (plane ? h->Blo : h->B)[s] = (double2*)base;
+      base += align_up((size_t)h->capx[s] * 2 * h->capx[s + 1] * sizeof(double2));
+    }
+  const size_t lam_b = align_up((size_t)(h->n + 1) * h->chi * sizeof(double));
+  h->d_lam = (double*)base;
+  base += lam_b;
+  if (dd) {
+    h->d_lam_lo = (double*)base;
+    base += lam_b;
+  }
+  if (with_dims) {
+    h->d_dimx = (int*)base;
+    base += align_up(sizeof(int) * (h->n + 1));
+  }
+  return base;
+}
+
+// |0...0> for every state on zeroed memory: B_s[0][0][0] = 1, first value of each
+// Schmidt slot = 1, all bond dims 1
+int set_product_states(Engine* E, const std::vector<mps_state*>& hs, int* dims, long n_dims, std::string* err) {
+  std::vector<double*> ones;
+  for (mps_state* h : hs) {
+    for (int s = 0; s < h->n; ++s) ones.push_back((double*)h->B[s]);
+    for (int sl = 0; sl <= h->n; ++sl) ones.push_back(h->d_lam + (size_t)sl * h->chi);
+  }
+  double** d_ones = nullptr;
+  HIPCHK(err, hipMalloc((void**)&d_ones, sizeof(double*) * ones.size()));
+  hipError_t e = hipMemcpy(d_ones, ones.data(), sizeof(double*) * ones.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = mpsk::launch_set_product(d_ones, (long)ones.size(), dims, n_dims, E->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(E->stream);
+  (void)hipFree(d_ones);
+  if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("state set-up: ") + hipGetErrorString(e));
+  for (mps_state* h : hs) h->dimx.assign(h->n + 1, 1);
   return MPS_OK;
 }
 
@@ -188,31 +354,34 @@ bool finite_gate(int k, const double* U) {
   return true;
 }
 
-int validate_gate(mps_state* h, int first, int k, const double* U, const double* Ulo) {
-  if (k < 1 || k > 3) return fail(h, MPS_EINVAL, "k must be 1, 2 or 3");
-  if (first < 0 || first + k > h->n) return fail(h, MPS_EINVAL, "gate sites out of range");
-  if (!U) return fail(h, MPS_EINVAL, "null gate matrix");
+int validate_gate(const mps_state* h, int first, int k, const double* U, const double* Ulo, std::string* err) {
+  if (k < 1 || k > 3) return fail(err, MPS_EINVAL, "k must be 1, 2 or 3");
+  if (first < 0 || first + k > h->n) return fail(err, MPS_EINVAL, "gate sites out of range");
+  if (!U) return fail(err, MPS_EINVAL, "null gate matrix");
   if (!finite_gate(k, U) || (Ulo && !finite_gate(k, Ulo)))
-    return fail(h, MPS_ENONFINITE, "gate matrix has a NaN or infinite entry");
+    return fail(err, MPS_ENONFINITE, "gate matrix has a NaN or infinite entry");
   return MPS_OK;
 }
 
 struct GateRef {
+  int unit;  // index of the state in the run's state list
   int first, k;
   const double* U;
   const double* Ulo;
 };
 
 // ------------------------------------------------------------------ update scheduler
-// Continuous batching of gate updates.  Each two-site split occupies a slot (task
-// descriptor + workspace).  One scheduler tick:
+// Continuous batching of gate updates over one or more states.  Each two-site
+// split occupies a slot (task descriptor + workspace from the engine's arena).
+// One scheduler tick:
 //   1. admit queued gates whose sites are free and not claimed by an earlier queued
-//      gate (gates on disjoint sites commute, so queue order is kept where it
-//      matters): a single-site gate runs at once; a two-site gate takes a slot and
-//      gets its prep + theta launch; a three-site gate takes a slot for its first
-//      split (s | s+1 s+2) and reserves a second one for its second split;
+//      gate of the same state (gates on disjoint sites commute, so queue order is
+//      kept where it matters; states are independent): a single-site gate runs at
+//      once; a two-site gate takes a slot and gets its prep + theta launch; a
+//      three-site gate takes a slot for its first split (s | s+1 s+2) and reserves
+//      a second one for its second split;
 //   2. one Jacobi sweep for every slot still iterating (FP64 sweeps, or dd polish
-//      sweeps after the FP64 iteration of a dd handle has converged);
+//      sweeps after the FP64 iteration of a dd state has converged);
 //   3. read the rotation flags; converged slots are truncated and split at once and
 //      their new bond dimensions read back.  A finished first split of a three-site
 //      gate hands Z1_k^H, weighted by its new Schmidt values, to the reserved slot as
@@ -227,18 +396,10 @@ struct Slot {
   int fp64_sweeps = 0, dd_sweeps = 0;
   bool fp64_conv = false, conv = false;
   int M = 0, N = 0;
+  size_t ws_off = 0, ws_len = 0;  // workspace held in the arena
 };
 
-struct SchedBufs {
-  int S = 0;
-  size_t slot_bytes = 0;
-  // offsets in the small device / pinned areas
-  size_t o_tasks = 0, o_flags = 0, o_stats = 0, o_fro = 0, o_dims = 0, o_u8 = 0, o_ents = 0, o_end = 0;
-  static constexpr int kLists = 9;  // new2, new3, jacobi, dd, dd-enter, final, final3, mid, gate1
-};
-
-size_t slot_workspace_bytes(const mps_state* h, int Mcap, int Ncap, int t1cap) {
-  const bool dd = h->prec == MPS_PREC_DD;
+size_t slot_workspace_bytes(bool dd, int Mcap, int Ncap, int t1cap) {
   const size_t MN = (size_t)Mcap * Ncap, NN = (size_t)Ncap * Ncap;
   size_t b = align_up((2 * MN + NN) * sizeof(double2)) * (dd ? 2 : 1);
   if (dd) b += 2 * align_up(NN * sizeof(double2));
@@ -247,9 +408,8 @@ size_t slot_workspace_bytes(const mps_state* h, int Mcap, int Ncap, int t1cap) {
   return b;
 }
 
-// workspace pointers of a task whose theta is M x N, carved from the slot region w
-void carve(mps_state* h, Task2& t, char* w, int* d_flags, double* d_stats, double* d_fro, int slot) {
-  const bool dd = h->prec == MPS_PREC_DD;
+// workspace pointers of a task whose theta is M x N, carved from the region w
+void carve(bool dd, Task2& t, char* w, int* d_flags, double* d_stats, double* d_fro, int slot) {
   const size_t MN = (size_t)t.M * t.N, NN = (size_t)t.N * t.N;
   t.thu = (double2*)w;
   t.thw = t.thu + MN;
@@ -284,8 +444,8 @@ void carve(mps_state* h, Task2& t, char* w, int* d_flags, double* d_stats, doubl
   t.fro2 = d_fro + slot;
 }
 
-// the two-site split between sites s and s+1 with bond dims a | (b) | c
-void setup_split(mps_state* h, Task2& t, int s, int a, int b, int c) {
+// the two-site split of state h between sites s and s+1 with bond dims a | (b) | c
+void setup_split(const mps_state* h, Task2& t, int s, int a, int b, int c) {
   const bool dd = h->prec == MPS_PREC_DD;
   t = Task2{};
   t.Bl = h->B[s];
@@ -304,192 +464,285 @@ void setup_split(mps_state* h, Task2& t, int s, int a, int b, int c) {
   t.lamS = h->d_lam + (size_t)(s + 1) * h->chi;
   t.lamS_lo = dd ? h->d_lam_lo + (size_t)(s + 1) * h->chi : nullptr;
   t.dim_out = h->d_dimx + s + 1;
+  t.chi = h->chi;
+  t.eps = h->eps;
 }
 
-int run_gates(mps_state* h, const std::vector<GateRef>& gates) {
+// workspace of a gate's first task (upper bound over the live dims: capacities)
+size_t gate_need_cap(bool dd, const mps_state* h, int first, int k) {
+  if (k == 2) return slot_workspace_bytes(dd, 2 * h->capx[first], 2 * h->capx[first + 2], 0);
+  if (k == 3)
+    return slot_workspace_bytes(dd, 2 * h->capx[first], 4 * h->capx[first + 3],
+                                4 * h->capx[first] * h->capx[first + 2]) +
+           slot_workspace_bytes(dd, 2 * h->capx[first + 1], 2 * h->capx[first + 3], 0);
+  return 0;
+}
+
+// Runs `gates` on the states `U` of engine E.  d_dims / dims_total: one device range
+// covering every state's bond-dimension table; dims_off[u] = offset of state u's.
+int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, int dims_total,
+              const std::vector<int>& dims_off, const std::vector<GateRef>& gates, std::string* err) {
   if (gates.empty()) return MPS_OK;
-  const bool dd = h->prec == MPS_PREC_DD;
+  const bool dd = E->prec == MPS_PREC_DD;
+  const int nu = (int)U.size();
+  std::vector<int> site_base(nu + 1, 0);
+  for (int u = 0; u < nu; ++u) site_base[u + 1] = site_base[u] + U[u]->n;
+  const int nsites = site_base[nu];
+  std::vector<std::vector<int>> queue(nu);
+  int n2 = 0, n3 = 0, par = 0;
+  size_t max_need = 0;
   int capmax = 1;
-  for (int b = 0; b <= h->n; ++b) capmax = std::max(capmax, h->capx[b]);
-  int n2 = 0, n3 = 0;
-  for (const auto& g : gates) {
+  for (int u = 0; u < nu; ++u) {
+    par += std::max(2, U[u]->n / 2 + 1);
+    for (int b = 0; b <= U[u]->n; ++b) capmax = std::max(capmax, U[u]->capx[b]);
+  }
+  for (size_t gi = 0; gi < gates.size(); ++gi) {
+    const GateRef& g = gates[gi];
+    queue[g.unit].push_back((int)gi);
     n2 += g.k == 2;
     n3 += g.k == 3;
+    max_need = std::max(max_need, gate_need_cap(dd, U[g.unit], g.first, g.k));
   }
-  const int Mcap = 2 * capmax, Ncap = (n3 ? 4 : 2) * capmax;
-  const int t1cap = n3 ? 4 * capmax * capmax : 0;
-  const int S = std::max(n3 ? 2 : 1,
-                         std::min(std::min(h->max_slots, std::max(2, h->n / 2 + 1)), std::max(1, n2 + 2 * n3)));
-  SchedBufs L;
-  L.S = S;
-  L.slot_bytes = slot_workspace_bytes(h, Mcap, Ncap, t1cap);
-  int rc = ensure_ws(h, L.slot_bytes * S);
+  const int S = std::max(n3 ? 2 : 1, std::min(std::min(E->max_slots, par), std::max(1, n2 + 2 * n3)));
+  // standalone engines: every slot takes the same, largest workspace (no
+  // fragmentation); batch engines: each update takes what its shape needs
+  size_t uniform = 0, arena_bytes;
+  if (!E->batch) {
+    const int Mcap = 2 * capmax, Ncap = (n3 ? 4 : 2) * capmax;
+    uniform = slot_workspace_bytes(dd, Mcap, Ncap, n3 ? 4 * capmax * capmax : 0);
+    arena_bytes = uniform * S;
+  } else {
+    arena_bytes = std::max(max_need, (size_t)std::min(E->ws_limit, (double)max_need * S));
+  }
+  int rc = ensure_ws(E, align_up(arena_bytes), err);
   if (rc) return rc;
-  L.o_tasks = 0;
-  L.o_flags = align_up(sizeof(Task2) * S);
-  L.o_stats = L.o_flags + align_up(sizeof(int) * 3 * S);
-  L.o_fro = L.o_stats + align_up(sizeof(double) * 8 * S);
-  L.o_dims = L.o_fro + align_up(sizeof(double) * S);
-  L.o_u8 = L.o_dims + align_up(sizeof(int) * (h->n + 1));
-  L.o_ents = L.o_u8 + align_up(sizeof(double2) * 128 * S);
-  const size_t list_bytes = align_up(std::max(sizeof(mpsk::Ent) * S, sizeof(Task1) * (size_t)h->n));
-  L.o_end = L.o_ents + SchedBufs::kLists * list_bytes;
-  rc = ensure_small(h, L.o_end);
+  // small device / pinned areas
+  const size_t o_tasks = 0;
+  const size_t o_flags = align_up(sizeof(Task2) * S);
+  const size_t o_stats = o_flags + align_up(sizeof(int) * 3 * S);
+  const size_t o_fro = o_stats + align_up(sizeof(double) * 8 * S);
+  const size_t o_dims = o_fro + align_up(sizeof(double) * S);
+  const size_t o_u8 = o_dims + align_up(sizeof(int) * dims_total);
+  const size_t o_g1 = o_u8 + align_up(sizeof(double2) * 128 * S);
+  const size_t o_ents = o_g1 + align_up(sizeof(Task1) * nsites);
+  constexpr int kLists = 8;  // new2, new3, jacobi, dd, dd-enter, final, final3, mid
+  const size_t list_bytes = align_up(sizeof(mpsk::Ent) * S);
+  rc = ensure_small(E, o_ents + kLists * list_bytes, err);
   if (rc) return rc;
-  Task2* ht = (Task2*)(h->h_stage + L.o_tasks);
-  Task2* dt = (Task2*)(h->d_small + L.o_tasks);
-  int* d_flags = (int*)(h->d_small + L.o_flags);
-  int* hflags = (int*)(h->h_stage + L.o_flags);
-  double* d_stats = (double*)(h->d_small + L.o_stats);
-  double* hstats = (double*)(h->h_stage + L.o_stats);
-  double* d_fro = (double*)(h->d_small + L.o_fro);
-  double2* hu8 = (double2*)(h->h_stage + L.o_u8);
-  double2* du8 = (double2*)(h->d_small + L.o_u8);
-  enum { LN2 = 0, LN3, LJ, LD, LENTER, LFIN, LFIN3, LMID, LG1 };
-  auto hlist = [&](int i) { return h->h_stage + L.o_ents + i * list_bytes; };
-  auto dlist = [&](int i) { return h->d_small + L.o_ents + i * list_bytes; };
+  Task2* ht = (Task2*)(E->h_stage + o_tasks);
+  Task2* dt = (Task2*)(E->d_small + o_tasks);
+  int* d_flags = (int*)(E->d_small + o_flags);
+  int* hflags = (int*)(E->h_stage + o_flags);
+  double* d_stats = (double*)(E->d_small + o_stats);
+  double* hstats = (double*)(E->h_stage + o_stats);
+  double* d_fro = (double*)(E->d_small + o_fro);
+  int* hdims = (int*)(E->h_stage + o_dims);
+  double2* hu8 = (double2*)(E->h_stage + o_u8);
+  double2* du8 = (double2*)(E->d_small + o_u8);
+  enum { LN2 = 0, LN3, LJ, LD, LENTER, LFIN, LFIN3, LMID };
+  auto hlist = [&](int i) { return E->h_stage + o_ents + i * list_bytes; };
+  auto dlist = [&](int i) { return E->d_small + o_ents + i * list_bytes; };
 
   std::vector<Slot> slot(S);
-  std::vector<char> done(gates.size(), 0), busy(h->n, 0);
+  std::vector<char> done(gates.size(), 0), busy(nsites, 0), claimed(nsites, 0);
   std::vector<double> gstats(8 * gates.size(), 0.0);
   std::vector<int> gsweeps(gates.size(), 0), gdd(gates.size(), 0);
-  size_t first_pending = 0;
+  std::vector<size_t> head(nu, 0);  // per state: first queue entry not yet admitted
+  size_t remaining = gates.size();
   int status = MPS_OK;
-  const int bw = h->block_width;
-  const size_t window = (size_t)4 * S + 16;
+  const int bw = E->block_width;
+  int rot0 = 0;  // first state scanned at admission (rotates for fairness)
   hipError_t e;
+  hipStream_t st = E->stream;
+  int dirty_lo = S, dirty_hi = -1;  // task descriptors changed since the last upload
+  auto mark = [&](int si) { dirty_lo = std::min(dirty_lo, si); dirty_hi = std::max(dirty_hi, si); };
+  auto upload_tasks = [&]() -> hipError_t {
+    if (dirty_hi < dirty_lo) return hipSuccess;
+    hipError_t ee = hipMemcpyAsync(dt + dirty_lo, ht + dirty_lo, sizeof(Task2) * (dirty_hi - dirty_lo + 1),
+                                   hipMemcpyHostToDevice, st);
+    dirty_lo = S;
+    dirty_hi = -1;
+    return ee;
+  };
 
   auto upload_list = [&](int li, const std::vector<mpsk::Ent>& ents) -> mpsk::Ent* {
     mpsk::Ent* hl = (mpsk::Ent*)hlist(li);
     for (size_t i = 0; i < ents.size(); ++i) hl[i] = ents[i];
-    hipError_t ee = hipMemcpyAsync(dlist(li), hl, sizeof(mpsk::Ent) * ents.size(), hipMemcpyHostToDevice, h->stream);
+    hipError_t ee = hipMemcpyAsync(dlist(li), hl, sizeof(mpsk::Ent) * ents.size(), hipMemcpyHostToDevice, st);
     return ee == hipSuccess ? (mpsk::Ent*)dlist(li) : nullptr;
   };
   auto ents_of = [&](const std::vector<int>& sl) {
     std::vector<mpsk::Ent> v;
+    v.reserve(sl.size());
     for (int si : sl) v.push_back(mpsk::Ent{si, slot[si].sweep});
     return v;
   };
-  auto free_slot = [&]() {
-    for (int si = 0; si < S; ++si)
-      if (slot[si].state == 0) return si;
-    return -1;
+  std::vector<int> free_list;  // free slot indices, lowest last
+  for (int si = S - 1; si >= 0; --si) free_list.push_back(si);
+  auto take_slot = [&]() {
+    const int si = free_list.back();
+    free_list.pop_back();
+    return si;
   };
+  auto release_slot = [&](int si) {
+    if (slot[si].ws_len) E->arena.release(slot[si].ws_off, slot[si].ws_len);
+    slot[si] = Slot{};
+    free_list.push_back(si);
+  };
+  auto ws_alloc = [&](size_t need, size_t& off) {
+    const size_t len = align_up(uniform ? uniform : need);
+    off = E->arena.alloc(len);
+    return off == SIZE_MAX ? (size_t)0 : len;
+  };
+  std::vector<int> active;  // slots not free
 
   bool unsynced = false;  // async copies from the pinned staging may still be pending
   while (true) {
     // the staging buffers are rewritten below: wait for copies a previous tick left
     if (unsynced) {
-      HIPCHK(h, hipStreamSynchronize(h->stream));
+      HIPCHK(err, hipStreamSynchronize(st));
       unsynced = false;
     }
     // ---- 1. admission
     std::vector<int> new2, new3;
-    std::vector<GateRef> g1;
-    std::vector<char> claimed(h->n, 0);
-    int free_slots = 0;
-    for (auto& sl : slot) free_slots += sl.state == 0;
-    while (first_pending < gates.size() && done[first_pending]) ++first_pending;
-    for (size_t gi = first_pending; gi < gates.size() && gi < first_pending + window; ++gi) {
-      if (done[gi]) continue;
-      const GateRef& g = gates[gi];
-      bool free_ = true;
-      for (int q = g.first; q < g.first + g.k; ++q) free_ &= !busy[q] && !claimed[q];
-      if (free_ && g.k == 1) {
-        g1.push_back(g);
-        done[gi] = 1;
-        claimed[g.first] = 1;  // later gates on this site wait for the next pass
-        continue;
-      }
-      if (free_ && ((g.k == 2 && free_slots >= 1) || (g.k == 3 && free_slots >= 2))) {
-        const int si = free_slot();
-        Slot& sl = slot[si];
-        sl = Slot{};
-        sl.state = 1;
-        sl.gate = (int)gi;
-        const int s0 = g.first;
-        Task2& t = ht[si];
-        if (g.k == 2) {
-          setup_split(h, t, s0, h->dimx[s0], h->dimx[s0 + 1], h->dimx[s0 + 2]);
-          for (int q = 0; q < 16; ++q) {
+    std::vector<Task1> g1;
+    long g1_maxel = 0;
+    std::fill(claimed.begin(), claimed.end(), 0);
+    for (int uu = 0; uu < nu && remaining; ++uu) {
+      const int u = (rot0 + uu) % nu;
+      const mps_state* h = U[u];
+      const int sb0 = site_base[u];
+      std::vector<int>& qu = queue[u];
+      while (head[u] < qu.size() && done[qu[head[u]]]) ++head[u];
+      int blocked = 0;  // sites of this state that no later gate may use this tick
+      for (int q = 0; q < h->n; ++q) blocked += busy[sb0 + q];
+      const size_t window = (size_t)4 * h->n + 16;
+      for (size_t qi = head[u]; qi < qu.size() && qi < head[u] + window && blocked < h->n; ++qi) {
+        const int gi = qu[qi];
+        if (done[gi]) continue;
+        const GateRef& g = gates[gi];
+        bool free_ = true;
+        for (int q = g.first; q < g.first + g.k; ++q) free_ &= !busy[sb0 + q] && !claimed[sb0 + q];
+        if (free_ && g.k == 1) {
+          Task1 t{};
+          t.B = h->B[g.first];
+          t.B_lo = dd ? h->Blo[g.first] : nullptr;
+          t.ld = h->capx[g.first + 1];
+          t.a = h->dimx[g.first];
+          t.b = h->dimx[g.first + 1];
+          for (int q = 0; q < 4; ++q) {
             t.U[q] = make_double2(g.U[2 * q], g.U[2 * q + 1]);
             t.U_lo[q] = (dd && g.Ulo) ? make_double2(g.Ulo[2 * q], g.Ulo[2 * q + 1]) : make_double2(0, 0);
           }
-          new2.push_back(si);
-        } else {
-          setup_split(h, t, s0, h->dimx[s0], h->dimx[s0 + 1], h->dimx[s0 + 2]);
-          t.B3 = h->B[s0 + 2];
-          t.B3_lo = dd ? h->Blo[s0 + 2] : nullptr;
-          t.ld3 = h->capx[s0 + 3];
-          t.d = h->dimx[s0 + 3];
-          t.N = 4 * t.d;
-          double2* u8h = hu8 + 128 * si;
-          for (int q = 0; q < 64; ++q) {
-            u8h[q] = make_double2(g.U[2 * q], g.U[2 * q + 1]);
-            u8h[64 + q] = (dd && g.Ulo) ? make_double2(g.Ulo[2 * q], g.Ulo[2 * q + 1]) : make_double2(0, 0);
+          g1.push_back(t);
+          g1_maxel = std::max(g1_maxel, (long)t.a * t.b);
+          done[gi] = 1;
+          --remaining;
+          claimed[sb0 + g.first] = 1;  // later gates on this site wait for the next tick
+          ++blocked;
+          continue;
+        }
+        const int s0 = g.first;
+        bool admitted = false;
+        if (free_ && (int)free_list.size() >= (g.k == 3 ? 2 : 1)) {
+          size_t off1 = 0, off2 = 0, len1 = 0, len2 = 0;
+          if (g.k == 2) {
+            len1 = ws_alloc(slot_workspace_bytes(dd, 2 * h->dimx[s0], 2 * h->dimx[s0 + 2], 0), off1);
+          } else {
+            const int a = h->dimx[s0], c = h->dimx[s0 + 2], d = h->dimx[s0 + 3];
+            len1 = ws_alloc(slot_workspace_bytes(dd, 2 * a, 4 * d, 4 * a * c), off1);
+            if (len1) {
+              len2 = ws_alloc(slot_workspace_bytes(dd, 2 * h->capx[s0 + 1], 2 * d, 0), off2);
+              if (!len2) {
+                E->arena.release(off1, len1);
+                len1 = 0;
+              }
+            }
           }
-          t.U8 = du8 + 128 * si;
-          t.U8_lo = du8 + 128 * si + 64;
-          sl.kind = 1;
-          const int sb = [&] {
-            for (int j = 0; j < S; ++j)
-              if (j != si && slot[j].state == 0) return j;
-            return -1;
-          }();
-          slot[sb] = Slot{};
-          slot[sb].state = 5;
-          slot[sb].kind = 2;
-          slot[sb].gate = (int)gi;
-          sl.partner = sb;
-          --free_slots;
-          new3.push_back(si);
+          if (len1) {
+            admitted = true;
+            const int si = take_slot();
+            Slot& sl = slot[si];
+            sl = Slot{};
+            sl.state = 1;
+            sl.gate = gi;
+            sl.ws_off = off1;
+            sl.ws_len = len1;
+            Task2& t = ht[si];
+            setup_split(h, t, s0, h->dimx[s0], h->dimx[s0 + 1], h->dimx[s0 + 2]);
+            if (g.k == 2) {
+              for (int q = 0; q < 16; ++q) {
+                t.U[q] = make_double2(g.U[2 * q], g.U[2 * q + 1]);
+                t.U_lo[q] = (dd && g.Ulo) ? make_double2(g.Ulo[2 * q], g.Ulo[2 * q + 1]) : make_double2(0, 0);
+              }
+              new2.push_back(si);
+            } else {
+              t.B3 = h->B[s0 + 2];
+              t.B3_lo = dd ? h->Blo[s0 + 2] : nullptr;
+              t.ld3 = h->capx[s0 + 3];
+              t.d = h->dimx[s0 + 3];
+              t.N = 4 * t.d;
+              double2* u8h = hu8 + 128 * si;
+              for (int q = 0; q < 64; ++q) {
+                u8h[q] = make_double2(g.U[2 * q], g.U[2 * q + 1]);
+                u8h[64 + q] = (dd && g.Ulo) ? make_double2(g.Ulo[2 * q], g.Ulo[2 * q + 1]) : make_double2(0, 0);
+              }
+              t.U8 = du8 + 128 * si;
+              t.U8_lo = du8 + 128 * si + 64;
+              sl.kind = 1;
+              const int sb = take_slot();
+              slot[sb] = Slot{};
+              slot[sb].state = 5;
+              slot[sb].kind = 2;
+              slot[sb].gate = gi;
+              slot[sb].ws_off = off2;
+              slot[sb].ws_len = len2;
+              sl.partner = sb;
+              active.push_back(sb);
+              new3.push_back(si);
+            }
+            carve(dd, t, E->ws + off1, d_flags, d_stats, d_fro, si);
+            mark(si);
+            sl.M = t.M;
+            sl.N = t.N;
+            active.push_back(si);
+            for (int q = g.first; q < g.first + g.k; ++q) busy[sb0 + q] = 1;
+            done[gi] = 1;
+            --remaining;
+          }
         }
-        carve(h, t, h->ws + L.slot_bytes * si, d_flags, d_stats, d_fro, si);
-        sl.M = t.M;
-        sl.N = t.N;
-        for (int q = g.first; q < g.first + g.k; ++q) busy[q] = 1;
-        done[gi] = 1;
-        --free_slots;
-        continue;
+        if (!admitted)
+          for (int q = g.first; q < g.first + g.k; ++q) {
+            blocked += !claimed[sb0 + q] && !busy[sb0 + q];
+            claimed[sb0 + q] = 1;
+          }
+        else
+          blocked += g.k;
       }
-      for (int q = g.first; q < g.first + g.k; ++q) claimed[q] = 1;
     }
+    rot0 = nu ? (rot0 + 1) % nu : 0;
     if (!g1.empty()) {
-      Task1* h1 = (Task1*)hlist(LG1);
-      long maxel = 0;
-      for (size_t i = 0; i < g1.size(); ++i) {
-        const int s0 = g1[i].first;
-        Task1 t{};
-        t.B = h->B[s0];
-        t.B_lo = dd ? h->Blo[s0] : nullptr;
-        t.ld = h->capx[s0 + 1];
-        t.a = h->dimx[s0];
-        t.b = h->dimx[s0 + 1];
-        for (int q = 0; q < 4; ++q) {
-          t.U[q] = make_double2(g1[i].U[2 * q], g1[i].U[2 * q + 1]);
-          t.U_lo[q] = (dd && g1[i].Ulo) ? make_double2(g1[i].Ulo[2 * q], g1[i].Ulo[2 * q + 1]) : make_double2(0, 0);
-        }
-        h1[i] = t;
-        maxel = std::max(maxel, (long)t.a * t.b);
-      }
-      HIPCHK(h, hipMemcpyAsync(dlist(LG1), h1, sizeof(Task1) * g1.size(), hipMemcpyHostToDevice, h->stream));
+      Task1* h1 = (Task1*)(E->h_stage + o_g1);
+      std::memcpy(h1, g1.data(), sizeof(Task1) * g1.size());
+      HIPCHK(err, hipMemcpyAsync(E->d_small + o_g1, h1, sizeof(Task1) * g1.size(), hipMemcpyHostToDevice, st));
       unsynced = true;
-      Timed tm(h, 4);
-      e = dd ? mpsk::launch_gate1_dd((Task1*)dlist(LG1), (int)g1.size(), maxel, h->stream)
-             : mpsk::launch_gate1((Task1*)dlist(LG1), (int)g1.size(), maxel, h->stream);
-      if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("gate1: ") + hipGetErrorString(e));
+      Timed tm(E, 4);
+      e = dd ? mpsk::launch_gate1_dd((Task1*)(E->d_small + o_g1), (int)g1.size(), g1_maxel, st)
+             : mpsk::launch_gate1((Task1*)(E->d_small + o_g1), (int)g1.size(), g1_maxel, st);
+      if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("gate1: ") + hipGetErrorString(e));
     }
     if (!new2.empty() || !new3.empty()) {
-      HIPCHK(h, hipMemcpyAsync(dt, ht, sizeof(Task2) * S, hipMemcpyHostToDevice, h->stream));
+      HIPCHK(err, upload_tasks());
       if (!new3.empty())
-        HIPCHK(h, hipMemcpyAsync(du8, hu8, sizeof(double2) * 128 * S, hipMemcpyHostToDevice, h->stream));
+        for (int si : new3)
+          HIPCHK(err, hipMemcpyAsync(du8 + 128 * si, hu8 + 128 * si, sizeof(double2) * 128, hipMemcpyHostToDevice, st));
       unsynced = true;
-      Timed tm(h, 0);
+      Timed tm(E, 0);
       for (int which = 0; which < 2; ++which) {
         const std::vector<int>& nl = which ? new3 : new2;
         if (nl.empty()) continue;
         mpsk::Ent* el = upload_list(which ? LN3 : LN2, ents_of(nl));
-        if (!el) return fail(h, MPS_EDEVICE, "list upload failed");
+        if (!el) return fail(err, MPS_EDEVICE, "list upload failed");
         int mM = 0, mN = 0, mA = 0, mC = 0, mD = 0;
         for (int si : nl) {
           mM = std::max(mM, slot[si].M);
@@ -498,69 +751,66 @@ int run_gates(mps_state* h, const std::vector<GateRef>& gates) {
           mC = std::max(mC, ht[si].c);
           mD = std::max(mD, ht[si].d);
         }
-        e = mpsk::launch_prep2(dt, el, (int)nl.size(), mN, h->stream);
+        e = mpsk::launch_prep2(dt, el, (int)nl.size(), mN, st);
         if (e == hipSuccess) {
           if (which)
-            e = mpsk::launch_theta3(dt, el, (int)nl.size(), mA, mC, mD, dd, h->stream);
+            e = mpsk::launch_theta3(dt, el, (int)nl.size(), mA, mC, mD, dd, st);
           else
-            e = dd ? mpsk::launch_theta2_dd(dt, el, (int)nl.size(), mM, mN, h->stream)
-                   : mpsk::launch_theta2(dt, el, (int)nl.size(), mM, mN, h->stream);
+            e = dd ? mpsk::launch_theta2_dd(dt, el, (int)nl.size(), mM, mN, st)
+                   : mpsk::launch_theta2(dt, el, (int)nl.size(), mM, mN, st);
         }
-        if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("theta: ") + hipGetErrorString(e));
+        if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("theta: ") + hipGetErrorString(e));
       }
     }
     // ---- 2. one sweep for every iterating slot
     std::vector<int> jl, dl;
-    for (int si = 0; si < S; ++si) {
+    for (int si : active) {
       if (slot[si].state == 1) jl.push_back(si);
       if (slot[si].state == 2) dl.push_back(si);
     }
     if (jl.empty() && dl.empty()) {
-      bool any_active = false;
-      for (auto& sl : slot) any_active |= sl.state != 0;
-      if (!any_active) {
-        while (first_pending < gates.size() && done[first_pending]) ++first_pending;
-        if (first_pending >= gates.size()) break;
-        continue;  // only single-site gates were pending; admit the rest
+      if (active.empty()) {
+        if (!remaining) break;
+        continue;  // only single-site gates were admitted; admit the rest
       }
     }
     if (!jl.empty()) {
       mpsk::Ent* el = upload_list(LJ, ents_of(jl));
-      if (!el) return fail(h, MPS_EDEVICE, "list upload failed");
+      if (!el) return fail(err, MPS_EDEVICE, "list upload failed");
       int mN = 0;
       for (int si : jl) mN = std::max(mN, slot[si].N);
       const int nb = (mN + bw - 1) / bw;
       const int nsteps = nb + (nb & 1) - 1;
-      Timed tm(h, 1, nsteps);
-      h->slot_sweeps += (long)jl.size();
+      Timed tm(E, 1, nsteps);
+      E->slot_sweeps += (long)jl.size();
       for (int stp = 0; stp < nsteps; ++stp) {
-        long long* pc = (h->d_phase && stp == nsteps / 2) ? h->d_phase : nullptr;
-        e = mpsk::launch_jacobi_step(dt, el, (int)jl.size(), mN, bw, stp, h->tol_mult, h->max_inner, h->stream, pc);
-        if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("jacobi: ") + hipGetErrorString(e));
+        long long* pc = (E->d_phase && stp == nsteps / 2) ? E->d_phase : nullptr;
+        e = mpsk::launch_jacobi_step(dt, el, (int)jl.size(), mN, bw, stp, E->tol_mult, E->max_inner, st, pc);
+        if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("jacobi: ") + hipGetErrorString(e));
       }
     }
     if (!dl.empty()) {
       mpsk::Ent* el = upload_list(LD, ents_of(dl));
-      if (!el) return fail(h, MPS_EDEVICE, "list upload failed");
+      if (!el) return fail(err, MPS_EDEVICE, "list upload failed");
       int mN = 0;
       for (int si : dl) mN = std::max(mN, slot[si].N);
       const int nb = (mN + 7) / 8;
       const int nsteps = nb + (nb & 1) - 1;
-      Timed tm(h, 6, nsteps);
-      h->slot_sweeps_dd += (long)dl.size();
+      Timed tm(E, 6, nsteps);
+      E->slot_sweeps_dd += (long)dl.size();
       for (int stp = 0; stp < nsteps; ++stp) {
-        e = mpsk::launch_jacobi_step_dd(dt, el, (int)dl.size(), mN, stp, h->tol_mult, h->max_inner, h->stream);
-        if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("dd jacobi: ") + hipGetErrorString(e));
+        e = mpsk::launch_jacobi_step_dd(dt, el, (int)dl.size(), mN, stp, E->tol_mult, E->max_inner, st);
+        if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("dd jacobi: ") + hipGetErrorString(e));
       }
     }
     // ---- 3. convergence
     if (!jl.empty() || !dl.empty()) {
-      HIPCHK(h, hipMemcpyAsync(hflags, d_flags, sizeof(int) * 3 * S, hipMemcpyDeviceToHost, h->stream));
-      HIPCHK(h, hipStreamSynchronize(h->stream));
+      HIPCHK(err, hipMemcpyAsync(hflags, d_flags, sizeof(int) * 3 * S, hipMemcpyDeviceToHost, st));
+      HIPCHK(err, hipStreamSynchronize(st));
       unsynced = false;
-      if (h->d_phase && !jl.empty()) {
+      if (E->d_phase && !jl.empty()) {
         long long pc[5];
-        HIPCHK(h, hipMemcpy(pc, h->d_phase, sizeof(pc), hipMemcpyDeviceToHost));
+        HIPCHK(err, hipMemcpy(pc, E->d_phase, sizeof(pc), hipMemcpyDeviceToHost));
         // wall_clock64 runs at 100 MHz on gfx950
         std::fprintf(stderr, "[mps] step phases (us, %zu updates, N %d): gram %.1f inner %.1f update %.1f rot %lld\n",
                      jl.size(), slot[jl[0]].N, (pc[1] - pc[0]) * 0.01, (pc[2] - pc[1]) * 0.01, (pc[3] - pc[2]) * 0.01,
@@ -572,7 +822,7 @@ int run_gates(mps_state* h, const std::vector<GateRef>& gates) {
       Slot& sl = slot[si];
       const bool rot = hflags[3 * si + sl.sweep % 3] != 0;
       ++sl.sweep;
-      if (!rot || sl.sweep >= h->max_sweeps) {
+      if (!rot || sl.sweep >= E->max_sweeps) {
         sl.fp64_sweeps = sl.sweep;
         sl.fp64_conv = !rot;
         if (dd) {
@@ -589,7 +839,7 @@ int run_gates(mps_state* h, const std::vector<GateRef>& gates) {
       Slot& sl = slot[si];
       const bool rot = hflags[3 * si + sl.sweep % 3] != 0;
       ++sl.sweep;
-      if (!rot || sl.sweep >= h->max_sweeps_dd) {
+      if (!rot || sl.sweep >= E->max_sweeps_dd) {
         sl.dd_sweeps = sl.sweep;
         sl.conv = !rot;
         sl.state = 3;
@@ -598,52 +848,52 @@ int run_gates(mps_state* h, const std::vector<GateRef>& gates) {
     if (!enter.empty()) {
       unsynced = true;
       mpsk::Ent* el = upload_list(LENTER, ents_of(enter));
-      if (!el) return fail(h, MPS_EDEVICE, "list upload failed");
+      if (!el) return fail(err, MPS_EDEVICE, "list upload failed");
       int mM = 0, mN = 0;
       for (int si : enter) { mM = std::max(mM, slot[si].M); mN = std::max(mN, slot[si].N); }
-      Timed tm(h, 6);
-      e = mpsk::launch_dd_enter(dt, el, (int)enter.size(), mM, mN, h->stream);
-      if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("dd enter: ") + hipGetErrorString(e));
+      Timed tm(E, 6);
+      e = mpsk::launch_dd_enter(dt, el, (int)enter.size(), mM, mN, st);
+      if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("dd enter: ") + hipGetErrorString(e));
     }
     // ---- 4. finalise converged slots
     std::vector<int> fl, fl2, fl3;
-    for (int si = 0; si < S; ++si)
+    for (int si : active)
       if (slot[si].state == 3) {
         fl.push_back(si);
         (slot[si].kind == 1 ? fl3 : fl2).push_back(si);
       }
     if (!fl.empty()) {
       mpsk::Ent* el = upload_list(LFIN, ents_of(fl));
-      if (!el) return fail(h, MPS_EDEVICE, "list upload failed");
-      int mM = 0, mN = 0;
-      for (int si : fl) { mM = std::max(mM, slot[si].M); mN = std::max(mN, slot[si].N); }
+      if (!el) return fail(err, MPS_EDEVICE, "list upload failed");
       {
-        Timed tm(h, 2);
-        e = dd ? mpsk::launch_truncate_dd(dt, el, (int)fl.size(), h->chi, h->eps, h->rank_floor_dd, h->stream)
-               : mpsk::launch_truncate(dt, el, (int)fl.size(), h->chi, h->eps, h->rank_floor, h->stream);
-        if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("truncate: ") + hipGetErrorString(e));
+        Timed tm(E, 2);
+        e = dd ? mpsk::launch_truncate_dd(dt, el, (int)fl.size(), E->rank_floor_dd, st)
+               : mpsk::launch_truncate(dt, el, (int)fl.size(), E->rank_floor, st);
+        if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("truncate: ") + hipGetErrorString(e));
       }
       {
-        Timed tm(h, 3);
+        Timed tm(E, 3);
         for (int which = 0; which < 2; ++which) {
           const std::vector<int>& ll = which ? fl3 : fl2;
           if (ll.empty()) continue;
           mpsk::Ent* e2 = which ? upload_list(LFIN3, ents_of(ll)) : upload_list(LMID, ents_of(ll));
-          if (!e2) return fail(h, MPS_EDEVICE, "list upload failed");
-          int lM = 0, lN = 0;
-          for (int si : ll) { lM = std::max(lM, slot[si].M); lN = std::max(lN, slot[si].N); }
-          const int maxK = std::min(h->chi, std::min(lM, lN));
-          e = dd ? mpsk::launch_split_dd(dt, e2, (int)ll.size(), lM, lN, maxK, h->stream, which == 0)
-                 : mpsk::launch_split(dt, e2, (int)ll.size(), lM, lN, maxK, h->stream, which == 0);
-          if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("split: ") + hipGetErrorString(e));
+          if (!e2) return fail(err, MPS_EDEVICE, "list upload failed");
+          int lM = 0, lN = 0, maxK = 1;
+          for (int si : ll) {
+            lM = std::max(lM, slot[si].M);
+            lN = std::max(lN, slot[si].N);
+            maxK = std::max(maxK, std::min(ht[si].chi, std::min(slot[si].M, slot[si].N)));
+          }
+          e = dd ? mpsk::launch_split_dd(dt, e2, (int)ll.size(), lM, lN, maxK, st, which == 0)
+                 : mpsk::launch_split(dt, e2, (int)ll.size(), lM, lN, maxK, st, which == 0);
+          if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("split: ") + hipGetErrorString(e));
         }
       }
-      HIPCHK(h, hipMemcpyAsync(hstats, d_stats, sizeof(double) * 8 * S, hipMemcpyDeviceToHost, h->stream));
-      HIPCHK(h, hipMemcpyAsync(h->h_stage + L.o_dims, h->d_dimx, sizeof(int) * (h->n + 1), hipMemcpyDeviceToHost,
-                               h->stream));
-      HIPCHK(h, hipStreamSynchronize(h->stream));
+      HIPCHK(err, hipMemcpyAsync(hstats, d_stats, sizeof(double) * 8 * S, hipMemcpyDeviceToHost, st));
+      HIPCHK(err, hipMemcpyAsync(hdims, d_dims, sizeof(int) * dims_total, hipMemcpyDeviceToHost, st));
+      HIPCHK(err, hipStreamSynchronize(st));
       unsynced = false;
-      std::memcpy(h->dimx.data(), h->h_stage + L.o_dims, sizeof(int) * (h->n + 1));
+      for (int u = 0; u < nu; ++u) std::memcpy(U[u]->dimx.data(), hdims + dims_off[u], sizeof(int) * (U[u]->n + 1));
       // first splits of three-site gates: the second split takes over in the reserved slot
       std::vector<mpsk::Ent> mids;
       std::vector<int> newB;
@@ -651,10 +901,12 @@ int run_gates(mps_state* h, const std::vector<GateRef>& gates) {
       for (int si : fl3) {
         Slot& sa = slot[si];
         const GateRef& g = gates[sa.gate];
+        const mps_state* h = U[g.unit];
         const int s0 = g.first, sb = sa.partner;
         Task2& tb = ht[sb];
         setup_split(h, tb, s0 + 1, h->dimx[s0 + 1], 0, h->dimx[s0 + 3]);
-        carve(h, tb, h->ws + L.slot_bytes * sb, d_flags, d_stats, d_fro, sb);
+        carve(dd, tb, E->ws + slot[sb].ws_off, d_flags, d_stats, d_fro, sb);
+        mark(sb);
         Slot& sbl = slot[sb];
         sbl.state = 1;
         sbl.sweep = 0;
@@ -670,17 +922,19 @@ int run_gates(mps_state* h, const std::vector<GateRef>& gates) {
         mNB = std::max(mNB, tb.N);
       }
       if (!mids.empty()) {
-        HIPCHK(h, hipMemcpyAsync(dt, ht, sizeof(Task2) * S, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(err, upload_tasks());
         unsynced = true;
         mpsk::Ent* eb = upload_list(LN2, ents_of(newB));
         mpsk::Ent* em = upload_list(LN3, mids);
-        if (!eb || !em) return fail(h, MPS_EDEVICE, "list upload failed");
-        Timed tm(h, 0);
-        e = mpsk::launch_prep2(dt, eb, (int)newB.size(), mNB, h->stream);
-        if (e == hipSuccess) e = mpsk::launch_mid3(dt, em, (int)mids.size(), mN1, mK1, dd, h->stream);
-        if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("mid: ") + hipGetErrorString(e));
-        for (int si : fl3) slot[si] = Slot{};  // its V is read by the mid kernel, queued before any reuse
+        if (!eb || !em) return fail(err, MPS_EDEVICE, "list upload failed");
+        Timed tm(E, 0);
+        e = mpsk::launch_prep2(dt, eb, (int)newB.size(), mNB, st);
+        if (e == hipSuccess) e = mpsk::launch_mid3(dt, em, (int)mids.size(), mN1, mK1, dd, st);
+        if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("mid: ") + hipGetErrorString(e));
       }
+      // a released slot's workspace is reused only by launches queued after the
+      // kernels that still read it (one stream)
+      for (int si : fl3) release_slot(si);
       for (int si : fl2) {
         Slot& sl = slot[si];
         const GateRef& g = gates[sl.gate];
@@ -688,34 +942,85 @@ int run_gates(mps_state* h, const std::vector<GateRef>& gates) {
         gsweeps[sl.gate] = std::max(gsweeps[sl.gate], sl.fp64_sweeps);
         gdd[sl.gate] = std::max(gdd[sl.gate], sl.dd_sweeps);
         if (!sl.conv) status = MPS_ENOCONV;
-        if (h->debug_sweeps)
-          std::fprintf(stderr, "[mps] update at site %d (M %d, N %d, kind %d): %d FP64 sweeps, %d dd sweeps\n",
-                       g.first, sl.M, sl.N, sl.kind, sl.fp64_sweeps, sl.dd_sweeps);
-        for (int q = g.first; q < g.first + g.k; ++q) busy[q] = 0;
-        sl = Slot{};
+        if (E->debug_sweeps)
+          std::fprintf(stderr, "[mps] update at state %d site %d (M %d, N %d, kind %d): %d FP64 sweeps, %d dd sweeps\n",
+                       g.unit, g.first, sl.M, sl.N, sl.kind, sl.fp64_sweeps, sl.dd_sweeps);
+        for (int q = g.first; q < g.first + g.k; ++q) busy[site_base[g.unit] + q] = 0;
+        release_slot(si);
       }
+      active.erase(std::remove_if(active.begin(), active.end(), [&](int si) { return slot[si].state == 0; }),
+                   active.end());
     }
   }
-  HIPCHK(h, hipStreamSynchronize(h->stream));
-  harvest_timing(h);
-  // diagnostics of the last multi-site gate in queue order
-  h->last.splits = 0;
-  for (size_t gi = gates.size(); gi-- > 0;) {
-    if (gates[gi].k == 1) continue;
-    const double* st = &gstats[8 * gi];
-    h->last.W = st[0];
-    h->last.w = st[1];
-    h->last.gap = st[2];
-    h->last.epsdist = st[3];
-    h->last.k = (int)st[4];
-    h->last.rank = (int)st[5];
-    h->last.sweeps = *std::max_element(gsweeps.begin(), gsweeps.end());
-    h->last.dd_sweeps = *std::max_element(gdd.begin(), gdd.end());
-    h->last.splits = gates[gi].k - 1;
-    break;
+  HIPCHK(err, hipStreamSynchronize(st));
+  harvest_timing(E);
+  // per state: diagnostics of its last multi-site gate in queue order
+  for (int u = 0; u < nu; ++u) {
+    mps_state* h = U[u];
+    for (size_t qi = queue[u].size(); qi-- > 0;) {
+      const int gi = queue[u][qi];
+      if (gates[gi].k == 1) continue;
+      const double* sv = &gstats[8 * gi];
+      h->last = mps_update_stats{};
+      h->last.W = sv[0];
+      h->last.w = sv[1];
+      h->last.gap = sv[2];
+      h->last.epsdist = sv[3];
+      h->last.k = (int)sv[4];
+      h->last.rank = (int)sv[5];
+      for (int gj : queue[u]) {
+        h->last.sweeps = std::max(h->last.sweeps, gsweeps[gj]);
+        h->last.dd_sweeps = std::max(h->last.dd_sweeps, gdd[gj]);
+      }
+      h->last.splits = gates[gi].k - 1;
+      break;
+    }
   }
-  if (status) return fail(h, status, "Jacobi sweep limit reached");
+  if (status) return fail(err, status, "Jacobi sweep limit reached");
   return MPS_OK;
+}
+
+int run_state(mps_state* h, const std::vector<GateRef>& gates) {
+  return run_sched(h->E, {h}, h->d_dimx, h->n + 1, {0}, gates, &h->err);
+}
+
+int set_option(Engine* E, int prec, int key, double value, std::string* err) {
+  switch (key) {
+    case MPS_OPT_MAX_SWEEPS:
+      if (!(value >= 1 && value <= 1000)) return fail(err, MPS_EINVAL, "max_sweeps out of range");
+      E->max_sweeps = (int)value;
+      E->max_sweeps_dd = (int)value;
+      return MPS_OK;
+    case MPS_OPT_JACOBI_TOL:
+      if (!(value > 0 && value <= 1e6)) return fail(err, MPS_EINVAL, "jacobi tol out of range");
+      E->tol_mult = value;
+      return MPS_OK;
+    case MPS_OPT_KERNEL_TIMING:
+      E->timing = value != 0;
+      return MPS_OK;
+    case MPS_OPT_BLOCK_WIDTH:
+      if (!(value == 4 || value == 8 || value == 16)) return fail(err, MPS_EINVAL, "block width must be 4, 8 or 16");
+      E->block_width = (int)value;
+      return MPS_OK;
+    case MPS_OPT_MAX_INNER:
+      if (!(value >= 1 && value <= 64)) return fail(err, MPS_EINVAL, "inner sweep limit out of range");
+      E->max_inner = (int)value;
+      return MPS_OK;
+    case MPS_OPT_RANK_FLOOR:
+      if (!(value >= 0 && value < 1)) return fail(err, MPS_EINVAL, "rank floor out of range");
+      if (prec == MPS_PREC_DD) E->rank_floor_dd = value; else E->rank_floor = value;
+      return MPS_OK;
+    case MPS_OPT_MAX_SLOTS:
+      if (!(value >= 1 && value <= 65536)) return fail(err, MPS_EINVAL, "slot limit out of range");
+      E->max_slots = (int)value;
+      return MPS_OK;
+    case MPS_OPT_WORKSPACE_MB:
+      if (!(value >= 1 && value <= 1 << 22)) return fail(err, MPS_EINVAL, "workspace limit out of range");
+      E->ws_limit = value * (1 << 20);
+      return MPS_OK;
+    default:
+      return fail(err, MPS_EINVAL, "unknown option");
+  }
 }
 
 }  // namespace
@@ -723,7 +1028,7 @@ int run_gates(mps_state* h, const std::vector<GateRef>& gates) {
 // ====================================================================== C ABI
 extern "C" {
 
-const char* mps_version(void) { return "mps-mi355x 0.1 (gfx950)"; }
+const char* mps_version(void) { return "mps-mi355x 0.2 (gfx950)"; }
 
 const char* mps_last_error(mps_handle h) { return h ? h->err.c_str() : g_create_error.c_str(); }
 
@@ -742,73 +1047,26 @@ mps_handle mps_create_ex(int n, int chi_max, double eps, int prec, void* hip_str
     return nullptr;
   }
   mps_state* h = new mps_state();
-  h->n = n;
-  h->chi = chi_max;
-  h->eps = eps;
-  h->prec = prec;
-  if (const char* dbg = std::getenv("MPS_DEBUG_SWEEPS")) h->debug_sweeps = dbg[0] == '1';
-  if (const char* dbg = std::getenv("MPS_DEBUG_PHASES"))
-    if (dbg[0] == '1' && hipMalloc((void**)&h->d_phase, 8 * sizeof(long long)) != hipSuccess) h->d_phase = nullptr;
-  auto bail = [&](const char* what, hipError_t e) {
-    g_create_error = std::string(what) + ": " + hipGetErrorString(e);
+  state_shape(h, n, chi_max, eps, prec);
+  h->E = engine_new(prec, hip_stream, &g_create_error);
+  if (!h->E) {
+    delete h;
+    return nullptr;
+  }
+  h->own_engine = true;
+  const size_t bytes = state_bytes(h, true);
+  hipError_t e = hipMalloc((void**)&h->mem, bytes);
+  if (e == hipSuccess) e = hipMemsetAsync(h->mem, 0, bytes, h->E->stream);
+  if (e != hipSuccess) {
+    g_create_error = std::string("mps_create: ") + hipGetErrorString(e);
     mps_destroy(h);
-    return (mps_handle) nullptr;
-  };
-  hipError_t e = hipGetDevice(&h->device);
-  if (e != hipSuccess) return bail("hipGetDevice", e);
-  if (hip_stream) {
-    h->stream = (hipStream_t)hip_stream;
-  } else {
-    e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
-    if (e != hipSuccess) return bail("hipStreamCreate", e);
-    h->own_stream = true;
+    return nullptr;
   }
-  h->capx.assign(n + 1, 1);
-  for (int b = 0; b + 1 < n; ++b) h->capx[b + 1] = bond_capacity(n, chi_max, b);
-  h->dimx.assign(n + 1, 1);
-  e = hipMalloc((void**)&h->d_dimx, sizeof(int) * (n + 1));
-  if (e != hipSuccess) return bail("hipMalloc", e);
-  const bool dd = prec == MPS_PREC_DD;
-  h->B.assign(n, nullptr);
-  if (dd) h->Blo.assign(n, nullptr);
-  for (int s = 0; s < n; ++s) {
-    size_t el = (size_t)h->capx[s] * 2 * h->capx[s + 1];
-    e = hipMalloc((void**)&h->B[s], el * sizeof(double2));
-    if (e != hipSuccess) return bail("hipMalloc", e);
-    if (dd) {
-      e = hipMalloc((void**)&h->Blo[s], el * sizeof(double2));
-      if (e != hipSuccess) return bail("hipMalloc", e);
-    }
+  state_carve(h, h->mem, true);
+  if (set_product_states(h->E, {h}, h->d_dimx, n + 1, &g_create_error)) {
+    mps_destroy(h);
+    return nullptr;
   }
-  size_t lam_el = (size_t)(n + 1) * chi_max;
-  e = hipMalloc((void**)&h->d_lam, lam_el * sizeof(double));
-  if (e != hipSuccess) return bail("hipMalloc", e);
-  if (dd) {
-    e = hipMalloc((void**)&h->d_lam_lo, lam_el * sizeof(double));
-    if (e != hipSuccess) return bail("hipMalloc", e);
-  }
-  // |0...0>: B_s[0][0][0] = 1, B_s[0][1][0] = 0, all V_s = [1]
-  std::vector<double> lam(lam_el, 0.0);
-  for (int sl = 0; sl <= n; ++sl) lam[(size_t)sl * chi_max] = 1.0;
-  e = hipMemcpy(h->d_lam, lam.data(), lam_el * sizeof(double), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return bail("hipMemcpy", e);
-  if (dd) {
-    e = hipMemset(h->d_lam_lo, 0, lam_el * sizeof(double));
-    if (e != hipSuccess) return bail("hipMemset", e);
-  }
-  for (int s = 0; s < n; ++s) {
-    size_t el = (size_t)h->capx[s] * 2 * h->capx[s + 1];
-    std::vector<double2> z(el, make_double2(0, 0));
-    z[0] = make_double2(1.0, 0.0);
-    e = hipMemcpy(h->B[s], z.data(), el * sizeof(double2), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return bail("hipMemcpy", e);
-    if (dd) {
-      e = hipMemset(h->Blo[s], 0, el * sizeof(double2));
-      if (e != hipSuccess) return bail("hipMemset", e);
-    }
-  }
-  e = hipMemcpy(h->d_dimx, h->dimx.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return bail("hipMemcpy", e);
   return h;
 }
 
@@ -818,19 +1076,10 @@ mps_handle mps_create(int n, int chi_max, double eps) {
 
 int mps_destroy(mps_handle h) {
   if (!h) return MPS_EINVAL;
-  if (h->stream) (void)hipStreamSynchronize(h->stream);
-  for (auto p : h->B) if (p) (void)hipFree(p);
-  for (auto p : h->Blo) if (p) (void)hipFree(p);
-  if (h->d_lam) (void)hipFree(h->d_lam);
-  if (h->d_lam_lo) (void)hipFree(h->d_lam_lo);
-  if (h->d_dimx) (void)hipFree(h->d_dimx);
-  if (h->d_phase) (void)hipFree(h->d_phase);
-  if (h->ws) (void)hipFree(h->ws);
-  if (h->d_small) (void)hipFree(h->d_small);
-  if (h->h_stage) (void)hipHostFree(h->h_stage);
-  for (auto& p : h->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
-  for (auto e : h->evpool) (void)hipEventDestroy(e);
-  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  if (h->batch) return fail(h, MPS_ESTATE, "a batch member is destroyed with its batch");
+  if (h->E && h->E->stream) (void)hipStreamSynchronize(h->E->stream);
+  if (h->mem) (void)hipFree(h->mem);
+  if (h->own_engine) engine_free(h->E);
   delete h;
   return MPS_OK;
 }
@@ -841,14 +1090,15 @@ int mps_apply_gates(mps_handle h, int count, const int* first, const int* k, con
   std::vector<GateRef> gates;
   gates.reserve(count);
   size_t off = 0;
+  const bool dd = h->prec == MPS_PREC_DD;
   for (int i = 0; i < count; ++i) {
-    const double* lo = U_lo ? U_lo + off : nullptr;
-    int rc = validate_gate(h, first[i], k[i], U + off, h->prec == MPS_PREC_DD ? lo : nullptr);
+    const double* lo = (U_lo && dd) ? U_lo + off : nullptr;
+    int rc = validate_gate(h, first[i], k[i], U + off, lo, &h->err);
     if (rc) return rc;
-    gates.push_back(GateRef{first[i], k[i], U + off, h->prec == MPS_PREC_DD ? lo : nullptr});
+    gates.push_back(GateRef{0, first[i], k[i], U + off, lo});
     off += (size_t)2 << (2 * k[i]);
   }
-  return run_gates(h, gates);
+  return run_state(h, gates);
 }
 
 int mps_apply_gate(mps_handle h, int first, int k, const double* U) {
@@ -872,7 +1122,7 @@ int mps_schmidt_dd(mps_handle h, int bond, double* lam_hi, double* lam_lo, int c
   const int mm = h->dimx[bond + 1];
   *m = mm;
   if (cap < mm) return fail(h, MPS_ERANGE, "Schmidt buffer too small");
-  HIPCHK(h, hipStreamSynchronize(h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->E->stream));
   HIPCHK(h, hipMemcpy(lam_hi, h->d_lam + (size_t)(bond + 1) * h->chi, sizeof(double) * mm, hipMemcpyDeviceToHost));
   if (lam_lo) {
     if (h->d_lam_lo)
@@ -895,13 +1145,14 @@ int mps_amplitudes(mps_handle h, int count, const unsigned char* bits, double* o
     if (bits[i] > 1) return fail(h, MPS_EINVAL, "bits must be 0 or 1");
   for (int s = 0; s <= h->n; ++s)
     if (h->dimx[s] > 1024) return fail(h, MPS_ERANGE, "amplitude kernel supports bond dims up to 1024");
+  Engine* E = h->E;
   const bool dd = h->prec == MPS_PREC_DD;
   const size_t nbits = align_up((size_t)count * h->n);
   const size_t o_ptr = nbits, o_ld = o_ptr + align_up(sizeof(void*) * 2 * h->n), o_out = o_ld + align_up(sizeof(int) * h->n);
   const size_t outb = (size_t)count * sizeof(double2) * (dd ? 2 : 1);
-  int rc = ensure_small(h, o_out + align_up(outb));
+  int rc = ensure_small(E, o_out + align_up(outb), &h->err);
   if (rc) return rc;
-  char* hs = h->h_stage;
+  char* hs = E->h_stage;
   std::memcpy(hs, bits, (size_t)count * h->n);
   const double2** hp = (const double2**)(hs + o_ptr);
   for (int s = 0; s < h->n; ++s) {
@@ -910,23 +1161,23 @@ int mps_amplitudes(mps_handle h, int count, const unsigned char* bits, double* o
   }
   int* hld = (int*)(hs + o_ld);
   for (int s = 0; s < h->n; ++s) hld[s] = h->capx[s + 1];
-  HIPCHK(h, hipMemcpyAsync(h->d_small, hs, o_out, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(E->d_small, hs, o_out, hipMemcpyHostToDevice, E->stream));
   mpsk::AmpArgs a{};
-  a.B = (const double2* const*)(h->d_small + o_ptr);
-  a.ld = (const int*)(h->d_small + o_ld);
+  a.B = (const double2* const*)(E->d_small + o_ptr);
+  a.ld = (const int*)(E->d_small + o_ld);
   a.dimx = h->d_dimx;
   a.n = h->n;
-  a.bits = (const unsigned char*)h->d_small;
-  a.out = (double2*)(h->d_small + o_out);
+  a.bits = (const unsigned char*)E->d_small;
+  a.out = (double2*)(E->d_small + o_out);
   {
-    Timed tm(h, 5);
-    hipError_t e = dd ? mpsk::launch_amplitude_dd(a, (const double2* const*)(h->d_small + o_ptr) + h->n, count, h->stream)
-                      : mpsk::launch_amplitude(a, count, h->stream);
+    Timed tm(E, 5);
+    hipError_t e = dd ? mpsk::launch_amplitude_dd(a, (const double2* const*)(E->d_small + o_ptr) + h->n, count, E->stream)
+                      : mpsk::launch_amplitude(a, count, E->stream);
     if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("amplitude: ") + hipGetErrorString(e));
   }
-  HIPCHK(h, hipMemcpyAsync(hs + o_out, h->d_small + o_out, outb, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(h, hipStreamSynchronize(h->stream));
-  harvest_timing(h);
+  HIPCHK(h, hipMemcpyAsync(hs + o_out, E->d_small + o_out, outb, hipMemcpyDeviceToHost, E->stream));
+  HIPCHK(h, hipStreamSynchronize(E->stream));
+  harvest_timing(E);
   std::memcpy(out, hs + o_out, outb);
   return MPS_OK;
 }
@@ -971,7 +1222,7 @@ int mps_load(mps_handle h, const int* dims, const double* const* B, const double
     if (dims[b] < 1 || dims[b] > h->capx[b + 1]) return fail(h, MPS_ERANGE, "bond dim above the bond's capacity");
     nd[b + 1] = dims[b];
   }
-  HIPCHK(h, hipStreamSynchronize(h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->E->stream));
   for (int s = 0; s < h->n; ++s) {
     const int a = nd[s], b = nd[s + 1], ld = h->capx[s + 1];
     for (int plane = 0; plane < (dd ? 2 : 1); ++plane) {
@@ -1005,7 +1256,7 @@ int mps_get_site(mps_handle h, int s, double* hi, double* lo, long cap_doubles) 
   if (s < 0 || s >= h->n) return fail(h, MPS_EINVAL, "site out of range");
   const int a = h->dimx[s], b = h->dimx[s + 1], ld = h->capx[s + 1];
   if (cap_doubles < (long)a * 2 * b * 2) return fail(h, MPS_ERANGE, "site buffer too small");
-  HIPCHK(h, hipStreamSynchronize(h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->E->stream));
   HIPCHK(h, hipMemcpy2D(hi, sizeof(double2) * b, h->B[s], sizeof(double2) * ld, sizeof(double2) * b, (size_t)2 * a,
                         hipMemcpyDeviceToHost));
   if (lo) {
@@ -1020,58 +1271,137 @@ int mps_get_site(mps_handle h, int s, double* hi, double* lo, long cap_doubles) 
 
 int mps_set_option(mps_handle h, int key, double value) {
   if (!h) return MPS_EINVAL;
-  switch (key) {
-    case MPS_OPT_MAX_SWEEPS:
-      if (!(value >= 1 && value <= 1000)) return fail(h, MPS_EINVAL, "max_sweeps out of range");
-      h->max_sweeps = (int)value;
-      h->max_sweeps_dd = (int)value;
-      return MPS_OK;
-    case MPS_OPT_JACOBI_TOL:
-      if (!(value > 0 && value <= 1e6)) return fail(h, MPS_EINVAL, "jacobi tol out of range");
-      h->tol_mult = value;
-      return MPS_OK;
-    case MPS_OPT_KERNEL_TIMING:
-      h->timing = value != 0;
-      return MPS_OK;
-    case MPS_OPT_BLOCK_WIDTH:
-      if (!(value == 4 || value == 8 || value == 16)) return fail(h, MPS_EINVAL, "block width must be 4, 8 or 16");
-      h->block_width = (int)value;
-      return MPS_OK;
-    case MPS_OPT_MAX_INNER:
-      if (!(value >= 1 && value <= 64)) return fail(h, MPS_EINVAL, "inner sweep limit out of range");
-      h->max_inner = (int)value;
-      return MPS_OK;
-    case MPS_OPT_RANK_FLOOR:
-      if (!(value >= 0 && value < 1)) return fail(h, MPS_EINVAL, "rank floor out of range");
-      if (h->prec == MPS_PREC_DD) h->rank_floor_dd = value; else h->rank_floor = value;
-      return MPS_OK;
-    default:
-      return fail(h, MPS_EINVAL, "unknown option");
-  }
+  return set_option(h->E, h->prec, key, value, &h->err);
 }
 
 int mps_sync(mps_handle h) {
   if (!h) return MPS_EINVAL;
-  HIPCHK(h, hipStreamSynchronize(h->stream));
-  harvest_timing(h);
+  HIPCHK(h, hipStreamSynchronize(h->E->stream));
+  harvest_timing(h->E);
   return MPS_OK;
 }
 
 int mps_kernel_time(mps_handle h, int cls, double* ms, long* launches, int reset) {
   if (!h || cls < 0 || cls >= 10) return MPS_EINVAL;
-  HIPCHK(h, hipStreamSynchronize(h->stream));
-  harvest_timing(h);
+  Engine* E = h->E;
+  HIPCHK(h, hipStreamSynchronize(E->stream));
+  harvest_timing(E);
   if (cls >= 8) {  // counters: update-sweeps of the FP64 Jacobi (8) and of the dd polish (9)
-    long& c = cls == 8 ? h->slot_sweeps : h->slot_sweeps_dd;
+    long& c = cls == 8 ? E->slot_sweeps : E->slot_sweeps_dd;
     if (ms) *ms = 0.0;
     if (launches) *launches = c;
     if (reset) c = 0;
     return MPS_OK;
   }
-  if (ms) *ms = h->tms[cls];
-  if (launches) *launches = h->tcount[cls];
-  if (reset) { h->tms[cls] = 0; h->tcount[cls] = 0; }
+  if (ms) *ms = E->tms[cls];
+  if (launches) *launches = E->tcount[cls];
+  if (reset) { E->tms[cls] = 0; E->tcount[cls] = 0; }
   return MPS_OK;
 }
+
+// ------------------------------------------------------------------ batches
+mps_batch_handle mps_batch_create(int count, const int* n, const int* chi_max, const double* eps, int prec) {
+  g_create_error.clear();
+  if (count < 1 || !n || !chi_max || !eps || (prec != MPS_PREC_FP64 && prec != MPS_PREC_DD)) {
+    g_create_error = "mps_batch_create: need count >= 1, per-circuit n, chi_max, eps and prec FP64 or DD";
+    return nullptr;
+  }
+  for (int i = 0; i < count; ++i)
+    if (n[i] < 1 || chi_max[i] < 1 || chi_max[i] > 2048 || !(eps[i] >= 0) || !std::isfinite(eps[i])) {
+      g_create_error = "mps_batch_create: circuit " + std::to_string(i) +
+                       " needs n >= 1, 1 <= chi_max <= 2048, finite eps >= 0";
+      return nullptr;
+    }
+  mps_batch* b = new mps_batch();
+  b->E = engine_new(prec, nullptr, &g_create_error);
+  if (!b->E) {
+    delete b;
+    return nullptr;
+  }
+  b->E->batch = true;
+  b->E->max_slots = 1024;
+  size_t bytes = 0;
+  for (int i = 0; i < count; ++i) {
+    mps_state* h = new mps_state();
+    state_shape(h, n[i], chi_max[i], eps[i], prec);
+    h->E = b->E;
+    h->batch = b;
+    b->units.push_back(h);
+    bytes += state_bytes(h, false);
+    b->dims_total += n[i] + 1;
+  }
+  const size_t dims_bytes = align_up(sizeof(int) * b->dims_total);
+  hipError_t e = hipMalloc((void**)&b->mem, bytes + dims_bytes);
+  if (e == hipSuccess) e = hipMemsetAsync(b->mem, 0, bytes + dims_bytes, b->E->stream);
+  if (e != hipSuccess) {
+    g_create_error = std::string("mps_batch_create: ") + hipGetErrorString(e);
+    mps_batch_destroy(b);
+    return nullptr;
+  }
+  char* p = b->mem;
+  b->d_dims = (int*)(b->mem + bytes);
+  int off = 0;
+  for (mps_state* h : b->units) {
+    p = state_carve(h, p, false);
+    h->d_dimx = b->d_dims + off;
+    off += h->n + 1;
+  }
+  if (set_product_states(b->E, b->units, b->d_dims, b->dims_total, &g_create_error)) {
+    mps_batch_destroy(b);
+    return nullptr;
+  }
+  return b;
+}
+
+int mps_batch_destroy(mps_batch_handle b) {
+  if (!b) return MPS_EINVAL;
+  if (b->E && b->E->stream) (void)hipStreamSynchronize(b->E->stream);
+  for (mps_state* h : b->units) delete h;
+  if (b->mem) (void)hipFree(b->mem);
+  engine_free(b->E);
+  delete b;
+  return MPS_OK;
+}
+
+mps_handle mps_batch_get(mps_batch_handle b, int circuit) {
+  if (!b || circuit < 0 || circuit >= (int)b->units.size()) return nullptr;
+  return b->units[circuit];
+}
+
+int mps_batch_run(mps_batch_handle b, long ngates, const int* circuit, const int* first, const int* k,
+                  const double* U, const double* U_lo) {
+  if (!b) return MPS_EINVAL;
+  if (ngates < 0 || (ngates > 0 && (!circuit || !first || !k || !U))) return fail(b, MPS_EINVAL, "bad gate list");
+  const bool dd = b->E->prec == MPS_PREC_DD;
+  std::vector<GateRef> gates;
+  gates.reserve(ngates);
+  size_t off = 0;
+  for (long i = 0; i < ngates; ++i) {
+    if (circuit[i] < 0 || circuit[i] >= (int)b->units.size())
+      return fail(b, MPS_EINVAL, "gate " + std::to_string(i) + ": circuit index out of range");
+    const double* lo = (U_lo && dd) ? U_lo + off : nullptr;
+    int rc = validate_gate(b->units[circuit[i]], first[i], k[i], U + off, lo, &b->err);
+    if (rc) {
+      b->err = "gate " + std::to_string(i) + ": " + b->err;
+      return rc;
+    }
+    gates.push_back(GateRef{circuit[i], first[i], k[i], U + off, lo});
+    off += (size_t)2 << (2 * k[i]);
+  }
+  std::vector<int> dims_off;
+  int o = 0;
+  for (mps_state* h : b->units) {
+    dims_off.push_back(o);
+    o += h->n + 1;
+  }
+  return run_sched(b->E, b->units, b->d_dims, b->dims_total, dims_off, gates, &b->err);
+}
+
+int mps_batch_set_option(mps_batch_handle b, int key, double value) {
+  if (!b) return MPS_EINVAL;
+  return set_option(b->E, b->E->prec, key, value, &b->err);
+}
+
+const char* mps_batch_last_error(mps_batch_handle b) { return b ? b->err.c_str() : g_create_error.c_str(); }
 
 }  // extern "C"

@@ -27,7 +27,7 @@ __all__ = [
     "bitstrings", "ghz_circuit", "paper_sample_circuit", "embed_gate",
     "product_state_prep", "qft_lnn_circuit", "random_mps_B", "batch_spec",
     "Gate", "hadamard", "cnot", "dd_split", "haar_unitary_dd", "brickwork_dd",
-    "random_circuit_dd", "basis_prep",
+    "random_circuit_dd", "basis_prep", "batch_gates", "CircuitSpec",
 ]
 
 
@@ -295,3 +295,17 @@ def batch_spec(count: int, seed: int) -> list[CircuitSpec]:
         depth = int(rng.integers(8, 25))
         out.append(CircuitSpec(n, chi, depth, int(kids[i].generate_state(1)[0])))
     return out
+
+
+def batch_gates(specs: list[CircuitSpec]) -> tuple[list[int], list[Gate]]:
+    """The brickwork circuits of `specs` (Haar U(4), each from its own seed) as one
+    gate list, layer-interleaved: layer t of every circuit, then layer t + 1.
+    Returns (circuit index per gate, gates)."""
+    layers = [brickwork(s.n, s.depth, s.seed) for s in specs]
+    circ, gates = [], []
+    for t in range(max((s.depth for s in specs), default=0)):
+        for i, ls in enumerate(layers):
+            if t < len(ls):
+                circ += [i] * len(ls[t])
+                gates += ls[t]
+    return circ, gates
