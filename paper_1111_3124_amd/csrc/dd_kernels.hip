@@ -5,7 +5,8 @@
 //   FP64 block Jacobi on round(theta_w)        [k_jacobi_step<BW> of kernels.hip] -> V0
 //   V <- V (I - E/2), E = V^H V - I, twice     [k_gram_dd + k_ns_fix] (Newton-Schulz step of
 //                                              the polar factor: orthogonality error squares)
-//   W = theta_w V in dd                        [k_wmul_dd]
+//   W = theta_w V in dd                        [k_wmul_dd]  (W = R^H V_R for a wide theta,
+//                                              whose Householder QR is in qr.hip)
 //   dd block Jacobi polish sweeps on (W, V)    [k_jacobi_step_dd]
 //   sort / truncate / renormalise in dd        [k_truncate_dd]
 //   B_{s+1}' = Z_k^H, B_s' = theta Z_k / nu    [k_split_*_dd]
@@ -85,9 +86,9 @@ struct ThetaOpDD {
 __global__ __launch_bounds__(256) void k_theta2_dd(Task2* tasks, const Ent* ents) {
   const Task2* t = &tasks[ents[blockIdx.z].slot];
   const int tm = blockIdx.x * 32, tn = blockIdx.y * 32;
-  if (tm >= t->M || tn >= t->N) return;
+  if (tm >= t->M || tn >= t->Nt) return;
   ThetaOpDD op{t};
-  ddgemm_tile(op, t->M, t->N, t->b, tm, tn);
+  ddgemm_tile(op, t->M, t->Nt, t->b, tm, tn);
 }
 
 // ------------------------------------------------------------------ Newton-Schulz
@@ -177,6 +178,7 @@ struct WOpDD {
   static constexpr bool kBColFast = false;
   const Task2* t;
   __device__ cdd a(int row, int kk) const {
+    if (t->Rh) return ldc(t->Rh, t->Rh_lo, (long)kk * t->M + row);  // wide: R^H
     const cdd x = ldc(t->thu, t->thu_lo, (long)kk * t->M + row);
     const ddr w = {t->lamL[row >> 1], t->lamL_lo[row >> 1]};
     return dd::cscale(x, w);
@@ -552,13 +554,13 @@ __global__ __launch_bounds__(1024) void k_truncate_dd(Task2* tasks, const Ent* e
 // ------------------------------------------------------------------ split (dd)
 __global__ __launch_bounds__(256) void k_split_right_dd(Task2* tasks, const Ent* ents) {
   const Task2& T = tasks[ents[blockIdx.z].slot];
-  const int k = *T.dim_out, N = T.N, c = T.c;
+  const int k = *T.dim_out, Nt = T.Nt, c = T.c;
   const int nu = blockIdx.y;
   if (nu >= k) return;
-  const int col = T.perm[nu];
-  for (int e = blockIdx.x * 256 + threadIdx.x; e < N; e += gridDim.x * 256) {
+  const int col = T.zdirect ? nu : T.perm[nu];
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < Nt; e += gridDim.x * 256) {
     const int j = e / c, ga = e - j * c;
-    const cdd v = dd::cconj(ldc(T.V, T.V_lo, (long)col * N + e));
+    const cdd v = dd::cconj(ldc(T.Z, T.Z_lo, (long)col * Nt + e));
     stc(T.Br, T.Br_lo, (long)(2 * nu + j) * T.ldr + ga, v);
   }
 }
@@ -570,7 +572,9 @@ struct SplitLeftOpDD {
   int k;
   ddr inv_nu;
   __device__ cdd a(int row, int kk) const { return ldc(t->thu, t->thu_lo, (long)kk * t->M + row); }
-  __device__ cdd b(int kk, int col) const { return ldc(t->V, t->V_lo, (long)t->perm[col] * t->N + kk); }
+  __device__ cdd b(int kk, int col) const {
+    return ldc(t->Z, t->Z_lo, (long)(t->zdirect ? col : t->perm[col]) * t->Nt + kk);
+  }
   __device__ void epilogue(int r0, int c0, cdd (&v)[2][2]) const {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -589,7 +593,7 @@ __global__ __launch_bounds__(256) void k_split_left_dd(Task2* tasks, const Ent* 
   if (tm >= t->M || tn >= k) return;
   const ddr nu = {t->stats[6], t->stats[7]};
   SplitLeftOpDD op{t, k, dd::div(dd::from(1.0), nu)};
-  ddgemm_tile(op, t->M, k, t->N, tm, tn);
+  ddgemm_tile(op, t->M, k, t->Nt, tm, tn);
 }
 
 // ------------------------------------------------------------------ amplitudes (dd)

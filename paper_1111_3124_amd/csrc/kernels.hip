@@ -91,9 +91,9 @@ struct ThetaOp {
 __global__ __launch_bounds__(256) void k_theta2(Task2* tasks, const Ent* ents) {
   const Task2* t = &tasks[ents[blockIdx.z].slot];
   const int tm = blockIdx.x * 64, tn = blockIdx.y * 64;
-  if (tm >= t->M || tn >= t->N) return;
+  if (tm >= t->M || tn >= t->Nt) return;
   ThetaOp op{t};
-  cgemm_tile(op, t->M, t->N, t->b, tm, tn);
+  cgemm_tile(op, t->M, t->Nt, t->b, tm, tn);
 }
 
 // ------------------------------------------------------------------ Jacobi step
@@ -480,16 +480,16 @@ __global__ __launch_bounds__(1024) void k_truncate(Task2* tasks, const Ent* ents
 }
 
 // ------------------------------------------------------------------ split
-// B_{s+1}'[nu][j][gamma] = conj(V[(j c + gamma), perm[nu]])  (rows of Z_k^H)
+// B_{s+1}'[nu][j][gamma] = conj(Z[(j c + gamma), nu-th kept column])  (rows of Z_k^H)
 __global__ __launch_bounds__(256) void k_split_right(Task2* tasks, const Ent* ents) {
   const Task2& T = tasks[ents[blockIdx.z].slot];
-  const int k = *T.dim_out, N = T.N, c = T.c;
+  const int k = *T.dim_out, Nt = T.Nt, c = T.c;
   const int nu = blockIdx.y;
   if (nu >= k) return;
-  const int col = T.perm[nu];
-  for (int e = blockIdx.x * 256 + threadIdx.x; e < N; e += gridDim.x * 256) {
+  const int col = T.zdirect ? nu : T.perm[nu];
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < Nt; e += gridDim.x * 256) {
     const int j = e / c, ga = e - j * c;
-    T.Br[(long)(2 * nu + j) * T.ldr + ga] = cconj(T.V[(long)col * N + e]);
+    T.Br[(long)(2 * nu + j) * T.ldr + ga] = cconj(T.Z[(long)col * Nt + e]);
   }
 }
 
@@ -501,7 +501,9 @@ struct SplitLeftOp {
   int k;
   double inv_nu;
   __device__ double2 a(int row, int kk) const { return t->thu[(long)kk * t->M + row]; }
-  __device__ double2 b(int kk, int col) const { return t->V[(long)t->perm[col] * t->N + kk]; }
+  __device__ double2 b(int kk, int col) const {
+    return t->Z[(long)(t->zdirect ? col : t->perm[col]) * t->Nt + kk];
+  }
   __device__ void epilogue(int r0, int c0, double2 (&acc)[4][4]) const {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -522,7 +524,7 @@ __global__ __launch_bounds__(256) void k_split_left(Task2* tasks, const Ent* ent
   const int tm = blockIdx.x * 64, tn = blockIdx.y * 64;
   if (tm >= t->M || tn >= k) return;
   SplitLeftOp op{t, k, 1.0 / t->stats[6]};
-  cgemm_tile(op, t->M, k, t->N, tm, tn);
+  cgemm_tile(op, t->M, k, t->Nt, tm, tn);
 }
 
 // ------------------------------------------------------------------ single-site gate

@@ -102,19 +102,20 @@ __global__ __launch_bounds__(256) void k_theta3(Task2* tasks, const Ent* ents) {
 }
 
 // theta of split 2 from split 1: theta2[(2 nu + j) + (k d + delta) M2] = conj(Z1[(j,k,delta), nu]),
+// (Z1 column nu = the nu-th kept right singular vector of split 1),
 // theta2_w = V_s'[nu] theta2.  ents[].slot = split-1 slot, ents[].sweep = split-2 slot.
 __global__ __launch_bounds__(256) void k_mid3(Task2* tasks, const Ent* ents) {
   const Task2& A = tasks[ents[blockIdx.z].slot];
   const Task2& Bt = tasks[ents[blockIdx.z].sweep];
-  const int k1 = *A.dim_out, d = A.d, N1 = A.N, M2 = Bt.M;
+  const int k1 = *A.dim_out, d = A.d, N1 = A.Nt, M2 = Bt.M;
   const int nu = blockIdx.y;
   double fro = 0.0;
   if (nu < k1) {
-    const int col = A.perm[nu];
+    const int col = A.zdirect ? nu : A.perm[nu];
     const double w = A.lamS[nu];
     for (int e = blockIdx.x * 256 + threadIdx.x; e < N1; e += gridDim.x * 256) {
       const int j = e / (2 * d), k = (e / d) & 1, de = e % d;
-      const double2 v = cconj(A.V[(long)col * N1 + e]);
+      const double2 v = cconj(A.Z[(long)col * N1 + e]);
       const long idx = (long)(k * d + de) * M2 + (2 * nu + j);
       Bt.thu[idx] = v;
       const double2 vw = cscale(v, w);
@@ -221,15 +222,15 @@ __global__ __launch_bounds__(256) void k_theta3_dd(Task2* tasks, const Ent* ents
 __global__ __launch_bounds__(256) void k_mid3_dd(Task2* tasks, const Ent* ents) {
   const Task2& A = tasks[ents[blockIdx.z].slot];
   const Task2& Bt = tasks[ents[blockIdx.z].sweep];
-  const int k1 = *A.dim_out, d = A.d, N1 = A.N, M2 = Bt.M;
+  const int k1 = *A.dim_out, d = A.d, N1 = A.Nt, M2 = Bt.M;
   const int nu = blockIdx.y;
   double fro = 0.0;
   if (nu < k1) {
-    const int col = A.perm[nu];
+    const int col = A.zdirect ? nu : A.perm[nu];
     const ddr w = {A.lamS[nu], A.lamS_lo[nu]};
     for (int e = blockIdx.x * 256 + threadIdx.x; e < N1; e += gridDim.x * 256) {
       const int j = e / (2 * d), k = (e / d) & 1, de = e % d;
-      const cdd v = dd::cconj(ldc(A.V, A.V_lo, (long)col * N1 + e));
+      const cdd v = dd::cconj(ldc(A.Z, A.Z_lo, (long)col * N1 + e));
       const long idx = (long)(k * d + de) * M2 + (2 * nu + j);
       stc(Bt.thu, Bt.thu_lo, idx, v);
       const cdd vw = dd::cscale(v, w);

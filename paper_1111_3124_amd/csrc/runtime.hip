@@ -24,6 +24,7 @@
 #include "dd_kernels.h"
 #include "kernels3.h"
 #include "launch.h"
+#include "qr.h"
 
 using mpsk::Task1;
 using mpsk::Task2;
@@ -395,22 +396,42 @@ struct Slot {
   int sweep = 0;
   int fp64_sweeps = 0, dd_sweeps = 0;
   bool fp64_conv = false, conv = false;
-  int M = 0, N = 0;
+  int M = 0, N = 0, Nt = 0;  // Jacobi rows, Jacobi columns, theta columns
   size_t ws_off = 0, ws_len = 0;  // workspace held in the arena
 };
 
-size_t slot_workspace_bytes(bool dd, int Mcap, int Ncap, int t1cap) {
-  const size_t MN = (size_t)Mcap * Ncap, NN = (size_t)Ncap * Ncap;
-  size_t b = align_up((2 * MN + NN) * sizeof(double2)) * (dd ? 2 : 1);
+// Workspace of a task with an M x Nt theta: theta and theta_w (later W, and Z for a
+// wide theta), V (N x N, N = Nt or M when wide), the dd scratch, sigma^2, the order,
+// T1 (three-site first split), and for a wide theta Q, tau and (dd) R^H.
+size_t task_ws_bytes(bool dd, int M, int Nt, int t1, bool wide) {
+  const int N = wide ? M : Nt, P = dd ? 2 : 1;
+  const size_t MN = (size_t)M * Nt, NN = (size_t)N * N;
+  size_t b = align_up((2 * MN + NN) * sizeof(double2)) * P;
   if (dd) b += 2 * align_up(NN * sizeof(double2));
-  b += align_up(Ncap * sizeof(double)) * (dd ? 2 : 1) + align_up(Ncap * sizeof(int));
-  b += align_up((size_t)t1cap * sizeof(double2)) * (dd ? 2 : 1);
+  b += align_up(N * sizeof(double)) * P + align_up(N * sizeof(int));
+  b += align_up((size_t)t1 * sizeof(double2)) * P;
+  if (wide) {
+    b += align_up(MN * sizeof(double2)) * P + align_up((size_t)M * sizeof(double2)) * P;
+    if (dd) b += 2 * align_up((size_t)M * M * sizeof(double2));
+  }
   return b;
 }
 
-// workspace pointers of a task whose theta is M x N, carved from the region w
+// a bound over every task with M <= Mcap and Nt <= Ncap
+size_t task_ws_bound(bool dd, int Mcap, int Ncap, int t1) {
+  return std::max(task_ws_bytes(dd, Mcap, std::min(Mcap, Ncap), t1, false), task_ws_bytes(dd, Mcap, Ncap, t1, true));
+}
+
+// theta columns; a wide theta (Nt > M) is QR-preconditioned and its Jacobi runs on R^H
+void set_cols(Task2& t, int Nt) {
+  t.Nt = Nt;
+  t.N = Nt > t.M ? t.M : Nt;
+}
+
+// workspace pointers of a task (shape already set), carved from the region w
 void carve(bool dd, Task2& t, char* w, int* d_flags, double* d_stats, double* d_fro, int slot) {
-  const size_t MN = (size_t)t.M * t.N, NN = (size_t)t.N * t.N;
+  const bool wide = t.Nt > t.M;
+  const size_t MN = (size_t)t.M * t.Nt, NN = (size_t)t.N * t.N;
   t.thu = (double2*)w;
   t.thw = t.thu + MN;
   t.V = t.thw + MN;
@@ -437,7 +458,33 @@ void carve(bool dd, Task2& t, char* w, int* d_flags, double* d_stats, double* d_
     const size_t t1 = (size_t)4 * t.a * t.c;
     t.T1 = (double2*)w;
     w += align_up(t1 * sizeof(double2));
-    if (dd) t.T1_lo = (double2*)w;
+    if (dd) {
+      t.T1_lo = (double2*)w;
+      w += align_up(t1 * sizeof(double2));
+    }
+  }
+  t.Z = t.V;
+  t.Z_lo = t.V_lo;
+  t.zdirect = 0;
+  t.Qh = t.Qh_lo = t.tau = t.tau_lo = t.Rh = t.Rh_lo = nullptr;
+  if (wide) {
+    t.Qh = (double2*)w;
+    w += align_up(MN * sizeof(double2));
+    t.tau = (double2*)w;
+    w += align_up((size_t)t.M * sizeof(double2));
+    if (dd) {
+      t.Qh_lo = (double2*)w;
+      w += align_up(MN * sizeof(double2));
+      t.tau_lo = (double2*)w;
+      w += align_up((size_t)t.M * sizeof(double2));
+      t.Rh = (double2*)w;
+      w += align_up((size_t)t.M * t.M * sizeof(double2));
+      t.Rh_lo = (double2*)w;
+      w += align_up((size_t)t.M * t.M * sizeof(double2));
+    }
+    t.Z = t.thw;  // Z (Nt x k) replaces W once the truncation has read sigma
+    t.Z_lo = t.thw_lo;
+    t.zdirect = 1;
   }
   t.flags = d_flags + 3 * slot;
   t.stats = d_stats + 8 * slot;
@@ -458,7 +505,7 @@ void setup_split(const mps_state* h, Task2& t, int s, int a, int b, int c) {
   t.b = b;
   t.c = c;
   t.M = 2 * a;
-  t.N = 2 * c;
+  set_cols(t, 2 * c);
   t.lamL = h->d_lam + (size_t)s * h->chi;
   t.lamL_lo = dd ? h->d_lam_lo + (size_t)s * h->chi : nullptr;
   t.lamS = h->d_lam + (size_t)(s + 1) * h->chi;
@@ -468,13 +515,12 @@ void setup_split(const mps_state* h, Task2& t, int s, int a, int b, int c) {
   t.eps = h->eps;
 }
 
-// workspace of a gate's first task (upper bound over the live dims: capacities)
+// workspace of a gate's tasks (upper bound over the live dims: capacities)
 size_t gate_need_cap(bool dd, const mps_state* h, int first, int k) {
-  if (k == 2) return slot_workspace_bytes(dd, 2 * h->capx[first], 2 * h->capx[first + 2], 0);
+  if (k == 2) return task_ws_bound(dd, 2 * h->capx[first], 2 * h->capx[first + 2], 0);
   if (k == 3)
-    return slot_workspace_bytes(dd, 2 * h->capx[first], 4 * h->capx[first + 3],
-                                4 * h->capx[first] * h->capx[first + 2]) +
-           slot_workspace_bytes(dd, 2 * h->capx[first + 1], 2 * h->capx[first + 3], 0);
+    return task_ws_bound(dd, 2 * h->capx[first], 4 * h->capx[first + 3], 4 * h->capx[first] * h->capx[first + 2]) +
+           task_ws_bound(dd, 2 * h->capx[first + 1], 2 * h->capx[first + 3], 0);
   return 0;
 }
 
@@ -509,7 +555,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
   size_t uniform = 0, arena_bytes;
   if (!E->batch) {
     const int Mcap = 2 * capmax, Ncap = (n3 ? 4 : 2) * capmax;
-    uniform = slot_workspace_bytes(dd, Mcap, Ncap, n3 ? 4 * capmax * capmax : 0);
+    uniform = task_ws_bound(dd, Mcap, Ncap, n3 ? 4 * capmax * capmax : 0);
     arena_bytes = uniform * S;
   } else {
     arena_bytes = std::max(max_need, (size_t)std::min(E->ws_limit, (double)max_need * S));
@@ -525,7 +571,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
   const size_t o_u8 = o_dims + align_up(sizeof(int) * dims_total);
   const size_t o_g1 = o_u8 + align_up(sizeof(double2) * 128 * S);
   const size_t o_ents = o_g1 + align_up(sizeof(Task1) * nsites);
-  constexpr int kLists = 8;  // new2, new3, jacobi, dd, dd-enter, final, final3, mid
+  constexpr int kLists = 11;  // new2, new3, jacobi, dd, dd-enter, final, final3, mid, qr, zform, qr2
   const size_t list_bytes = align_up(sizeof(mpsk::Ent) * S);
   rc = ensure_small(E, o_ents + kLists * list_bytes, err);
   if (rc) return rc;
@@ -539,7 +585,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
   int* hdims = (int*)(E->h_stage + o_dims);
   double2* hu8 = (double2*)(E->h_stage + o_u8);
   double2* du8 = (double2*)(E->d_small + o_u8);
-  enum { LN2 = 0, LN3, LJ, LD, LENTER, LFIN, LFIN3, LMID };
+  enum { LN2 = 0, LN3, LJ, LD, LENTER, LFIN, LFIN3, LMID, LQR, LZF, LQR2 };
   auto hlist = [&](int i) { return E->h_stage + o_ents + i * list_bytes; };
   auto dlist = [&](int i) { return E->d_small + o_ents + i * list_bytes; };
 
@@ -647,12 +693,13 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
         if (free_ && (int)free_list.size() >= (g.k == 3 ? 2 : 1)) {
           size_t off1 = 0, off2 = 0, len1 = 0, len2 = 0;
           if (g.k == 2) {
-            len1 = ws_alloc(slot_workspace_bytes(dd, 2 * h->dimx[s0], 2 * h->dimx[s0 + 2], 0), off1);
+            const int M = 2 * h->dimx[s0], Nt = 2 * h->dimx[s0 + 2];
+            len1 = ws_alloc(task_ws_bytes(dd, M, Nt, 0, Nt > M), off1);
           } else {
             const int a = h->dimx[s0], c = h->dimx[s0 + 2], d = h->dimx[s0 + 3];
-            len1 = ws_alloc(slot_workspace_bytes(dd, 2 * a, 4 * d, 4 * a * c), off1);
+            len1 = ws_alloc(task_ws_bytes(dd, 2 * a, 4 * d, 4 * a * c, 4 * d > 2 * a), off1);
             if (len1) {
-              len2 = ws_alloc(slot_workspace_bytes(dd, 2 * h->capx[s0 + 1], 2 * d, 0), off2);
+              len2 = ws_alloc(task_ws_bound(dd, 2 * h->capx[s0 + 1], 2 * d, 0), off2);
               if (!len2) {
                 E->arena.release(off1, len1);
                 len1 = 0;
@@ -681,7 +728,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
               t.B3_lo = dd ? h->Blo[s0 + 2] : nullptr;
               t.ld3 = h->capx[s0 + 3];
               t.d = h->dimx[s0 + 3];
-              t.N = 4 * t.d;
+              set_cols(t, 4 * t.d);
               double2* u8h = hu8 + 128 * si;
               for (int q = 0; q < 64; ++q) {
                 u8h[q] = make_double2(g.U[2 * q], g.U[2 * q + 1]);
@@ -705,6 +752,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
             mark(si);
             sl.M = t.M;
             sl.N = t.N;
+            sl.Nt = t.Nt;
             active.push_back(si);
             for (int q = g.first; q < g.first + g.k; ++q) busy[sb0 + q] = 1;
             done[gi] = 1;
@@ -737,16 +785,17 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
         for (int si : new3)
           HIPCHK(err, hipMemcpyAsync(du8 + 128 * si, hu8 + 128 * si, sizeof(double2) * 128, hipMemcpyHostToDevice, st));
       unsynced = true;
-      Timed tm(E, 0);
       for (int which = 0; which < 2; ++which) {
+        Timed tm(E, 0);
         const std::vector<int>& nl = which ? new3 : new2;
         if (nl.empty()) continue;
         mpsk::Ent* el = upload_list(which ? LN3 : LN2, ents_of(nl));
         if (!el) return fail(err, MPS_EDEVICE, "list upload failed");
-        int mM = 0, mN = 0, mA = 0, mC = 0, mD = 0;
+        int mM = 0, mN = 0, mNt = 0, mA = 0, mC = 0, mD = 0;
         for (int si : nl) {
           mM = std::max(mM, slot[si].M);
           mN = std::max(mN, slot[si].N);
+          mNt = std::max(mNt, slot[si].Nt);
           mA = std::max(mA, ht[si].a);
           mC = std::max(mC, ht[si].c);
           mD = std::max(mD, ht[si].d);
@@ -756,10 +805,20 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
           if (which)
             e = mpsk::launch_theta3(dt, el, (int)nl.size(), mA, mC, mD, dd, st);
           else
-            e = dd ? mpsk::launch_theta2_dd(dt, el, (int)nl.size(), mM, mN, st)
-                   : mpsk::launch_theta2(dt, el, (int)nl.size(), mM, mN, st);
+            e = dd ? mpsk::launch_theta2_dd(dt, el, (int)nl.size(), mM, mNt, st)
+                   : mpsk::launch_theta2(dt, el, (int)nl.size(), mM, mNt, st);
         }
         if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("theta: ") + hipGetErrorString(e));
+      }
+      std::vector<int> ql;
+      for (int si : new2) if (slot[si].Nt > slot[si].M) ql.push_back(si);
+      for (int si : new3) if (slot[si].Nt > slot[si].M) ql.push_back(si);
+      if (!ql.empty()) {
+        mpsk::Ent* el = upload_list(LQR, ents_of(ql));
+        if (!el) return fail(err, MPS_EDEVICE, "list upload failed");
+        Timed tq(E, 7);
+        e = mpsk::launch_qr(dt, el, (int)ql.size(), dd, st);
+        if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("qr: ") + hipGetErrorString(e));
       }
     }
     // ---- 2. one sweep for every iterating slot
@@ -872,6 +931,23 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
         if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("truncate: ") + hipGetErrorString(e));
       }
       {
+        std::vector<int> zl;
+        int zNt = 0, zK = 1;
+        for (int si : fl)
+          if (slot[si].Nt > slot[si].M) {
+            zl.push_back(si);
+            zNt = std::max(zNt, slot[si].Nt);
+            zK = std::max(zK, std::min(ht[si].chi, slot[si].M));
+          }
+        if (!zl.empty()) {
+          mpsk::Ent* ez = upload_list(LZF, ents_of(zl));
+          if (!ez) return fail(err, MPS_EDEVICE, "list upload failed");
+          Timed tz(E, 7);
+          e = mpsk::launch_zform(dt, ez, (int)zl.size(), zNt, zK, dd, st);
+          if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("zform: ") + hipGetErrorString(e));
+        }
+      }
+      {
         Timed tm(E, 3);
         for (int which = 0; which < 2; ++which) {
           const std::vector<int>& ll = which ? fl3 : fl2;
@@ -881,7 +957,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
           int lM = 0, lN = 0, maxK = 1;
           for (int si : ll) {
             lM = std::max(lM, slot[si].M);
-            lN = std::max(lN, slot[si].N);
+            lN = std::max(lN, slot[si].Nt);
             maxK = std::max(maxK, std::min(ht[si].chi, std::min(slot[si].M, slot[si].N)));
           }
           e = dd ? mpsk::launch_split_dd(dt, e2, (int)ll.size(), lM, lN, maxK, st, which == 0)
@@ -912,12 +988,13 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
         sbl.sweep = 0;
         sbl.M = tb.M;
         sbl.N = tb.N;
+        sbl.Nt = tb.Nt;
         gsweeps[sa.gate] = sa.fp64_sweeps;
         gdd[sa.gate] = sa.dd_sweeps;
         if (!sa.conv) status = MPS_ENOCONV;
         mids.push_back(mpsk::Ent{si, sb});
         newB.push_back(sb);
-        mN1 = std::max(mN1, sa.N);
+        mN1 = std::max(mN1, sa.Nt);
         mK1 = std::max(mK1, std::min(h->chi, sa.M));
         mNB = std::max(mNB, tb.N);
       }
@@ -927,10 +1004,21 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
         mpsk::Ent* eb = upload_list(LN2, ents_of(newB));
         mpsk::Ent* em = upload_list(LN3, mids);
         if (!eb || !em) return fail(err, MPS_EDEVICE, "list upload failed");
-        Timed tm(E, 0);
-        e = mpsk::launch_prep2(dt, eb, (int)newB.size(), mNB, st);
-        if (e == hipSuccess) e = mpsk::launch_mid3(dt, em, (int)mids.size(), mN1, mK1, dd, st);
-        if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("mid: ") + hipGetErrorString(e));
+        {
+          Timed tm(E, 0);
+          e = mpsk::launch_prep2(dt, eb, (int)newB.size(), mNB, st);
+          if (e == hipSuccess) e = mpsk::launch_mid3(dt, em, (int)mids.size(), mN1, mK1, dd, st);
+          if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("mid: ") + hipGetErrorString(e));
+        }
+        std::vector<int> ql;
+        for (int sb : newB) if (slot[sb].Nt > slot[sb].M) ql.push_back(sb);
+        if (!ql.empty()) {
+          mpsk::Ent* eq = upload_list(LQR2, ents_of(ql));
+          if (!eq) return fail(err, MPS_EDEVICE, "list upload failed");
+          Timed tq(E, 7);
+          e = mpsk::launch_qr(dt, eq, (int)ql.size(), dd, st);
+          if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("qr: ") + hipGetErrorString(e));
+        }
       }
       // a released slot's workspace is reused only by launches queued after the
       // kernels that still read it (one stream)
