@@ -87,6 +87,7 @@ struct Task2 {
   double2* Rh;
   double2* Rh_lo;
   double2* aux1;        // dd handles: N x N scratch (V^H V - I), binary64
+  double2* aux3;        // dd handles: M x N scratch (refinement products), binary64
   double2* aux2;        // dd handles: N x N scratch (V (V^H V - I)), binary64
   double* sig2;         // N: squared column norms of W (from the Jacobi Gram diagonals)
   double* sig2_lo;

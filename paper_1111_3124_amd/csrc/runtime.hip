@@ -22,6 +22,7 @@
 #include "../../include/mps.h"
 #include "common.h"
 #include "dd_kernels.h"
+#include "ddref.h"
 #include "kernels3.h"
 #include "launch.h"
 #include "qr.h"
@@ -91,6 +92,8 @@ struct Engine {
   int max_slots = 32;
   double ws_limit = 16.0 * (1ull << 30);  // batch engines: workspace arena cap, bytes
   double tol_mult = 1.0;
+  bool dd_refine = true;  // dd: simultaneous first-order corrections before any pairwise polish
+  int max_ref_passes = 4;
   double rank_floor = 0x1p-44;
   double rank_floor_dd = 0x1p-96;
   bool timing = false;
@@ -389,7 +392,8 @@ struct GateRef {
 //      the theta of the second split; any other finished slot frees its sites.
 // A slow update never holds back updates that do not depend on it.
 struct Slot {
-  int state = 0;  // 0 free, 1 FP64 Jacobi, 2 dd polish, 3 ready to finalise, 5 reserved
+  int state = 0;  // 0 free, 1 FP64 Jacobi, 2 dd refinement passes, 4 dd pairwise polish,
+                  // 3 ready to finalise, 5 reserved
   int kind = 0;   // 0 two-site, 1 three-site first split, 2 three-site second split
   int gate = -1;
   int partner = -1;  // kind 1: the reserved slot of the second split
@@ -407,7 +411,7 @@ size_t task_ws_bytes(bool dd, int M, int Nt, int t1, bool wide) {
   const int N = wide ? M : Nt, P = dd ? 2 : 1;
   const size_t MN = (size_t)M * Nt, NN = (size_t)N * N;
   size_t b = align_up((2 * MN + NN) * sizeof(double2)) * P;
-  if (dd) b += 2 * align_up(NN * sizeof(double2));
+  if (dd) b += 2 * align_up(NN * sizeof(double2)) + align_up((size_t)M * N * sizeof(double2));
   b += align_up(N * sizeof(double)) * P + align_up(N * sizeof(int));
   b += align_up((size_t)t1 * sizeof(double2)) * P;
   if (wide) {
@@ -445,6 +449,8 @@ void carve(bool dd, Task2& t, char* w, int* d_flags, double* d_stats, double* d_
     w += align_up(NN * sizeof(double2));
     t.aux2 = (double2*)w;
     w += align_up(NN * sizeof(double2));
+    t.aux3 = (double2*)w;
+    w += align_up((size_t)t.M * t.N * sizeof(double2));
   }
   t.sig2 = (double*)w;
   w += align_up(t.N * sizeof(double));
@@ -571,7 +577,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
   const size_t o_u8 = o_dims + align_up(sizeof(int) * dims_total);
   const size_t o_g1 = o_u8 + align_up(sizeof(double2) * 128 * S);
   const size_t o_ents = o_g1 + align_up(sizeof(Task1) * nsites);
-  constexpr int kLists = 11;  // new2, new3, jacobi, dd, dd-enter, final, final3, mid, qr, zform, qr2
+  constexpr int kLists = 13;  // new2, new3, jacobi, dd, dd-enter, final, final3, mid, qr, zform, qr2, ref, polish
   const size_t list_bytes = align_up(sizeof(mpsk::Ent) * S);
   rc = ensure_small(E, o_ents + kLists * list_bytes, err);
   if (rc) return rc;
@@ -585,7 +591,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
   int* hdims = (int*)(E->h_stage + o_dims);
   double2* hu8 = (double2*)(E->h_stage + o_u8);
   double2* du8 = (double2*)(E->d_small + o_u8);
-  enum { LN2 = 0, LN3, LJ, LD, LENTER, LFIN, LFIN3, LMID, LQR, LZF, LQR2 };
+  enum { LN2 = 0, LN3, LJ, LD, LENTER, LFIN, LFIN3, LMID, LQR, LZF, LQR2, LR, LPOL };
   auto hlist = [&](int i) { return E->h_stage + o_ents + i * list_bytes; };
   auto dlist = [&](int i) { return E->d_small + o_ents + i * list_bytes; };
 
@@ -822,12 +828,13 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
       }
     }
     // ---- 2. one sweep for every iterating slot
-    std::vector<int> jl, dl;
+    std::vector<int> jl, rl, dl;
     for (int si : active) {
       if (slot[si].state == 1) jl.push_back(si);
-      if (slot[si].state == 2) dl.push_back(si);
+      if (slot[si].state == 2) rl.push_back(si);
+      if (slot[si].state == 4) dl.push_back(si);
     }
-    if (jl.empty() && dl.empty()) {
+    if (jl.empty() && rl.empty() && dl.empty()) {
       if (active.empty()) {
         if (!remaining) break;
         continue;  // only single-site gates were admitted; admit the rest
@@ -848,6 +855,16 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
         if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("jacobi: ") + hipGetErrorString(e));
       }
     }
+    if (!rl.empty()) {
+      mpsk::Ent* el = upload_list(LR, ents_of(rl));
+      if (!el) return fail(err, MPS_EDEVICE, "list upload failed");
+      int mM = 0, mN = 0;
+      for (int si : rl) { mM = std::max(mM, slot[si].M); mN = std::max(mN, slot[si].N); }
+      Timed tm(E, 6);
+      E->slot_sweeps_dd += (long)rl.size();
+      e = mpsk::launch_ddref_pass(dt, el, (int)rl.size(), mM, mN, E->tol_mult, st);
+      if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("dd refinement: ") + hipGetErrorString(e));
+    }
     if (!dl.empty()) {
       mpsk::Ent* el = upload_list(LD, ents_of(dl));
       if (!el) return fail(err, MPS_EDEVICE, "list upload failed");
@@ -863,7 +880,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
       }
     }
     // ---- 3. convergence
-    if (!jl.empty() || !dl.empty()) {
+    if (!jl.empty() || !rl.empty() || !dl.empty()) {
       HIPCHK(err, hipMemcpyAsync(hflags, d_flags, sizeof(int) * 3 * S, hipMemcpyDeviceToHost, st));
       HIPCHK(err, hipStreamSynchronize(st));
       unsynced = false;
@@ -886,7 +903,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
         sl.fp64_conv = !rot;
         if (dd) {
           enter.push_back(si);
-          sl.state = 2;
+          sl.state = E->dd_refine ? 2 : 4;
           sl.sweep = 0;
         } else {
           sl.conv = sl.fp64_conv;
@@ -894,15 +911,38 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
         }
       }
     }
+    std::vector<int> to_polish;
+    for (int si : rl) {
+      Slot& sl = slot[si];
+      const int code = hflags[3 * si + sl.sweep % 3];
+      ++sl.sweep;
+      if (code == 0) {
+        sl.dd_sweeps = sl.sweep;
+        sl.conv = true;
+        sl.state = 3;
+      } else if ((code & 2) || sl.sweep >= E->max_ref_passes) {
+        sl.dd_sweeps = sl.sweep;
+        sl.state = 4;
+        sl.sweep = 0;
+        to_polish.push_back(si);
+      }
+    }
     for (int si : dl) {
       Slot& sl = slot[si];
       const bool rot = hflags[3 * si + sl.sweep % 3] != 0;
       ++sl.sweep;
       if (!rot || sl.sweep >= E->max_sweeps_dd) {
-        sl.dd_sweeps = sl.sweep;
+        sl.dd_sweeps += sl.sweep;
         sl.conv = !rot;
         sl.state = 3;
       }
+    }
+    if (!to_polish.empty()) {
+      unsynced = true;
+      mpsk::Ent* el = upload_list(LPOL, ents_of(to_polish));
+      if (!el) return fail(err, MPS_EDEVICE, "list upload failed");
+      e = mpsk::launch_flags_clear(dt, el, (int)to_polish.size(), st);
+      if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("flags: ") + hipGetErrorString(e));
     }
     if (!enter.empty()) {
       unsynced = true;
@@ -1101,6 +1141,10 @@ int set_option(Engine* E, int prec, int key, double value, std::string* err) {
     case MPS_OPT_MAX_SLOTS:
       if (!(value >= 1 && value <= 65536)) return fail(err, MPS_EINVAL, "slot limit out of range");
       E->max_slots = (int)value;
+      return MPS_OK;
+    case MPS_OPT_DD_REFINE:
+      if (!(value == 0 || value == 1)) return fail(err, MPS_EINVAL, "dd refinement switch must be 0 or 1");
+      E->dd_refine = value != 0;
       return MPS_OK;
     case MPS_OPT_WORKSPACE_MB:
       if (!(value >= 1 && value <= 1 << 22)) return fail(err, MPS_EINVAL, "workspace limit out of range");
