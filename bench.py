@@ -29,6 +29,9 @@ sys.path.insert(0, ROOT)
 METRIC = "MPS gate updates/s at χ=256: FP64 vs dd-refined, error vs 256-bit oracle"
 N_QUBITS, CHI, EPS, SEED = 40, 256, 1e-12, 2
 PEAK_FP64 = 78.6e12  # MI355X FP64 vector (and matrix) peak, FLOP/s
+PEAK_HBM = 8.0e12    # MI355X HBM3E bandwidth, B/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jacobi_step_chi256_traffic.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_1111_3124_amd", "csrc", "kernels.hip")
 
 
 def jacobi_flops(M: int, N: int) -> float:
@@ -95,19 +98,72 @@ def run_variant(B, W, prec: int, steps: int, warmup: int):
                 slot_sweeps=slot_sweeps, ktimes=ktimes, lam_ok=lam_ok, noconv=rc != 0, steps=steps)
 
 
+def step_bytes(M: int, N: int) -> float:
+    """Memory traffic of one step of one update: every column of W (M x N) and of
+    V (N x N) is read once and written once (complex128)."""
+    return 2.0 * 16.0 * (M * N + N * N)
+
+
+def measured_traffic():
+    """Memory-fabric bytes per update-step of the Jacobi step kernel (N = 512) from the
+    committed rocprofv3 counter summary, or None if there is none or the kernel
+    source changed since the counters were taken."""
+    try:
+        import hashlib
+        text = open(TRAFFIC_FILE).read()
+        kv = dict(l.split(":", 1) for l in text.splitlines()
+                  if l.startswith(("bytes_per_update_step:", "kernels_hip_sha256:")))
+        digest = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        if kv["kernels_hip_sha256"].strip() != digest:
+            return None
+        return float(kv["bytes_per_update_step"].strip())
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def roofline(res):
-    """Dominant kernel: the FP64 Jacobi step.  Algorithmic flops of the timed region
-    = update-sweeps executed x J(512, 512) (the scalar one-sided Jacobi count of one
-    sweep); achieved = that / the step kernels' HIP-event time."""
+    """Dominant kernel: the FP64 Jacobi step (k_jacobi_step<8>).  Per launch it does,
+    for each update it serves, one of the nsteps = N - 1 steps of a sweep: J(M, N) /
+    nsteps flops and step_bytes(M, N) of traffic.  Totals over the timed region:
+    update-sweeps executed x nsteps x those; achieved = total / the step kernels'
+    HIP-event time.  The primary bound is the one the kernel is closer to."""
     ms, launches = res["ktimes"]["jacobi"]
     if launches == 0:
         return None
     M = N = 2 * CHI
+    nsteps = N // 8 - 1
+    sec = ms * 1e-3
     flops = res["slot_sweeps"] * jacobi_flops(M, N)
-    achieved = flops / (ms * 1e-3)
-    return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64, "traffic": None, "kernel": "k_jacobi_step<8>",
-            "avg_launch_us": 1e3 * ms / launches, "launches": launches, "flops_per_launch": flops / launches}
+    nbytes = res["slot_sweeps"] * nsteps * step_bytes(M, N)
+    f_alu = flops / sec / PEAK_FP64
+    f_hbm = nbytes / sec / PEAK_HBM
+    per_step = measured_traffic()
+    # measured bytes per launch: the per-update-step figure x the update-steps one
+    # launch serves on average in the timed region
+    traffic = per_step * (nbytes / launches) / step_bytes(M, N) if per_step else None
+    hbm = {"bound": "hbm", "achieved": nbytes / sec / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": f_hbm,
+           "traffic": traffic, "bytes_per_launch": nbytes / launches}
+    alu = {"bound": "alu", "achieved": flops / sec / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": f_alu,
+           "traffic": traffic, "flops_per_launch": flops / launches}
+    main, other = (hbm, alu) if f_hbm >= f_alu else (alu, hbm)
+    main = dict(main)
+    main.update({"kernel": "k_jacobi_step<8>", "avg_launch_us": 1e3 * ms / launches, "launches": launches,
+                 "other_bound": other})
+    return main
+
+
+def calibrate_copy(mib: int = 256, reps: int = 10):
+    """A plain device-to-device copy of known size (the calibration kernel for the
+    FETCH_SIZE / WRITE_SIZE counters): reads and writes `mib` MiB per dispatch."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "copy", "bytes_read_per_dispatch": mib << 20,
+                      "bytes_written_per_dispatch": mib << 20, "dispatches": reps}), flush=True)
 
 
 def cpu_baseline():
@@ -141,10 +197,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--variants", default="auto", help="fp64, dd, both or auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a device copy of known size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one MI355X: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     from paper_1111_3124_amd import binding as B
     from paper_1111_3124_amd import workloads as W
 

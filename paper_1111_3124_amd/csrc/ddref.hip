@@ -102,7 +102,9 @@ __global__ __launch_bounds__(256) void k_ref_e(Task2* tasks, const Ent* ents, do
     T.aux1[e] = ep;                                        // E_pq
     T.aux1[(long)p * N + q] = cmk(-ep.x, ep.y);            // E_qp = -conj(E_pq)
   }
-  if (code) atomicOr(&T.flags[pass % 3], code);
+  // one flag update per block (the same word is shared by all of the task's blocks)
+  const int c1 = __syncthreads_or(code & 1), c2 = __syncthreads_or(code & 2);
+  if (threadIdx.x == 0 && (c1 || c2)) atomicOr(&T.flags[pass % 3], (c1 ? 1 : 0) | (c2 ? 2 : 0));
 }
 
 __device__ __forceinline__ bool ref_void(const Task2& T, int pass) { return (T.flags[pass % 3] & 2) != 0; }
