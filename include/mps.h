@@ -187,8 +187,7 @@ int mps_sync(mps_handle h);
 /* With MPS_OPT_KERNEL_TIMING on, accumulated device time (ms, from HIP events
  * recorded on the handle's stream around each launch) and launch count of kernel
  * class `cls` (0 theta, 1 jacobi step, 2 truncate, 3 split, 4 single-site gate,
- * 5 amplitude, 6 dd refinement, 7 QR preconditioning of wide thetas and the
- * forming of their Z); reset = 1 clears the counters after reading.
+ * 5 amplitude, 6 dd refinement); reset = 1 clears the counters after reading.
  * cls 8 / 9 are counters (always on): *launches receives the number of
  * update-sweeps executed by the FP64 Jacobi / the dd polish (one update taking
  * one sweep counts 1), *ms receives 0. */

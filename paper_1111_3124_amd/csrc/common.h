@@ -5,9 +5,9 @@
 //                                     ld = capacity of the site's right bond;
 //   theta (M x Nt), column-major, ld = M (compact to the live dims);
 //     2-site rows r = 2*alpha + i (M = 2a), columns col = j*c + gamma (Nt = 2c);
-//   the Jacobi problem W (M x N) with V (N x N), column-major: W = theta_w and N = Nt,
-//     or, for a wide theta (Nt > M), W = R^H (M x M) from theta_w^H = Q R;
-//   Z (Nt x ...), column-major, ld = Nt: the right singular vectors the split uses.
+//   the Jacobi problem W (JM x N) with V (N x N), column-major: W = theta_w (JM = M,
+//     N = Nt), or for a wide theta (Nt > M) W = theta_w^H (JM = Nt, N = M);
+//   Z (Nt x N), column-major, ld = Nt: the right singular vectors the split uses.
 // A double-double handle keeps a second "lo" plane beside every hi array.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -55,8 +55,9 @@ struct Task2 {
   double2* Br_lo;
   int ldl, ldr;         // row lengths of Bl, Br
   int a, b, c;          // live bond dims m_{s-1}, m_s, m_{s+1}
-  int M, N;             // Jacobi problem: M rows, N columns (N = Nt, or M for a wide theta)
-  int Nt;               // theta columns (2c, or 4d for the first split of a three-site gate)
+  int M, Nt;            // theta rows (2a) and columns (2c, or 4d: three-site first split)
+  int JM, N;            // Jacobi problem rows and columns: (M, Nt), or (Nt, M) when tr
+  int tr;               // 1: wide theta, the Jacobi runs on theta_w^H
   const double* lamL;   // V_{s-1}: a values (boundary: a 1)
   const double* lamL_lo;
   double* lamS;         // V_s output slot
@@ -74,18 +75,10 @@ struct Task2 {
   double2* thu_lo;      // dd planes of the above (dd handles)
   double2* thw_lo;
   double2* V_lo;
-  // right factor of the split: Z = V (column perm[nu] is kept column nu), or for a
-  // wide theta Z = Q V_R formed after the truncation (column nu is kept column nu)
+  // right factor of the split (Nt rows; column perm[nu] is the nu-th kept one): V, or
+  // for a wide theta W itself, whose kept columns are scaled to unit norm
   double2* Z;
   double2* Z_lo;
-  int zdirect;          // 1: Z column nu is the nu-th kept column; 0: column perm[nu]
-  // wide theta only: Q (Nt x M, explicit), the reflector scalars, dd R^H (M x M)
-  double2* Qh;
-  double2* Qh_lo;
-  double2* tau;
-  double2* tau_lo;
-  double2* Rh;
-  double2* Rh_lo;
   double2* aux1;        // dd handles: N x N scratch (V^H V - I), binary64
   double2* aux3;        // dd handles: M x N scratch (refinement products), binary64
   double2* aux2;        // dd handles: N x N scratch (V (V^H V - I)), binary64

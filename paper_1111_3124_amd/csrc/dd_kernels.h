@@ -11,6 +11,7 @@ hipError_t launch_theta2_dd(Task2* d_tasks, const Ent* d_ents, int nent, int max
 hipError_t launch_dd_enter(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, int maxN, hipStream_t st);
 hipError_t launch_jacobi_step_dd(Task2* d_tasks, const Ent* d_ents, int nent, int maxN, int step, double tol_mult,
                                  int maxin, hipStream_t st);
+hipError_t launch_znorm_dd(Task2* d_tasks, const Ent* d_ents, int nent, int maxJM, int maxK, hipStream_t st);
 // chi_max and eps are read from each task
 hipError_t launch_truncate_dd(Task2* d_tasks, const Ent* d_ents, int nent, double floor_rel, hipStream_t st);
 hipError_t launch_split_dd(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, int maxN, int maxK, hipStream_t st,

@@ -5,8 +5,7 @@
 //   FP64 block Jacobi on round(theta_w)        [k_jacobi_step<BW> of kernels.hip] -> V0
 //   V <- V (I - E/2), E = V^H V - I, twice     [k_gram_dd + k_ns_fix] (Newton-Schulz step of
 //                                              the polar factor: orthogonality error squares)
-//   W = theta_w V in dd                        [k_wmul_dd]  (W = R^H V_R for a wide theta,
-//                                              whose Householder QR is in qr.hip)
+//   W = theta_w V in dd                        [k_wmul_dd]  (theta_w^H V for a wide theta)
 //   dd block Jacobi polish sweeps on (W, V)    [k_jacobi_step_dd]
 //   sort / truncate / renormalise in dd        [k_truncate_dd]
 //   B_{s+1}' = Z_k^H, B_s' = theta Z_k / nu    [k_split_*_dd]
@@ -68,7 +67,10 @@ struct ThetaOpDD {
           const long idx = (long)(j * t->c + ga) * M + (2 * al + i);
           stc(t->thu, t->thu_lo, idx, v);
           const cdd w = dd::cscale(v, wl);
-          t->thw[idx] = make_double2(w.re.hi, w.im.hi);
+          if (t->tr)
+            t->thw[(long)(2 * al + i) * t->Nt + (j * t->c + ga)] = make_double2(w.re.hi, -w.im.hi);
+          else
+            t->thw[idx] = make_double2(w.re.hi, w.im.hi);
           fro += w.re.hi * w.re.hi + w.im.hi * w.im.hi;
         }
     }
@@ -178,7 +180,11 @@ struct WOpDD {
   static constexpr bool kBColFast = false;
   const Task2* t;
   __device__ cdd a(int row, int kk) const {
-    if (t->Rh) return ldc(t->Rh, t->Rh_lo, (long)kk * t->M + row);  // wide: R^H
+    if (t->tr) {  // theta_w^H: row = theta column, kk = theta row
+      const cdd x = ldc(t->thu, t->thu_lo, (long)row * t->M + kk);
+      const ddr w = {t->lamL[kk >> 1], t->lamL_lo[kk >> 1]};
+      return dd::cconj(dd::cscale(x, w));
+    }
     const cdd x = ldc(t->thu, t->thu_lo, (long)kk * t->M + row);
     const ddr w = {t->lamL[row >> 1], t->lamL_lo[row >> 1]};
     return dd::cscale(x, w);
@@ -190,7 +196,7 @@ struct WOpDD {
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int r = r0 + i, c = c0 + j;
-        if (r < t->M && c < t->N) stc(t->thw, t->thw_lo, (long)c * t->M + r, v[i][j]);
+        if (r < t->JM && c < t->N) stc(t->thw, t->thw_lo, (long)c * t->JM + r, v[i][j]);
       }
   }
 };
@@ -198,9 +204,9 @@ struct WOpDD {
 __global__ __launch_bounds__(256) void k_wmul_dd(Task2* tasks, const Ent* ents) {
   const Task2* t = &tasks[ents[blockIdx.z].slot];
   const int tm = blockIdx.x * 32, tn = blockIdx.y * 32;
-  if (tm >= t->M || tn >= t->N) return;
+  if (tm >= t->JM || tn >= t->N) return;
   WOpDD op{t};
-  ddgemm_tile(op, t->M, t->N, t->N, tm, tn);
+  ddgemm_tile(op, t->JM, t->N, t->N, tm, tn);
 }
 
 // ------------------------------------------------------------------ dd Jacobi step
@@ -258,7 +264,7 @@ __global__ __launch_bounds__(256) void k_jacobi_step_dd(Task2* tasks, const Ent*
   constexpr int BW = 8, W2 = 16, TB = 2, LPT = 64 * W2 / 256;
   const Task2& T = tasks[ents[blockIdx.y].slot];
   const int sweep = ents[blockIdx.y].sweep;
-  const int N = T.N, M = T.M;
+  const int N = T.N, M = T.JM;
   const int nb = (N + BW - 1) / BW;
   const int nbp = nb + (nb & 1);
   const int pi = blockIdx.x;
@@ -453,7 +459,7 @@ __global__ __launch_bounds__(1024) void k_truncate_dd(Task2* tasks, const Ent* e
   Task2& T = tasks[ents[blockIdx.x].slot];
   const int chi = T.chi;
   const double eps = T.eps;
-  const int N = T.N, M = T.M;
+  const int N = T.N, M = T.JM;
   int P = 1;
   while (P < N) P <<= 1;
   __shared__ ddr key[kMaxSort];
@@ -557,7 +563,7 @@ __global__ __launch_bounds__(256) void k_split_right_dd(Task2* tasks, const Ent*
   const int k = *T.dim_out, Nt = T.Nt, c = T.c;
   const int nu = blockIdx.y;
   if (nu >= k) return;
-  const int col = T.zdirect ? nu : T.perm[nu];
+  const int col = T.perm[nu];
   for (int e = blockIdx.x * 256 + threadIdx.x; e < Nt; e += gridDim.x * 256) {
     const int j = e / c, ga = e - j * c;
     const cdd v = dd::cconj(ldc(T.Z, T.Z_lo, (long)col * Nt + e));
@@ -573,7 +579,7 @@ struct SplitLeftOpDD {
   ddr inv_nu;
   __device__ cdd a(int row, int kk) const { return ldc(t->thu, t->thu_lo, (long)kk * t->M + row); }
   __device__ cdd b(int kk, int col) const {
-    return ldc(t->Z, t->Z_lo, (long)(t->zdirect ? col : t->perm[col]) * t->Nt + kk);
+    return ldc(t->Z, t->Z_lo, (long)t->perm[col] * t->Nt + kk);
   }
   __device__ void epilogue(int r0, int c0, cdd (&v)[2][2]) const {
 #pragma unroll
@@ -594,6 +600,19 @@ __global__ __launch_bounds__(256) void k_split_left_dd(Task2* tasks, const Ent* 
   const ddr nu = {t->stats[6], t->stats[7]};
   SplitLeftOpDD op{t, k, dd::div(dd::from(1.0), nu)};
   ddgemm_tile(op, t->M, k, t->Nt, tm, tn);
+}
+
+// wide theta: Z = the kept columns of W scaled to unit norm, in dd
+__global__ __launch_bounds__(256) void k_znorm_dd(Task2* tasks, const Ent* ents) {
+  const Task2& T = tasks[ents[blockIdx.z].slot];
+  const int k = *T.dim_out, nu = blockIdx.y;
+  if (nu >= k) return;
+  const int col = T.perm[nu];
+  const ddr s = dd::div(dd::from(1.0), dd::sqrt(ddr{T.sig2[col], T.sig2_lo[col]}));
+  for (int r = blockIdx.x * 256 + threadIdx.x; r < T.JM; r += gridDim.x * 256) {
+    const long o = (long)col * T.JM + r;
+    stc(T.Z, T.Z_lo, o, dd::cscale(ldc(T.Z, T.Z_lo, o), s));
+  }
 }
 
 // ------------------------------------------------------------------ amplitudes (dd)
@@ -672,6 +691,12 @@ hipError_t launch_jacobi_step_dd(Task2* d_tasks, const Ent* d_ents, int nent, in
   const int nb = (maxN + 7) / 8;
   const int nbp = nb + (nb & 1);
   hipLaunchKernelGGL(k_jacobi_step_dd, dim3(nbp / 2, nent), dim3(256), 0, st, d_tasks, d_ents, step, tol_mult, maxin);
+  MPS_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_znorm_dd(Task2* d_tasks, const Ent* d_ents, int nent, int maxJM, int maxK, hipStream_t st) {
+  hipLaunchKernelGGL(k_znorm_dd, dim3((maxJM + 255) / 256, maxK, nent), dim3(256), 0, st, d_tasks, d_ents);
   MPS_LAUNCH_CHECK();
   return hipSuccess;
 }

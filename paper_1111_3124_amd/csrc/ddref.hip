@@ -2,7 +2,7 @@
 // first-order corrections (gfx950).
 //
 // On entry (after the dd promotion and Newton-Schulz steps) V is unitary to dd
-// precision and W = theta_w V (dd) has nearly orthogonal columns: the off-diagonal
+// precision and W = theta_w V (dd; theta_w^H V for a wide theta) has nearly orthogonal columns: the off-diagonal
 // Gram entries g_pq are ~2^-53 sqrt(g_pp g_qq) (the FP64 Jacobi's stopping point).
 // All pairs are then corrected at once, as in the matrix-multiplication based SVD
 // refinement of Ogita and Aishima (J. Comput. Appl. Math. 369, 2020), in its
@@ -36,8 +36,8 @@ struct WGramOp {
   static constexpr bool kARowFast = false;
   static constexpr bool kBColFast = false;
   const Task2* t;
-  __device__ cdd a(int row, int kk) const { return dd::cconj(ldc(t->thw, t->thw_lo, (long)row * t->M + kk)); }
-  __device__ cdd b(int kk, int col) const { return ldc(t->thw, t->thw_lo, (long)col * t->M + kk); }
+  __device__ cdd a(int row, int kk) const { return dd::cconj(ldc(t->thw, t->thw_lo, (long)row * t->JM + kk)); }
+  __device__ cdd b(int kk, int col) const { return ldc(t->thw, t->thw_lo, (long)col * t->JM + kk); }
   __device__ void epilogue(int r0, int c0, cdd (&v)[2][2]) const {
     const int N = t->N;
 #pragma unroll
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(256) void k_ref_gram(Task2* tasks, const Ent* ents)
   if (tm >= t->N || tn >= t->N || tm > tn) return;  // upper tiles (and the diagonal ones)
   if (tm == 0 && tn == 0 && threadIdx.x == 0) t->flags[(ents[blockIdx.z].sweep + 1) % 3] = 0;
   WGramOp op{t};
-  ddgemm_tile(op, t->N, t->N, t->M, tm, tn);
+  ddgemm_tile(op, t->N, t->N, t->JM, tm, tn);
 }
 
 // E from G; flags[pass % 3] |= 1 while some pair is above the convergence level,
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void k_ref_gram(Task2* tasks, const Ent* ents)
 __global__ __launch_bounds__(256) void k_ref_e(Task2* tasks, const Ent* ents, double tol_mult) {
   const Task2& T = tasks[ents[blockIdx.y].slot];
   const int pass = ents[blockIdx.y].sweep;
-  const int N = T.N, M = T.M;
+  const int N = T.N, M = T.JM;
   const double tol = tol_mult * (double)(M > 16 ? M : 16) * 0x1p-101;
   const double rtol = sqrt(tol / (double)(N > 1 ? N : 1));
   const double ztol = *T.fro2 * 0x1p-192;
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256) void k_ref_mul(Task2* tasks, const Ent* ents, 
   if (ref_void(*t, ents[blockIdx.z].sweep)) return;
   const bool isw = (int)blockIdx.x < wtiles;
   const int tm = (isw ? blockIdx.x : blockIdx.x - wtiles) * 64, tn = blockIdx.y * 64;
-  const int rows = isw ? t->M : t->N;
+  const int rows = isw ? t->JM : t->N;
   if (tm >= rows || tn >= t->N) return;
   RefMulOp op{isw ? t->thw : t->V, t->aux2, isw ? t->aux3 : t->aux1, rows, t->N};
   cgemm_tile(op, rows, t->N, t->N, tm, tn);
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) void k_ref_mul(Task2* tasks, const Ent* ents, 
 // W += aux3, V += aux1 (dd sums), sigma^2 = |W column|^2 in dd: a block per column
 __global__ __launch_bounds__(256) void k_ref_add(Task2* tasks, const Ent* ents) {
   const Task2& T = tasks[ents[blockIdx.y].slot];
-  const int c = blockIdx.x, M = T.M, N = T.N;
+  const int c = blockIdx.x, M = T.JM, N = T.N;
   if (c >= N || ref_void(T, ents[blockIdx.y].sweep)) return;
   const int tid = threadIdx.x;
   cacc s = cacc0();

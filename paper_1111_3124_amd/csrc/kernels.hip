@@ -71,7 +71,10 @@ struct ThetaOp {
             const long idx = (long)(j * c_ + ga) * M + (2 * al + i);
             t->thu[idx] = o;
             const double2 ow = cscale(o, wl);
-            t->thw[idx] = ow;
+            if (t->tr)
+              t->thw[(long)(2 * al + i) * t->Nt + (j * c_ + ga)] = cconj(ow);
+            else
+              t->thw[idx] = ow;
             fro += ow.x * ow.x + ow.y * ow.y;
           }
       }
@@ -164,7 +167,7 @@ __global__ __launch_bounds__(256) void k_jacobi_step(Task2* tasks, const Ent* en
   static_assert(W2 == 8 || W2 == 16 || W2 == 32, "block width");
   const Task2& T = tasks[ents[blockIdx.y].slot];
   const int sweep = ents[blockIdx.y].sweep;
-  const int N = T.N, M = T.M;
+  const int N = T.N, M = T.JM;
   const int nb = (N + BW - 1) / BW;
   const int nbp = nb + (nb & 1);
   const int pi = blockIdx.x;
@@ -385,7 +388,7 @@ __global__ __launch_bounds__(1024) void k_truncate(Task2* tasks, const Ent* ents
   Task2& T = tasks[ents[blockIdx.x].slot];
   const int chi = T.chi;
   const double eps = T.eps;
-  const int N = T.N, M = T.M;
+  const int N = T.N, M = T.JM;
   int P = 1;
   while (P < N) P <<= 1;
   __shared__ double key[kMaxSort];
@@ -486,7 +489,7 @@ __global__ __launch_bounds__(256) void k_split_right(Task2* tasks, const Ent* en
   const int k = *T.dim_out, Nt = T.Nt, c = T.c;
   const int nu = blockIdx.y;
   if (nu >= k) return;
-  const int col = T.zdirect ? nu : T.perm[nu];
+  const int col = T.perm[nu];
   for (int e = blockIdx.x * 256 + threadIdx.x; e < Nt; e += gridDim.x * 256) {
     const int j = e / c, ga = e - j * c;
     T.Br[(long)(2 * nu + j) * T.ldr + ga] = cconj(T.Z[(long)col * Nt + e]);
@@ -502,7 +505,7 @@ struct SplitLeftOp {
   double inv_nu;
   __device__ double2 a(int row, int kk) const { return t->thu[(long)kk * t->M + row]; }
   __device__ double2 b(int kk, int col) const {
-    return t->Z[(long)(t->zdirect ? col : t->perm[col]) * t->Nt + kk];
+    return t->Z[(long)t->perm[col] * t->Nt + kk];
   }
   __device__ void epilogue(int r0, int c0, double2 (&acc)[4][4]) const {
 #pragma unroll
@@ -525,6 +528,21 @@ __global__ __launch_bounds__(256) void k_split_left(Task2* tasks, const Ent* ent
   if (tm >= t->M || tn >= k) return;
   SplitLeftOp op{t, k, 1.0 / t->stats[6]};
   cgemm_tile(op, t->M, k, t->Nt, tm, tn);
+}
+
+// Wide theta: the kept columns of W = theta_w^H V are sigma_j times the right singular
+// vectors of theta_w; scale them to unit norm in place (they are orthogonal to the
+// Jacobi tolerance, which is what the split needs).
+__global__ __launch_bounds__(256) void k_znorm(Task2* tasks, const Ent* ents) {
+  const Task2& T = tasks[ents[blockIdx.z].slot];
+  const int k = *T.dim_out, nu = blockIdx.y;
+  if (nu >= k) return;
+  const int col = T.perm[nu];
+  const double s = 1.0 / sqrt(T.sig2[col]);
+  for (int r = blockIdx.x * 256 + threadIdx.x; r < T.JM; r += gridDim.x * 256) {
+    double2* p = T.Z + (long)col * T.JM + r;
+    *p = cscale(*p, s);
+  }
 }
 
 // ------------------------------------------------------------------ single-site gate
@@ -626,6 +644,12 @@ hipError_t launch_split(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, i
   }
   hipLaunchKernelGGL(k_split_left, dim3((maxM + 63) / 64, (maxK + 63) / 64, nent), dim3(256), 0, st, d_tasks,
                      d_ents);
+  MPS_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_znorm(Task2* d_tasks, const Ent* d_ents, int nent, int maxJM, int maxK, hipStream_t st) {
+  hipLaunchKernelGGL(k_znorm, dim3((maxJM + 255) / 256, maxK, nent), dim3(256), 0, st, d_tasks, d_ents);
   MPS_LAUNCH_CHECK();
   return hipSuccess;
 }

@@ -77,7 +77,10 @@ struct Theta3Op {
           const long idx = (long)(jk * d + de) * M + (2 * al + i);
           t->thu[idx] = v;
           const double2 w = cscale(v, wl);
-          t->thw[idx] = w;
+          if (t->tr)
+            t->thw[(long)(2 * al + i) * t->Nt + (jk * d + de)] = cconj(w);
+          else
+            t->thw[idx] = w;
           fro += w.x * w.x + w.y * w.y;
         }
       }
@@ -111,7 +114,7 @@ __global__ __launch_bounds__(256) void k_mid3(Task2* tasks, const Ent* ents) {
   const int nu = blockIdx.y;
   double fro = 0.0;
   if (nu < k1) {
-    const int col = A.zdirect ? nu : A.perm[nu];
+    const int col = A.perm[nu];
     const double w = A.lamS[nu];
     for (int e = blockIdx.x * 256 + threadIdx.x; e < N1; e += gridDim.x * 256) {
       const int j = e / (2 * d), k = (e / d) & 1, de = e % d;
@@ -119,7 +122,10 @@ __global__ __launch_bounds__(256) void k_mid3(Task2* tasks, const Ent* ents) {
       const long idx = (long)(k * d + de) * M2 + (2 * nu + j);
       Bt.thu[idx] = v;
       const double2 vw = cscale(v, w);
-      Bt.thw[idx] = vw;
+      if (Bt.tr)
+        Bt.thw[(long)(2 * nu + j) * Bt.Nt + (k * d + de)] = cconj(vw);
+      else
+        Bt.thw[idx] = vw;
       fro += vw.x * vw.x + vw.y * vw.y;
     }
   }
@@ -196,7 +202,10 @@ struct Theta3OpDD {
         const long idx = (long)(jk * d + de) * M + (2 * al + i);
         stc(t->thu, t->thu_lo, idx, v);
         const cdd w = dd::cscale(v, wl);
-        t->thw[idx] = make_double2(w.re.hi, w.im.hi);
+        if (t->tr)
+          t->thw[(long)(2 * al + i) * t->Nt + (jk * d + de)] = make_double2(w.re.hi, -w.im.hi);
+        else
+          t->thw[idx] = make_double2(w.re.hi, w.im.hi);
         fro += w.re.hi * w.re.hi + w.im.hi * w.im.hi;
       }
     }
@@ -226,7 +235,7 @@ __global__ __launch_bounds__(256) void k_mid3_dd(Task2* tasks, const Ent* ents) 
   const int nu = blockIdx.y;
   double fro = 0.0;
   if (nu < k1) {
-    const int col = A.zdirect ? nu : A.perm[nu];
+    const int col = A.perm[nu];
     const ddr w = {A.lamS[nu], A.lamS_lo[nu]};
     for (int e = blockIdx.x * 256 + threadIdx.x; e < N1; e += gridDim.x * 256) {
       const int j = e / (2 * d), k = (e / d) & 1, de = e % d;
@@ -234,7 +243,10 @@ __global__ __launch_bounds__(256) void k_mid3_dd(Task2* tasks, const Ent* ents) 
       const long idx = (long)(k * d + de) * M2 + (2 * nu + j);
       stc(Bt.thu, Bt.thu_lo, idx, v);
       const cdd vw = dd::cscale(v, w);
-      Bt.thw[idx] = make_double2(vw.re.hi, vw.im.hi);
+      if (Bt.tr)
+        Bt.thw[(long)(2 * nu + j) * Bt.Nt + (k * d + de)] = make_double2(vw.re.hi, -vw.im.hi);
+      else
+        Bt.thw[idx] = make_double2(vw.re.hi, vw.im.hi);
       fro += vw.re.hi * vw.re.hi + vw.im.hi * vw.im.hi;
     }
   }

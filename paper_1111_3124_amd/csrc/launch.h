@@ -24,6 +24,8 @@ hipError_t launch_truncate(Task2* d_tasks, const Ent* d_ents, int nent, double f
 // right = false: only B_s' (the first split of a three-site gate)
 hipError_t launch_split(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, int maxN, int maxK, hipStream_t st,
                         bool right = true);
+// wide thetas, after the truncation: the kept columns of W scaled to unit norm (Z)
+hipError_t launch_znorm(Task2* d_tasks, const Ent* d_ents, int nent, int maxJM, int maxK, hipStream_t st);
 hipError_t launch_gate1(Task1* d_tasks, int ntask, long maxel, hipStream_t st);
 hipError_t launch_amplitude(const AmpArgs& args, int count, hipStream_t st);
 // *ones[i] = 1.0 for i < n_ones; dims[i] = 1 for i < n_dims (one launch for many states)

@@ -25,7 +25,6 @@
 #include "ddref.h"
 #include "kernels3.h"
 #include "launch.h"
-#include "qr.h"
 
 using mpsk::Task1;
 using mpsk::Task2;
@@ -400,41 +399,37 @@ struct Slot {
   int sweep = 0;
   int fp64_sweeps = 0, dd_sweeps = 0;
   bool fp64_conv = false, conv = false;
-  int M = 0, N = 0, Nt = 0;  // Jacobi rows, Jacobi columns, theta columns
+  int M = 0, Nt = 0, JM = 0, N = 0;  // theta rows and columns, Jacobi rows and columns
   size_t ws_off = 0, ws_len = 0;  // workspace held in the arena
 };
 
-// Workspace of a task with an M x Nt theta: theta and theta_w (later W, and Z for a
-// wide theta), V (N x N, N = Nt or M when wide), the dd scratch, sigma^2, the order,
-// T1 (three-site first split), and for a wide theta Q, tau and (dd) R^H.
-size_t task_ws_bytes(bool dd, int M, int Nt, int t1, bool wide) {
-  const int N = wide ? M : Nt, P = dd ? 2 : 1;
+// Workspace of a task with an M x Nt theta: theta and theta_w (later W; for a wide
+// theta theta_w^H, then Z), V (N x N, N = min(M, Nt)), the dd scratch (two N x N, one
+// M x N), sigma^2, the order and T1 (three-site first split).
+size_t task_ws_bytes(bool dd, int M, int Nt, int t1) {
+  const int N = std::min(M, Nt), P = dd ? 2 : 1;
   const size_t MN = (size_t)M * Nt, NN = (size_t)N * N;
   size_t b = align_up((2 * MN + NN) * sizeof(double2)) * P;
-  if (dd) b += 2 * align_up(NN * sizeof(double2)) + align_up((size_t)M * N * sizeof(double2));
+  if (dd) b += 2 * align_up(NN * sizeof(double2)) + align_up(MN * sizeof(double2));
   b += align_up(N * sizeof(double)) * P + align_up(N * sizeof(int));
   b += align_up((size_t)t1 * sizeof(double2)) * P;
-  if (wide) {
-    b += align_up(MN * sizeof(double2)) * P + align_up((size_t)M * sizeof(double2)) * P;
-    if (dd) b += 2 * align_up((size_t)M * M * sizeof(double2));
-  }
   return b;
 }
 
-// a bound over every task with M <= Mcap and Nt <= Ncap
-size_t task_ws_bound(bool dd, int Mcap, int Ncap, int t1) {
-  return std::max(task_ws_bytes(dd, Mcap, std::min(Mcap, Ncap), t1, false), task_ws_bytes(dd, Mcap, Ncap, t1, true));
-}
+// a bound over every task with M <= Mcap and Nt <= Ncap (task_ws_bytes is monotone)
+size_t task_ws_bound(bool dd, int Mcap, int Ncap, int t1) { return task_ws_bytes(dd, Mcap, Ncap, t1); }
 
-// theta columns; a wide theta (Nt > M) is QR-preconditioned and its Jacobi runs on R^H
+// theta columns; a wide theta (Nt > M) runs its one-sided Jacobi on theta_w^H, whose
+// M columns are independent (theta_w's Nt columns would have to be driven to rank M)
 void set_cols(Task2& t, int Nt) {
   t.Nt = Nt;
-  t.N = Nt > t.M ? t.M : Nt;
+  t.tr = Nt > t.M ? 1 : 0;
+  t.JM = t.tr ? Nt : t.M;
+  t.N = t.tr ? t.M : Nt;
 }
 
 // workspace pointers of a task (shape already set), carved from the region w
 void carve(bool dd, Task2& t, char* w, int* d_flags, double* d_stats, double* d_fro, int slot) {
-  const bool wide = t.Nt > t.M;
   const size_t MN = (size_t)t.M * t.Nt, NN = (size_t)t.N * t.N;
   t.thu = (double2*)w;
   t.thw = t.thu + MN;
@@ -450,7 +445,7 @@ void carve(bool dd, Task2& t, char* w, int* d_flags, double* d_stats, double* d_
     t.aux2 = (double2*)w;
     w += align_up(NN * sizeof(double2));
     t.aux3 = (double2*)w;
-    w += align_up((size_t)t.M * t.N * sizeof(double2));
+    w += align_up(MN * sizeof(double2));
   }
   t.sig2 = (double*)w;
   w += align_up(t.N * sizeof(double));
@@ -469,29 +464,10 @@ void carve(bool dd, Task2& t, char* w, int* d_flags, double* d_stats, double* d_
       w += align_up(t1 * sizeof(double2));
     }
   }
-  t.Z = t.V;
-  t.Z_lo = t.V_lo;
-  t.zdirect = 0;
-  t.Qh = t.Qh_lo = t.tau = t.tau_lo = t.Rh = t.Rh_lo = nullptr;
-  if (wide) {
-    t.Qh = (double2*)w;
-    w += align_up(MN * sizeof(double2));
-    t.tau = (double2*)w;
-    w += align_up((size_t)t.M * sizeof(double2));
-    if (dd) {
-      t.Qh_lo = (double2*)w;
-      w += align_up(MN * sizeof(double2));
-      t.tau_lo = (double2*)w;
-      w += align_up((size_t)t.M * sizeof(double2));
-      t.Rh = (double2*)w;
-      w += align_up((size_t)t.M * t.M * sizeof(double2));
-      t.Rh_lo = (double2*)w;
-      w += align_up((size_t)t.M * t.M * sizeof(double2));
-    }
-    t.Z = t.thw;  // Z (Nt x k) replaces W once the truncation has read sigma
-    t.Z_lo = t.thw_lo;
-    t.zdirect = 1;
-  }
+  // the split's right factor: V, or for a wide theta W itself (its kept columns are
+  // scaled to unit norm after the truncation)
+  t.Z = t.tr ? t.thw : t.V;
+  t.Z_lo = t.tr ? t.thw_lo : t.V_lo;
   t.flags = d_flags + 3 * slot;
   t.stats = d_stats + 8 * slot;
   t.fro2 = d_fro + slot;
@@ -577,7 +553,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
   const size_t o_u8 = o_dims + align_up(sizeof(int) * dims_total);
   const size_t o_g1 = o_u8 + align_up(sizeof(double2) * 128 * S);
   const size_t o_ents = o_g1 + align_up(sizeof(Task1) * nsites);
-  constexpr int kLists = 13;  // new2, new3, jacobi, dd, dd-enter, final, final3, mid, qr, zform, qr2, ref, polish
+  constexpr int kLists = 11;  // new2, new3, jacobi, dd, dd-enter, final, final3, mid, znorm, ref, polish
   const size_t list_bytes = align_up(sizeof(mpsk::Ent) * S);
   rc = ensure_small(E, o_ents + kLists * list_bytes, err);
   if (rc) return rc;
@@ -591,7 +567,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
   int* hdims = (int*)(E->h_stage + o_dims);
   double2* hu8 = (double2*)(E->h_stage + o_u8);
   double2* du8 = (double2*)(E->d_small + o_u8);
-  enum { LN2 = 0, LN3, LJ, LD, LENTER, LFIN, LFIN3, LMID, LQR, LZF, LQR2, LR, LPOL };
+  enum { LN2 = 0, LN3, LJ, LD, LENTER, LFIN, LFIN3, LMID, LZN, LR, LPOL };
   auto hlist = [&](int i) { return E->h_stage + o_ents + i * list_bytes; };
   auto dlist = [&](int i) { return E->d_small + o_ents + i * list_bytes; };
 
@@ -699,11 +675,10 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
         if (free_ && (int)free_list.size() >= (g.k == 3 ? 2 : 1)) {
           size_t off1 = 0, off2 = 0, len1 = 0, len2 = 0;
           if (g.k == 2) {
-            const int M = 2 * h->dimx[s0], Nt = 2 * h->dimx[s0 + 2];
-            len1 = ws_alloc(task_ws_bytes(dd, M, Nt, 0, Nt > M), off1);
+            len1 = ws_alloc(task_ws_bytes(dd, 2 * h->dimx[s0], 2 * h->dimx[s0 + 2], 0), off1);
           } else {
             const int a = h->dimx[s0], c = h->dimx[s0 + 2], d = h->dimx[s0 + 3];
-            len1 = ws_alloc(task_ws_bytes(dd, 2 * a, 4 * d, 4 * a * c, 4 * d > 2 * a), off1);
+            len1 = ws_alloc(task_ws_bytes(dd, 2 * a, 4 * d, 4 * a * c), off1);
             if (len1) {
               len2 = ws_alloc(task_ws_bound(dd, 2 * h->capx[s0 + 1], 2 * d, 0), off2);
               if (!len2) {
@@ -759,6 +734,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
             sl.M = t.M;
             sl.N = t.N;
             sl.Nt = t.Nt;
+            sl.JM = t.JM;
             active.push_back(si);
             for (int q = g.first; q < g.first + g.k; ++q) busy[sb0 + q] = 1;
             done[gi] = 1;
@@ -816,16 +792,6 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
         }
         if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("theta: ") + hipGetErrorString(e));
       }
-      std::vector<int> ql;
-      for (int si : new2) if (slot[si].Nt > slot[si].M) ql.push_back(si);
-      for (int si : new3) if (slot[si].Nt > slot[si].M) ql.push_back(si);
-      if (!ql.empty()) {
-        mpsk::Ent* el = upload_list(LQR, ents_of(ql));
-        if (!el) return fail(err, MPS_EDEVICE, "list upload failed");
-        Timed tq(E, 7);
-        e = mpsk::launch_qr(dt, el, (int)ql.size(), dd, st);
-        if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("qr: ") + hipGetErrorString(e));
-      }
     }
     // ---- 2. one sweep for every iterating slot
     std::vector<int> jl, rl, dl;
@@ -859,7 +825,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
       mpsk::Ent* el = upload_list(LR, ents_of(rl));
       if (!el) return fail(err, MPS_EDEVICE, "list upload failed");
       int mM = 0, mN = 0;
-      for (int si : rl) { mM = std::max(mM, slot[si].M); mN = std::max(mN, slot[si].N); }
+      for (int si : rl) { mM = std::max(mM, slot[si].JM); mN = std::max(mN, slot[si].N); }
       Timed tm(E, 6);
       E->slot_sweeps_dd += (long)rl.size();
       e = mpsk::launch_ddref_pass(dt, el, (int)rl.size(), mM, mN, E->tol_mult, st);
@@ -949,7 +915,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
       mpsk::Ent* el = upload_list(LENTER, ents_of(enter));
       if (!el) return fail(err, MPS_EDEVICE, "list upload failed");
       int mM = 0, mN = 0;
-      for (int si : enter) { mM = std::max(mM, slot[si].M); mN = std::max(mN, slot[si].N); }
+      for (int si : enter) { mM = std::max(mM, slot[si].JM); mN = std::max(mN, slot[si].N); }
       Timed tm(E, 6);
       e = mpsk::launch_dd_enter(dt, el, (int)enter.size(), mM, mN, st);
       if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("dd enter: ") + hipGetErrorString(e));
@@ -972,19 +938,20 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
       }
       {
         std::vector<int> zl;
-        int zNt = 0, zK = 1;
+        int zJM = 0, zK = 1;
         for (int si : fl)
-          if (slot[si].Nt > slot[si].M) {
+          if (ht[si].tr) {
             zl.push_back(si);
-            zNt = std::max(zNt, slot[si].Nt);
-            zK = std::max(zK, std::min(ht[si].chi, slot[si].M));
+            zJM = std::max(zJM, ht[si].JM);
+            zK = std::max(zK, std::min(ht[si].chi, ht[si].N));
           }
         if (!zl.empty()) {
-          mpsk::Ent* ez = upload_list(LZF, ents_of(zl));
+          mpsk::Ent* ez = upload_list(LZN, ents_of(zl));
           if (!ez) return fail(err, MPS_EDEVICE, "list upload failed");
-          Timed tz(E, 7);
-          e = mpsk::launch_zform(dt, ez, (int)zl.size(), zNt, zK, dd, st);
-          if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("zform: ") + hipGetErrorString(e));
+          Timed tz(E, 3);
+          e = dd ? mpsk::launch_znorm_dd(dt, ez, (int)zl.size(), zJM, zK, st)
+                 : mpsk::launch_znorm(dt, ez, (int)zl.size(), zJM, zK, st);
+          if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("znorm: ") + hipGetErrorString(e));
         }
       }
       {
@@ -1029,6 +996,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
         sbl.M = tb.M;
         sbl.N = tb.N;
         sbl.Nt = tb.Nt;
+        sbl.JM = tb.JM;
         gsweeps[sa.gate] = sa.fp64_sweeps;
         gdd[sa.gate] = sa.dd_sweeps;
         if (!sa.conv) status = MPS_ENOCONV;
@@ -1049,15 +1017,6 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
           e = mpsk::launch_prep2(dt, eb, (int)newB.size(), mNB, st);
           if (e == hipSuccess) e = mpsk::launch_mid3(dt, em, (int)mids.size(), mN1, mK1, dd, st);
           if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("mid: ") + hipGetErrorString(e));
-        }
-        std::vector<int> ql;
-        for (int sb : newB) if (slot[sb].Nt > slot[sb].M) ql.push_back(sb);
-        if (!ql.empty()) {
-          mpsk::Ent* eq = upload_list(LQR2, ents_of(ql));
-          if (!eq) return fail(err, MPS_EDEVICE, "list upload failed");
-          Timed tq(E, 7);
-          e = mpsk::launch_qr(dt, eq, (int)ql.size(), dd, st);
-          if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("qr: ") + hipGetErrorString(e));
         }
       }
       // a released slot's workspace is reused only by launches queued after the
