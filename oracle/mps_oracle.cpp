@@ -33,9 +33,14 @@
 // paper's own MPS example), round-to-nearest.  Inputs arrive as binary64 or as
 // exact double-double pairs; outputs leave as (hi, lo) pairs.
 //
-// Parity pins (the tests in tests/test_oracle_*.py): the paper's 3-qubit example,
-// GHZ and QFT closed forms, a dense state vector for <= 12 qubits, SVD identities
-// checked outside this file, Eckart-Young, and the invariants sum lambda^2 = 1.
+//  * Reduced density operators (Section 3.2's RDO_block / RDO(list)): the partial
+//    trace of |Psi><Psi| over the unlisted qubits, contracted site by site.
+//
+// Parity pins (the tests in tests/test_oracle_*.py): the paper's 3-qubit example
+// (amplitudes and its printed RDOs), GHZ and QFT closed forms, a dense state vector
+// for <= 12 qubits, SVD identities checked outside this file, Eckart-Young, the
+// invariants sum lambda^2 = 1, and RDOs against a textbook partial trace, product
+// and GHZ closed forms and Tr rho = 1.
 
 #include <mpfr.h>
 #include <omp.h>
@@ -113,6 +118,15 @@ void cfma(Cx& z, const Cx& x, const Cx& y, Scratch& s) {
   mpfr_sub(z.re.v, z.re.v, s.t[0].v, RN);
   mpfr_fma(z.im.v, x.re.v, y.im.v, z.im.v, RN);
   mpfr_fma(z.im.v, x.im.v, y.re.v, z.im.v, RN);
+}
+
+// z += x * conj(y)  (complex)
+void cfma_cj(Cx& z, const Cx& x, const Cx& y, Scratch& s) {
+  mpfr_fma(z.re.v, x.re.v, y.re.v, z.re.v, RN);
+  mpfr_fma(z.re.v, x.im.v, y.im.v, z.re.v, RN);
+  mpfr_fma(z.im.v, x.im.v, y.re.v, z.im.v, RN);
+  mpfr_mul(s.t[0].v, x.re.v, y.im.v, RN);
+  mpfr_sub(z.im.v, z.im.v, s.t[0].v, RN);
 }
 
 // z = x * y (complex), z distinct from x and y
@@ -859,6 +873,101 @@ int osvd(int M, int N, const double* a_hi, const double* a_lo, int prec,
     }
   }
   return r.converged ? r.sweeps : -5;
+}
+
+// Reduced density operator rho = Tr_{other qubits} |Psi><Psi| of the listed qubits
+// (Section 3.2: RDO(list); RDO_block(a, b) is the list a..b), straight from the
+// definition: |Psi><Psi| of Eq. (1) is contracted site by site from the left,
+//   env[(I, I')][beta][beta'] = sum over all indices left of the cut, except the
+//                               listed ones (I, I'), of c(.., beta) conj(c(.., beta')),
+// with the site matrices M_s[i] = Q_s[i] V_s (V_{n-1} = [1]).  A listed site opens a
+// pair (i, i'), any other site is traced (i = i').  No canonical form is assumed.
+// out: 2^L x 2^L, row-major, 4 doubles per entry (re_hi, re_lo, im_hi, im_lo); the
+// row index is sum_t i_{q[t]} 2^{L-1-t} for the qubits in the order given.
+int omps_rdo(void* h, int L, const int* q, double* out) {
+  Mps* m = (Mps*)h;
+  if (!m || !q || !out || L < 1 || L > 10) return -1;
+  const int n = m->n;
+  std::vector<char> listed(n, 0);
+  for (int t = 0; t < L; ++t) {
+    if (q[t] < 0 || q[t] >= n || listed[q[t]]) return -1;
+    listed[q[t]] = 1;
+  }
+  g_prec = m->prec;
+  Re one; mpfr_set_ui(one.v, 1, RN);
+  int l = 0, mcur = 1;  // listed qubits opened so far, current bond dim
+  std::vector<CVec> env(1, CVec(1));
+  mpfr_set_ui(env[0][0].re.v, 1, RN);
+  for (int s = 0; s < n; ++s) {
+    Site& S = m->site[s];
+    const int ml = S.ml, mr = S.mr;
+    // M_s[i] = Q_s[i] V_s
+    CVec M((size_t)ml * 2 * mr);
+    for (int al = 0; al < ml; ++al)
+      for (int i = 0; i < 2; ++i)
+        for (int be = 0; be < mr; ++be) {
+          const Re& lv = lam_at(*m, s, be, one);
+          Cx& x = M[((size_t)al * 2 + i) * mr + be];
+          mpfr_mul(x.re.v, S.at(al, i, be).re.v, lv.v, RN);
+          mpfr_mul(x.im.v, S.at(al, i, be).im.v, lv.v, RN);
+        }
+    auto Mat = [&](int al, int i, int be) -> const Cx& { return M[((size_t)al * 2 + i) * mr + be]; };
+    const int D = (int)env.size();
+    const bool open = listed[s] != 0;
+    const int Dn = open ? 4 * D : D;
+    std::vector<CVec> nenv(Dn, CVec((size_t)mr * mr));
+    // F[d][i][al'][be] = sum_al env[d][al][al'] M[al][i][be]
+    std::vector<CVec> F(D, CVec((size_t)2 * ml * mr));
+#pragma omp parallel for collapse(2) schedule(dynamic, 1) if (D * ml * mr > 256)
+    for (int d = 0; d < D; ++d)
+      for (int ap = 0; ap < ml; ++ap) {
+        Scratch sc;
+        for (int i = 0; i < 2; ++i)
+          for (int be = 0; be < mr; ++be) {
+            Cx& f = F[d][((size_t)i * ml + ap) * mr + be];
+            for (int al = 0; al < ml; ++al) cfma(f, env[d][(size_t)al * mcur + ap], Mat(al, i, be), sc);
+          }
+      }
+    // env'[..][be][be'] = sum_al' F[d][i][al'][be] conj(M[al'][i'][be'])
+#pragma omp parallel for collapse(2) schedule(dynamic, 1) if (D * mr * mr > 256)
+    for (int d = 0; d < D; ++d)
+      for (int be = 0; be < mr; ++be) {
+        Scratch sc;
+        const int I = d >> l, Ip = d & ((1 << l) - 1);
+        for (int bp = 0; bp < mr; ++bp)
+          for (int i = 0; i < 2; ++i)
+            for (int ip = 0; ip < 2; ++ip) {
+              if (!open && ip != i) continue;
+              const int dn = open ? ((2 * I + i) << (l + 1)) + (2 * Ip + ip) : d;
+              Cx& e = nenv[dn][(size_t)be * mr + bp];
+              for (int ap = 0; ap < ml; ++ap) cfma_cj(e, F[d][((size_t)i * ml + ap) * mr + be], Mat(ap, ip, bp), sc);
+            }
+      }
+    env = std::move(nenv);
+    mcur = mr;
+    if (open) ++l;
+  }
+  // sorted order of the listed qubits -> the requested order
+  std::vector<int> sorted;
+  for (int s = 0; s < n; ++s)
+    if (listed[s]) sorted.push_back(s);
+  std::vector<int> pos(L);  // bit position (from the MSB) of q[t] in the sorted index
+  for (int t = 0; t < L; ++t)
+    pos[t] = (int)(std::find(sorted.begin(), sorted.end(), q[t]) - sorted.begin());
+  const int dim = 1 << L;
+  for (int r = 0; r < dim; ++r)
+    for (int c = 0; c < dim; ++c) {
+      int rs = 0, cs = 0;
+      for (int t = 0; t < L; ++t) {
+        rs |= ((r >> (L - 1 - t)) & 1) << (L - 1 - pos[t]);
+        cs |= ((c >> (L - 1 - t)) & 1) << (L - 1 - pos[t]);
+      }
+      const Cx& v = env[((size_t)rs << L) + cs][0];
+      double* o = out + 4 * ((size_t)r * dim + c);
+      get_d2(v.re.v, &o[0], &o[1]);
+      get_d2(v.im.v, &o[2], &o[3]);
+    }
+  return 0;
 }
 
 // Dense state vector of n qubits at `prec` bits, |0...0>.  Basis index

@@ -42,6 +42,7 @@ def _load():
     L.osv_destroy.argtypes = [C.c_void_p]
     L.osv_apply.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int), dp, dp]
     L.osv_amplitudes.argtypes = [C.c_void_p, dp]
+    L.omps_rdo.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int), dp]
     L.oracle_threads.restype = C.c_int
     _lib = L
     return L
@@ -131,6 +132,17 @@ class OracleMPS:
         for i, b in enumerate(bits_2d):
             hi[i], lo[i] = self.amplitude(b)
         return hi, lo
+
+    def rdo(self, qubits):
+        """Reduced density operator of `qubits` (in the order given: the first is the
+        most significant bit of the basis index), as (hi, lo) complex 2^L x 2^L arrays."""
+        L = len(qubits)
+        q = (C.c_int * L)(*[int(x) for x in qubits])
+        out = np.zeros(4 << (2 * L))
+        if _load().omps_rdo(self._h, L, q, _dp(out)) != 0:
+            raise ValueError("bad qubit list")
+        o = out.reshape(1 << L, 1 << L, 4)
+        return o[..., 0] + 1j * o[..., 2], o[..., 1] + 1j * o[..., 3]
 
     def last_stats(self) -> list[dict]:
         out = np.zeros(18)
