@@ -160,6 +160,25 @@ int mps_amplitude_dd(mps_handle h, const unsigned char* bits, double out[4]);
  * 2 doubles per amplitude (FP64 handle) or 4 (dd handle: re_hi, re_lo, im_hi, im_lo). */
 int mps_amplitudes(mps_handle h, int count, const unsigned char* bits, double* out);
 
+/* Reduced density operator (paper, Section 3.2: RDO(list)) of `count` distinct
+ * qubits q[0..count-1], 1 <= count <= 7: rho = Tr over every other qubit of
+ * |Psi><Psi|, contracted exactly from the site tensors (no canonical form assumed;
+ * for a normalised state Tr rho = 1).  rho is 2^count x 2^count complex, row-major,
+ * interleaved (re, im): rho[r][c] = <r|rho|c> with r = sum_t i_{q[t]} 2^{count-1-t}
+ * (q[0] is the most significant bit), 2 * 4^count doubles.  On a dd handle mps_rdo
+ * returns hi + lo rounded to binary64.
+ * Errors: MPS_EINVAL (count out of range, a qubit out of range or repeated, NULL),
+ * MPS_ERANGE (the contraction needs more device memory than the workspace cap:
+ * about 4^count x 16 bytes per element of a bond's m x m). */
+int mps_rdo(mps_handle h, int count, const int* q, double* rho);
+
+/* Double-double RDO: rho = rho_hi + rho_lo (same layout each; rho_lo may be NULL).
+ * On an FP64 handle rho_lo receives zeros. */
+int mps_rdo_dd(mps_handle h, int count, const int* q, double* rho_hi, double* rho_lo);
+
+/* RDO_block(first, last) of the paper: the RDO of qubits first, first+1, ..., last. */
+int mps_rdo_block(mps_handle h, int first, int last, double* rho);
+
 /* Diagnostics of the last split. */
 int mps_stats(mps_handle h, struct mps_update_stats* s);
 
@@ -187,7 +206,8 @@ int mps_sync(mps_handle h);
 /* With MPS_OPT_KERNEL_TIMING on, accumulated device time (ms, from HIP events
  * recorded on the handle's stream around each launch) and launch count of kernel
  * class `cls` (0 theta, 1 jacobi step, 2 truncate, 3 split, 4 single-site gate,
- * 5 amplitude, 6 dd refinement); reset = 1 clears the counters after reading.
+ * 5 amplitude, 6 dd refinement, 7 reduced density operators); reset = 1 clears the
+ * counters after reading.
  * cls 8 / 9 are counters (always on): *launches receives the number of
  * update-sweeps executed by the FP64 Jacobi / the dd polish (one update taking
  * one sweep counts 1), *ms receives 0. */

@@ -26,7 +26,7 @@ MPS_PREC_FP64, MPS_PREC_DD = 0, 1
 MPS_OPT_MAX_SWEEPS, MPS_OPT_JACOBI_TOL, MPS_OPT_KERNEL_TIMING, MPS_OPT_RANK_FLOOR = 1, 2, 3, 4
 MPS_OPT_BLOCK_WIDTH, MPS_OPT_MAX_INNER, MPS_OPT_MAX_SLOTS, MPS_OPT_WORKSPACE_MB = 5, 6, 7, 8
 MPS_OPT_DD_REFINE = 9
-KERNEL_CLASSES = ["theta", "jacobi", "truncate", "split", "gate1", "amplitude", "dd_refine"]
+KERNEL_CLASSES = ["theta", "jacobi", "truncate", "split", "gate1", "amplitude", "dd_refine", "rdo"]
 COUNTER_SWEEPS, COUNTER_SWEEPS_DD = 8, 9
 
 _STATUS = {0: "MPS_OK", -1: "MPS_EINVAL", -2: "MPS_ERANGE", -3: "MPS_ENOMEM", -4: "MPS_EDEVICE",
@@ -70,6 +70,9 @@ _lib.mps_kernel_time.argtypes = [_h, C.c_int, _dp, C.POINTER(C.c_long), C.c_int]
 _lib.mps_last_error.restype = C.c_char_p
 _lib.mps_last_error.argtypes = [_h]
 _lib.mps_version.restype = C.c_char_p
+_lib.mps_rdo.argtypes = [_h, C.c_int, C.POINTER(C.c_int), _dp]
+_lib.mps_rdo_dd.argtypes = [_h, C.c_int, C.POINTER(C.c_int), _dp, _dp]
+_lib.mps_rdo_block.argtypes = [_h, C.c_int, C.c_int, _dp]
 _b = C.c_void_p
 _ip = C.POINTER(C.c_int)
 _lib.mps_batch_create.restype = _b
@@ -86,7 +89,7 @@ EXPORTED = ["mps_create", "mps_create_ex", "mps_destroy", "mps_apply_gate", "mps
             "mps_apply_gates", "mps_bond_dim", "mps_schmidt", "mps_schmidt_dd", "mps_amplitude",
             "mps_amplitude_dd", "mps_amplitudes", "mps_stats", "mps_load", "mps_get_site",
             "mps_set_option", "mps_sync", "mps_kernel_time", "mps_last_error", "mps_version",
-            "mps_batch_create", "mps_batch_run", "mps_batch_get", "mps_batch_set_option",
+            "mps_rdo", "mps_rdo_dd", "mps_rdo_block", "mps_batch_create", "mps_batch_run", "mps_batch_get", "mps_batch_set_option",
             "mps_batch_last_error", "mps_batch_destroy"]
 
 
@@ -217,6 +220,30 @@ def mps_amplitudes(h, bits_2d, dd: bool = False):
         return o[:, 0] + 1j * o[:, 2], o[:, 1] + 1j * o[:, 3]
     o = out.reshape(count, 2)
     return o[:, 0] + 1j * o[:, 1]
+
+
+def mps_rdo(h, qubits):
+    """Reduced density operator of `qubits` (the first is the most significant bit)."""
+    L = len(qubits)
+    q = (C.c_int * L)(*[int(x) for x in qubits])
+    out = np.zeros(2 << (2 * L))
+    _check(h, _lib.mps_rdo(h, L, q, _ptr(out)))
+    return out.view(np.complex128).reshape(1 << L, 1 << L)
+
+
+def mps_rdo_dd(h, qubits):
+    L = len(qubits)
+    q = (C.c_int * L)(*[int(x) for x in qubits])
+    hi, lo = np.zeros(2 << (2 * L)), np.zeros(2 << (2 * L))
+    _check(h, _lib.mps_rdo_dd(h, L, q, _ptr(hi), _ptr(lo)))
+    return (hi.view(np.complex128).reshape(1 << L, 1 << L), lo.view(np.complex128).reshape(1 << L, 1 << L))
+
+
+def mps_rdo_block(h, first: int, last: int):
+    L = last - first + 1
+    out = np.zeros(2 << (2 * max(L, 0)))
+    _check(h, _lib.mps_rdo_block(h, first, last, _ptr(out)))
+    return out.view(np.complex128).reshape(1 << L, 1 << L)
 
 
 def mps_stats(h) -> dict:
@@ -378,6 +405,12 @@ class MPS:
 
     def stats(self):
         return mps_stats(self.h)
+
+    def rdo(self, qubits, dd=False):
+        return mps_rdo_dd(self.h, qubits) if dd else mps_rdo(self.h, qubits)
+
+    def rdo_block(self, first, last):
+        return mps_rdo_block(self.h, first, last)
 
     def load(self, B, lam, B_lo=None, lam_lo=None):
         return mps_load(self.h, B, lam, B_lo, lam_lo)

@@ -25,6 +25,7 @@
 #include "ddref.h"
 #include "kernels3.h"
 #include "launch.h"
+#include "rdo.h"
 
 using mpsk::Task1;
 using mpsk::Task2;
@@ -1296,6 +1297,150 @@ int mps_amplitude_dd(mps_handle h, const unsigned char* bits, double out[4]) {
     return MPS_OK;
   }
   return mps_amplitudes(h, 1, bits, out);
+}
+
+int mps_rdo_dd(mps_handle h, int count, const int* qubits, double* rho_hi, double* rho_lo) {
+  if (!h || !qubits || !rho_hi) return MPS_EINVAL;
+  const int n = h->n;
+  if (count < 1 || count > 7) return fail(h, MPS_EINVAL, "rdo: count must be 1..7");
+  std::vector<char> listed(n, 0);
+  for (int t = 0; t < count; ++t) {
+    if (qubits[t] < 0 || qubits[t] >= n) return fail(h, MPS_EINVAL, "rdo: qubit out of range");
+    if (listed[qubits[t]]) return fail(h, MPS_EINVAL, "rdo: repeated qubit");
+    listed[qubits[t]] = 1;
+  }
+  Engine* E = h->E;
+  const bool dd = h->prec == MPS_PREC_DD;
+  int s1 = 0;
+  for (int s = 0; s < n; ++s)
+    if (listed[s]) s1 = s;
+  // sizes: left environments (D blocks of m x m), F, right environments, rho
+  size_t maxE = 1, maxF = 1, maxR = 1;
+  long D = 1;
+  for (int s = 0; s <= s1; ++s) {
+    const size_t ml = h->dimx[s], mr = h->dimx[s + 1];
+    maxE = std::max(maxE, (size_t)D * ml * ml);
+    maxF = std::max(maxF, (size_t)D * 2 * ml * mr);
+    if (listed[s]) D *= 4;
+    maxE = std::max(maxE, (size_t)D * mr * mr);
+  }
+  for (int s = n - 1; s > s1; --s) {
+    const size_t ml = h->dimx[s], mr = h->dimx[s + 1];
+    maxR = std::max(maxR, std::max(ml * ml, mr * mr));
+    maxF = std::max(maxF, 2 * ml * mr);
+  }
+  maxR = std::max(maxR, (size_t)h->dimx[s1 + 1] * h->dimx[s1 + 1]);
+  const size_t P = dd ? 2 : 1;
+  const size_t oA = 0, oB = oA + align_up(maxE * 16) * P, oF = oB + align_up(maxE * 16) * P;
+  const size_t oR1 = oF + align_up(maxF * 16) * P, oR2 = oR1 + align_up(maxR * 16) * P;
+  const size_t oRho = oR2 + align_up(maxR * 16) * P, total = oRho + align_up((size_t)D * 16) * P;
+  if ((double)total > E->ws_limit) return fail(h, MPS_ERANGE, "rdo: the contraction needs more than the workspace cap");
+  int rc = ensure_ws(E, total, &h->err);
+  if (rc) return rc;
+  char* w = E->ws;
+  auto hi = [&](size_t o) { return (double2*)(w + o); };
+  auto lo = [&](size_t o, size_t elems) { return dd ? (double2*)(w + o + align_up(elems * 16)) : nullptr; };
+  hipStream_t st = E->stream;
+  hipError_t e = hipSuccess;
+  {
+    Timed tm(E, 7);
+    // right environment R = 1 (1 x 1) at the right end, then sites n-1 .. s1+1
+    const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
+    HIPCHK(h, hipMemcpyAsync(hi(oR1), &one, 16, hipMemcpyHostToDevice, st));
+    if (dd) HIPCHK(h, hipMemcpyAsync(lo(oR1, maxR), &zero, 16, hipMemcpyHostToDevice, st));
+    size_t rc_ = oR1, rn = oR2;
+    for (int s = n - 1; s > s1 && e == hipSuccess; --s) {
+      mpsk::RdoStep p{};
+      p.B = h->B[s];
+      p.Blo = dd ? h->Blo[s] : nullptr;
+      p.ld = h->capx[s + 1];
+      p.ml = h->dimx[s];
+      p.mr = h->dimx[s + 1];
+      p.E = hi(rc_); p.Elo = lo(rc_, maxR);
+      p.F = hi(oF); p.Flo = lo(oF, maxF);
+      p.En = hi(rn); p.Enlo = lo(rn, maxR);
+      e = mpsk::launch_rdo_right(p, dd, st);
+      std::swap(rc_, rn);
+    }
+    // left environment E = 1 at the left end, then sites 0 .. s1
+    HIPCHK(h, hipMemcpyAsync(hi(oA), &one, 16, hipMemcpyHostToDevice, st));
+    if (dd) HIPCHK(h, hipMemcpyAsync(lo(oA, maxE), &zero, 16, hipMemcpyHostToDevice, st));
+    size_t ec = oA, en = oB;
+    long Dc = 1;
+    int l = 0;
+    for (int s = 0; s <= s1 && e == hipSuccess; ++s) {
+      mpsk::RdoStep p{};
+      p.B = h->B[s];
+      p.Blo = dd ? h->Blo[s] : nullptr;
+      p.ld = h->capx[s + 1];
+      p.ml = h->dimx[s];
+      p.mr = h->dimx[s + 1];
+      p.l = l;
+      p.E = hi(ec); p.Elo = lo(ec, maxE);
+      p.F = hi(oF); p.Flo = lo(oF, maxF);
+      p.En = hi(en); p.Enlo = lo(en, maxE);
+      e = mpsk::launch_rdo_left(p, (int)Dc, listed[s] != 0, dd, st);
+      if (listed[s]) { Dc *= 4; ++l; }
+      std::swap(ec, en);
+    }
+    if (e == hipSuccess) {
+      mpsk::RdoStep p{};
+      p.mr = h->dimx[s1 + 1];
+      p.E = hi(ec); p.Elo = lo(ec, maxE);
+      p.F = hi(rc_); p.Flo = lo(rc_, maxR);
+      p.En = hi(oRho); p.Enlo = lo(oRho, (size_t)D);
+      e = mpsk::launch_rdo_final(p, (int)Dc, dd, st);
+    }
+  }
+  if (e != hipSuccess) return fail(h, MPS_EDEVICE, std::string("rdo: ") + hipGetErrorString(e));
+  std::vector<double2> rh(D), rl(dd ? D : 0);
+  HIPCHK(h, hipMemcpyAsync(rh.data(), hi(oRho), D * 16, hipMemcpyDeviceToHost, st));
+  if (dd) HIPCHK(h, hipMemcpyAsync(rl.data(), lo(oRho, (size_t)D), D * 16, hipMemcpyDeviceToHost, st));
+  HIPCHK(h, hipStreamSynchronize(st));
+  harvest_timing(E);
+  // ascending-site order of the contraction -> the order the caller listed
+  std::vector<int> sorted;
+  for (int s = 0; s < n; ++s)
+    if (listed[s]) sorted.push_back(s);
+  std::vector<int> pos(count);
+  for (int t = 0; t < count; ++t)
+    pos[t] = (int)(std::find(sorted.begin(), sorted.end(), qubits[t]) - sorted.begin());
+  const int dim = 1 << count;
+  for (int r = 0; r < dim; ++r)
+    for (int c = 0; c < dim; ++c) {
+      int rs = 0, cs = 0;
+      for (int t = 0; t < count; ++t) {
+        rs |= ((r >> (count - 1 - t)) & 1) << (count - 1 - pos[t]);
+        cs |= ((c >> (count - 1 - t)) & 1) << (count - 1 - pos[t]);
+      }
+      const size_t src = ((size_t)rs << count) + cs, dst = (size_t)r * dim + c;
+      rho_hi[2 * dst] = rh[src].x;
+      rho_hi[2 * dst + 1] = rh[src].y;
+      if (rho_lo) {
+        rho_lo[2 * dst] = dd ? rl[src].x : 0.0;
+        rho_lo[2 * dst + 1] = dd ? rl[src].y : 0.0;
+      }
+    }
+  return MPS_OK;
+}
+
+int mps_rdo(mps_handle h, int count, const int* qubits, double* rho) {
+  if (!h || !rho) return MPS_EINVAL;
+  if (h->prec != MPS_PREC_DD) return mps_rdo_dd(h, count, qubits, rho, nullptr);
+  const int dim = (count >= 1 && count <= 7) ? 1 << count : 1;
+  std::vector<double> lo((size_t)2 * dim * dim);
+  int rc = mps_rdo_dd(h, count, qubits, rho, lo.data());
+  if (rc) return rc;
+  for (size_t i = 0; i < lo.size(); ++i) rho[i] += lo[i];
+  return MPS_OK;
+}
+
+int mps_rdo_block(mps_handle h, int first, int last, double* rho) {
+  if (!h) return MPS_EINVAL;
+  if (first < 0 || last < first || last >= h->n) return fail(h, MPS_EINVAL, "rdo_block: need 0 <= first <= last < n");
+  std::vector<int> q;
+  for (int s = first; s <= last; ++s) q.push_back(s);
+  return mps_rdo(h, (int)q.size(), q.data(), rho);
 }
 
 int mps_stats(mps_handle h, mps_update_stats* s) {
