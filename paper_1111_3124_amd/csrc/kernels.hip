@@ -103,15 +103,17 @@ __global__ __launch_bounds__(256) void k_theta2(Task2* tasks, const Ent* ents) {
 // One step of the block one-sided Jacobi sweep.  Columns are grouped in blocks of
 // BW; the blocks are paired by the round-robin ("circle") schedule, so that the
 // 2*BW-column groups of one step are disjoint and all block pairs meet once per
-// sweep.  Each 256-thread block takes one pair of one task:
+// sweep.  Each 512-thread block takes one pair of one task:
 //   1. G = A_P^H A_P (W2 x W2, W2 = 2 BW) from the pair's columns A_P of W: row chunks
-//      staged in LDS, each wavefront a quarter of the rows, each lane a TB x TB
+//      staged in LDS, each wavefront an eighth of the rows, each lane a TB x TB
 //      register block of G;
-//   2. cyclic two-sided Jacobi on G in LDS, R accumulating the rotations.  Each
-//      rotation is the complex symmetric Schur 2x2 (Golub & Van Loan 8.4/8.5) for
-//      the pair's Gram entries.  The disjoint pairs of a round act as one unitary J;
-//      every thread forms its elements of J^H G J and R J directly from the
-//      2x2 neighbourhood of the old values (double-buffered: one barrier a round);
+//   2. two-sided Jacobi on G in LDS, R accumulating the rotations.  Each rotation is
+//      the complex symmetric Schur 2x2 (Golub & Van Loan 8.4/8.5) for the pair's
+//      Gram entries.  The disjoint pairs of a round act as one unitary J; every
+//      thread forms its elements of J^H G J and R J directly from the 2x2
+//      neighbourhood of the old values (double-buffered).  With many blocks, a
+//      block's inner pairs are rotated at the sweep's first step and the later
+//      steps rotate only the pairs across the two blocks (BW rounds, not 2 BW - 1);
 //   3. A_P <- A_P R and V_P <- V_P R (a row per thread), sig2 <- diag(R^H G R).
 // A pair whose off-diagonal entries are all below tol * sqrt(G_pp G_qq) is left
 // alone; a task whose previous sweep rotated nothing is converged and skipped.
@@ -157,13 +159,104 @@ __device__ __forceinline__ bool pair_rot(double al, double be, double2 g, double
   return true;
 }
 
+// Block-wide inner two-sided Jacobi on the pair's W2 x W2 Gram (NT threads): per
+// round, one thread per pair forms the rotation, then every thread forms its elements
+// of J^H G J and R J from the 2 x 2 neighbourhood of the old values (double-buffered).
+// G[0] holds the Gram on entry; returns the buffer with the result, any_rot is set
+// when something rotated.  The LDS scratch comes from the caller.
+template <int W2>
+struct InnerLds {
+  double2 ra[W2], rb[W2];      // (X J)[:, x] = ra[x] X_x + rb[x] X_partner(x)
+  int rpart[W2], rrot[W2];
+  int rnd_rot[2];              // did any pair of the round rotate (alternating slots)
+  int swf[3];                  // did any pair of the inner sweep rotate
+  int any_rot;
+};
+
+// cross: only the (W2/2)^2 pairs between the two column blocks, in W2/2 rounds
+// (round r pairs p with W2/2 + (p + r) mod W2/2); else all pairs, round-robin.
+template <int W2, int NT>
+__device__ int inner_jacobi_block(double2 (&G)[2][W2][W2 + 1], double2 (&R)[2][W2][W2 + 1], InnerLds<W2>& L,
+                                  const int (&cols)[W2], int inner, double tol, double ztol, bool cross = false) {
+  constexpr int H = W2 / 2;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < W2 * W2; e += NT) R[0][e / W2][e % W2] = cmk(e / W2 == e % W2 ? 1.0 : 0.0, 0.0);
+  if (tid < 3) L.swf[tid] = 0;
+  if (tid < 2) L.rnd_rot[tid] = 0;
+  if (tid == 0) L.any_rot = 0;
+  __syncthreads();
+  int cur = 0;
+  for (int isw = 0; isw < inner; ++isw) {
+    // slot isw%3 is written this sweep and read after its last barrier; slot
+    // (isw+1)%3 was last read two sweeps ago (many barriers back): clear it now
+    if (tid == 0) L.swf[(isw + 1) % 3] = 0;
+    const int nrnd = cross ? H : W2 - 1;
+    for (int rnd = 0; rnd < nrnd; ++rnd) {
+      if (tid < H) {
+        const int pa = cross ? tid : rr_player(tid, rnd, W2);
+        const int pb = cross ? H + (tid + rnd) % H : rr_player(W2 - 1 - tid, rnd, W2);
+        const int p = pa < pb ? pa : pb, q = pa < pb ? pb : pa;
+        PairRot r;
+        const bool rot = cols[p] >= 0 && cols[q] >= 0 &&
+                         pair_rot(G[cur][p][p].x, G[cur][q][q].x, G[cur][p][q], tol, ztol, r);
+        L.rpart[p] = q; L.rpart[q] = p;
+        L.rrot[p] = rot; L.rrot[q] = rot;
+        if (rot) {
+          L.ra[p] = cmk(r.c, 0.0);          L.rb[p] = cscale(r.e, -r.s);
+          L.ra[q] = cscale(r.e, r.c);       L.rb[q] = cmk(r.s, 0.0);
+          L.swf[isw % 3] = 1;
+          L.rnd_rot[rnd & 1] = 1;
+        } else {
+          L.ra[p] = L.ra[q] = cmk(1.0, 0.0);
+          L.rb[p] = L.rb[q] = cmk(0.0, 0.0);
+        }
+      }
+      __syncthreads();
+      // slot (rnd+1)&1 was last read in the previous round, before its closing barrier
+      if (tid == 0) L.rnd_rot[(rnd + 1) & 1] = 0;
+      if (!L.rnd_rot[rnd & 1]) {  // nothing rotated: G and R are unchanged
+        __syncthreads();
+        continue;
+      }
+      for (int e = tid; e < W2 * W2; e += NT) {
+        const int i = e / W2, j = e % W2;
+        const int pi_ = L.rpart[i], pj = L.rpart[j];
+        const double2 ai = L.ra[i], bi_ = L.rb[i], aj = L.ra[j], bj_ = L.rb[j];
+        const double2(*Gc)[W2 + 1] = G[cur];
+        const double2 colj = cadd(cmul(aj, Gc[i][j]), cmul(bj_, Gc[i][pj]));
+        const double2 colpj = cadd(cmul(aj, Gc[pi_][j]), cmul(bj_, Gc[pi_][pj]));
+        double2 v = cadd(cmul(cconj(ai), colj), cmul(cconj(bi_), colpj));
+        if (L.rrot[i] && j == pi_) v = cmk(0.0, 0.0);  // the rotated pair's off-diagonal is zero
+        if (i == j) v.y = 0.0;
+        G[cur ^ 1][i][j] = v;
+        R[cur ^ 1][i][j] = cadd(cmul(aj, R[cur][i][j]), cmul(bj_, R[cur][i][pj]));
+      }
+      cur ^= 1;
+      __syncthreads();
+    }
+    if (!L.swf[isw % 3]) break;
+    if (tid == 0) L.any_rot = 1;
+  }
+  __syncthreads();
+  return cur;
+}
+
+// One Jacobi step: blockIdx.x is a column-block pair (I, J) of the round-robin
+// schedule, blockIdx.y a task; 512 threads.  Rotating the pair's 2 BW columns:
+//   1. G = A_P^H A_P (W2 x W2, A_P = the pair's columns of W) from row chunks staged
+//      in LDS, D chunks of loads in flight;
+//   2. inner two-sided Jacobi on G (inner_jacobi_block), R accumulating the rotations;
+//   3. A_P <- A_P R and V_P <- V_P R (a row a thread), sig2 <- diag(R^H G R).
 template <int BW>
-__global__ __launch_bounds__(256) void k_jacobi_step(Task2* tasks, const Ent* ents, int step, double tol_mult,
-                                                      int maxin, long long* phase_clock) {
+__global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* ents, int step, double tol_mult,
+                                                        int maxin, long long* phase_clock) {
+  constexpr int NT = 512, NW = NT / 64;
   constexpr int W2 = 2 * BW;
-  constexpr int TB = W2 / 8;                   // register block edge of the Gram phase
-  constexpr int CR = W2 <= 8 ? 128 : 64;        // rows per Gram chunk
-  constexpr int LPT = CR * W2 / 256;           // chunk elements loaded per thread
+  constexpr int TB = W2 / 8;
+  constexpr int CR = 1024 / W2;                // rows per Gram chunk
+  constexpr int LPT = CR * W2 / NT;            // chunk elements loaded per thread
+  constexpr int D = 4;                         // chunks in flight
+  constexpr int RPT = 1;                       // update: rows a thread per pass
   static_assert(W2 == 8 || W2 == 16 || W2 == 32, "block width");
   const Task2& T = tasks[ents[blockIdx.y].slot];
   const int sweep = ents[blockIdx.y].sweep;
@@ -183,12 +276,7 @@ __global__ __launch_bounds__(256) void k_jacobi_step(Task2* tasks, const Ent* en
   __shared__ double2 Ch[2][CR][W2 + 1];
   __shared__ double2 Gb[2][W2][W2 + 1];
   __shared__ double2 Rb[2][W2][W2 + 1];
-  __shared__ double rc_[W2], rs_[W2];       // per index x: coefficient of X_x and of X_partner
-  __shared__ double2 ra_[W2], rb_[W2];      // (X J)[:, x] = ra_[x] X_x + rb_[x] X_partner(x)
-  __shared__ int rpart[W2], rrot[W2];
-  __shared__ int rnd_rot[2];  // did any pair of the round rotate (alternating slots)
-  __shared__ int swf[3];
-  __shared__ int any_rot;
+  __shared__ InnerLds<W2> L;
 
   const bool clk = phase_clock && pi == 0 && blockIdx.y == 0 && tid == 0;
   if (clk) phase_clock[0] = wall_clock64();
@@ -198,32 +286,18 @@ __global__ __launch_bounds__(256) void k_jacobi_step(Task2* tasks, const Ent* en
     const int c = blk * BW + (tid % BW);
     cols[tid] = (blk < nb && c < N) ? c : -1;
   }
-  if (tid < 3) swf[tid] = 0;
-  if (tid < 2) rnd_rot[tid] = 0;
-  if (tid == 0) any_rot = 0;
   __syncthreads();
 
-  // chunk loader: element e = tid + 256 q -> row e % CR, pair column e / CR
-  auto load_chunk = [&](const double2* X, int rows, int r0, double2 (&v)[LPT]) {
-#pragma unroll
-    for (int q = 0; q < LPT; ++q) {
-      const int e = tid + 256 * q;
-      const int rr = e % CR, l = e / CR;
-      const int c = cols[l], r = r0 + rr;
-      v[q] = (c >= 0 && r < rows) ? X[(long)c * rows + r] : cmk(0.0, 0.0);
-    }
-  };
-  auto store_chunk = [&](int buf, const double2 (&v)[LPT]) {
-#pragma unroll
-    for (int q = 0; q < LPT; ++q) {
-      const int e = tid + 256 * q;
-      Ch[buf][e % CR][e / CR] = v[q];
-    }
-  };
-
-  // 1. Gram, row chunks double-buffered: the loads of chunk i+1 are in flight while
-  //    chunk i is reduced.  Wave w takes rows w, w+4, ...; lane (bi, bj) a TB x TB block.
+  // 1. Gram: element e = tid + NT q of a chunk -> row e % CR, pair column e / CR
   const double2* __restrict__ A = T.thw;
+  auto load_chunk = [&](int r0, double2 (&v)[LPT]) {
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+      const int e = tid + NT * q;
+      const int c = cols[e / CR], r = r0 + e % CR;
+      v[q] = (c >= 0 && r < M) ? A[(long)c * M + r] : cmk(0.0, 0.0);
+    }
+  };
   const int wave = tid >> 6, lane = tid & 63;
   const int bi = lane >> 3, bj = lane & 7;
   double2 acc[TB][TB];
@@ -233,31 +307,40 @@ __global__ __launch_bounds__(256) void k_jacobi_step(Task2* tasks, const Ent* en
     for (int j = 0; j < TB; ++j) acc[i][j] = cmk(0.0, 0.0);
   const int nch = (M + CR - 1) / CR;
   {
-    double2 v[LPT];
-    load_chunk(A, M, 0, v);
-    store_chunk(0, v);
-    for (int ch = 0; ch < nch; ++ch) {
-      const bool more = ch + 1 < nch;
-      if (more) load_chunk(A, M, (ch + 1) * CR, v);
-      __syncthreads();
-      const int b = ch & 1;
+    double2 v[D][LPT];
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+      if (d < nch) load_chunk(d * CR, v[d]);
+    for (int c0 = 0; c0 < nch; c0 += D) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const int ch = c0 + d;
+        if (ch >= nch) break;
+        const int b = ch & 1;
+        // buffer b was last read for chunk ch - 2, before chunk ch - 1's barrier
+#pragma unroll
+        for (int q = 0; q < LPT; ++q) {
+          const int e = tid + NT * q;
+          Ch[b][e % CR][e / CR] = v[d][q];
+        }
+        if (ch + D < nch) load_chunk((ch + D) * CR, v[d]);
+        __syncthreads();
 #pragma unroll 4
-      for (int rr = wave; rr < CR; rr += 4) {
-        double2 x[TB], y[TB];
+        for (int rr = wave; rr < CR; rr += NW) {
+          double2 x[TB], y[TB];
 #pragma unroll
-        for (int i = 0; i < TB; ++i) x[i] = Ch[b][rr][bi * TB + i];
+          for (int i = 0; i < TB; ++i) x[i] = Ch[b][rr][bi * TB + i];
 #pragma unroll
-        for (int j = 0; j < TB; ++j) y[j] = Ch[b][rr][bj * TB + j];
+          for (int j = 0; j < TB; ++j) y[j] = Ch[b][rr][bj * TB + j];
 #pragma unroll
-        for (int i = 0; i < TB; ++i)
+          for (int i = 0; i < TB; ++i)
 #pragma unroll
-          for (int j = 0; j < TB; ++j) acc[i][j] = cfmac(x[i], y[j], acc[i][j]);
+            for (int j = 0; j < TB; ++j) acc[i][j] = cfmac(x[i], y[j], acc[i][j]);
+        }
       }
-      if (more) store_chunk(b ^ 1, v);  // buffer b^1 was last read before this chunk's barrier
     }
   }
-  // reduce the four waves' partial Grams into Gb[0] (one wave at a time: deterministic)
-  for (int w = 0; w < 4; ++w) {
+  for (int w = 0; w < NW; ++w) {  // the waves' sums into Gb[0], in wave order
     __syncthreads();
     if (wave == w) {
 #pragma unroll
@@ -269,82 +352,29 @@ __global__ __launch_bounds__(256) void k_jacobi_step(Task2* tasks, const Ent* en
         }
     }
   }
-  for (int e = tid; e < W2 * W2; e += 256) Rb[0][e / W2][e % W2] = cmk(e / W2 == e % W2 ? 1.0 : 0.0, 0.0);
-  const double tol = tol_mult * (double)(M > 16 ? M : 16) * 0x1p-53;
-  const double ztol = *T.fro2 * 0x1p-88;  // columns below 2^-44 ||theta|| are rounding noise
   __syncthreads();
   if (clk) phase_clock[1] = wall_clock64();
 
-  // 2. two-sided Jacobi on G: per round, one thread per pair forms the rotation, then
-  //    every thread forms its elements of J^H G J and R J (double-buffered).  With
-  //    many column blocks a single inner sweep per step is enough (the next steps
-  //    revisit every column); with few blocks each pair is diagonalised fully.
-  const int inner = nbp >= 16 ? maxin : 12;
-  int cur = 0;
-  for (int isw = 0; isw < inner; ++isw) {
-    // slot isw%3 is written this sweep and read after its last barrier; slot
-    // (isw+1)%3 was last read two sweeps ago (many barriers back): clear it now
-    if (tid == 0) swf[(isw + 1) % 3] = 0;
-    for (int rnd = 0; rnd < W2 - 1; ++rnd) {
-      if (tid < W2 / 2) {
-        const int pa = rr_player(tid, rnd, W2), pb = rr_player(W2 - 1 - tid, rnd, W2);
-        const int p = pa < pb ? pa : pb, q = pa < pb ? pb : pa;
-        PairRot r;
-        const bool rot = cols[p] >= 0 && cols[q] >= 0 &&
-                         pair_rot(Gb[cur][p][p].x, Gb[cur][q][q].x, Gb[cur][p][q], tol, ztol, r);
-        rpart[p] = q; rpart[q] = p;
-        rrot[p] = rot; rrot[q] = rot;
-        if (rot) {
-          ra_[p] = cmk(r.c, 0.0);          rb_[p] = cscale(r.e, -r.s);
-          ra_[q] = cscale(r.e, r.c);       rb_[q] = cmk(r.s, 0.0);
-          swf[isw % 3] = 1;
-          rnd_rot[rnd & 1] = 1;
-        } else {
-          ra_[p] = ra_[q] = cmk(1.0, 0.0);
-          rb_[p] = rb_[q] = cmk(0.0, 0.0);
-        }
-      }
-      __syncthreads();
-      // slot (rnd+1)&1 was last read in the previous round, before its closing barrier
-      if (tid == 0) rnd_rot[(rnd + 1) & 1] = 0;
-      if (!rnd_rot[rnd & 1]) {  // nothing rotated: G and R are unchanged
-        __syncthreads();
-        continue;
-      }
-      for (int e = tid; e < W2 * W2; e += 256) {
-        const int i = e / W2, j = e % W2;
-        const int pi_ = rpart[i], pj = rpart[j];
-        const double2 ai = ra_[i], bi_ = rb_[i], aj = ra_[j], bj_ = rb_[j];
-        const double2(*G)[W2 + 1] = Gb[cur];
-        const double2 colj = cadd(cmul(aj, G[i][j]), cmul(bj_, G[i][pj]));
-        const double2 colpj = cadd(cmul(aj, G[pi_][j]), cmul(bj_, G[pi_][pj]));
-        double2 v = cadd(cmul(cconj(ai), colj), cmul(cconj(bi_), colpj));
-        if (rrot[i] && j == pi_) v = cmk(0.0, 0.0);  // the rotated pair's off-diagonal is zero
-        if (i == j) v.y = 0.0;
-        Gb[cur ^ 1][i][j] = v;
-        Rb[cur ^ 1][i][j] = cadd(cmul(aj, Rb[cur][i][j]), cmul(bj_, Rb[cur][i][pj]));
-      }
-      cur ^= 1;
-      __syncthreads();
-    }
-    if (!swf[isw % 3]) break;
-    if (tid == 0) any_rot = 1;
-  }
-  __syncthreads();
+  // 2. inner Jacobi (with many column blocks a single inner sweep per step is enough:
+  //    the next steps revisit every column; with few blocks each pair is diagonalised)
+  const double tol = tol_mult * (double)(M > 16 ? M : 16) * 0x1p-53;
+  const double ztol = *T.fro2 * 0x1p-88;
+  //    Within a sweep, the pairs inside each block are rotated at its first step; the
+  //    later steps rotate only the pairs across the two blocks.
+  const bool many = nbp >= 16;
+  const int cur = inner_jacobi_block<W2, NT>(Gb, Rb, L, cols, many ? maxin : 12, tol, ztol, many && step > 0);
+  const int res_rot = L.any_rot;
   if (clk) phase_clock[2] = wall_clock64();
 
-  // 3. apply R to the pair's columns of W (M rows) and V (N rows), treated as one
-  //    list of M + N rows: each thread takes RPT rows at a time and issues all their
-  //    loads before computing, so that RPT * W2 loads per thread are in flight.
-  if (any_rot) {
+  // 3. A_P <- A_P R and V_P <- V_P R over the JM + N rows
+  if (res_rot) {
     const double2(*R)[W2 + 1] = Rb[cur];
-    constexpr int RPT = W2 <= 8 ? 4 : (W2 <= 16 ? 2 : 1);  // rows per thread in flight
     const int total = M + N;
-    for (int r0 = 0; r0 < total; r0 += 256 * RPT) {
+    for (int r0 = 0; r0 < total; r0 += NT * RPT) {
       double2 x[RPT][W2];
 #pragma unroll
       for (int k = 0; k < RPT; ++k) {
-        const int rr = r0 + tid + 256 * k;
+        const int rr = r0 + tid + NT * k;
         const bool inA = rr < M;
         const double2* X = inA ? T.thw : T.V;
         const int rows = inA ? M : N;
@@ -355,7 +385,7 @@ __global__ __launch_bounds__(256) void k_jacobi_step(Task2* tasks, const Ent* en
       }
 #pragma unroll
       for (int k = 0; k < RPT; ++k) {
-        const int rr = r0 + tid + 256 * k;
+        const int rr = r0 + tid + NT * k;
         if (rr >= total) continue;
         const bool inA = rr < M;
         double2* X = inA ? T.thw : T.V;
@@ -376,7 +406,7 @@ __global__ __launch_bounds__(256) void k_jacobi_step(Task2* tasks, const Ent* en
   if (clk) {
     __threadfence();
     phase_clock[3] = wall_clock64();
-    phase_clock[4] = any_rot;
+    phase_clock[4] = res_rot;
   }
 }
 
@@ -615,15 +645,17 @@ hipError_t launch_theta2(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, 
   return hipSuccess;
 }
 
-hipError_t launch_jacobi_step(Task2* d_tasks, const Ent* d_ents, int nent, int maxN, int bw, int step, double tol_mult,
-                              int maxin, hipStream_t st, long long* phase_clock) {
+hipError_t launch_jacobi_step(Task2* d_tasks, const Ent* d_ents, int nent, int maxN, int bw, int step,
+                              double tol_mult, int maxin, hipStream_t st, long long* phase_clock) {
   const int nb = (maxN + bw - 1) / bw;
-  const int nbp = nb + (nb & 1);
-  const dim3 grid(nbp / 2, nent);
+  const dim3 grid((nb + (nb & 1)) / 2, nent);
   switch (bw) {
-    case 4: hipLaunchKernelGGL(k_jacobi_step<4>, grid, dim3(256), 0, st, d_tasks, d_ents, step, tol_mult, maxin, phase_clock); break;
-    case 8: hipLaunchKernelGGL(k_jacobi_step<8>, grid, dim3(256), 0, st, d_tasks, d_ents, step, tol_mult, maxin, phase_clock); break;
-    case 16: hipLaunchKernelGGL(k_jacobi_step<16>, grid, dim3(256), 0, st, d_tasks, d_ents, step, tol_mult, maxin, phase_clock); break;
+    case 4: hipLaunchKernelGGL(k_jacobi_step<4>, grid, dim3(512), 0, st, d_tasks, d_ents, step, tol_mult, maxin,
+                                   phase_clock); break;
+    case 8: hipLaunchKernelGGL(k_jacobi_step<8>, grid, dim3(512), 0, st, d_tasks, d_ents, step, tol_mult, maxin,
+                                   phase_clock); break;
+    case 16: hipLaunchKernelGGL(k_jacobi_step<16>, grid, dim3(512), 0, st, d_tasks, d_ents, step, tol_mult, maxin,
+                                   phase_clock); break;
     default: return hipErrorInvalidValue;
   }
   MPS_LAUNCH_CHECK();
