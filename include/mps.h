@@ -72,9 +72,12 @@ enum mps_option {
   MPS_OPT_MAX_INNER = 6,      /* inner sweeps per block pair, tasks with >= 16 blocks (1)  */
   MPS_OPT_MAX_SLOTS = 7,      /* updates in flight at once (default 32; batches 1024)     */
   MPS_OPT_WORKSPACE_MB = 8,   /* batches: cap of the update workspace, MiB (16384)        */
-  MPS_OPT_DD_REFINE = 9       /* dd: 1 (default) simultaneous first-order corrections,
+  MPS_OPT_DD_REFINE = 9,      /* dd: 1 (default) simultaneous first-order corrections,
                                  then the pairwise polish only where those do not apply;
                                  0: the pairwise dd Jacobi polish alone                  */
+  MPS_OPT_JACOBI_STREAMS = 10 /* 2 (default): the FP64 Jacobi steps of concurrent updates
+                                 run as two launch sequences on two internal streams,
+                                 joined into the handle's stream; 1: one sequence        */
 };
 
 /* Diagnostics of the most recent split (the last one of a three-qubit gate). */

@@ -118,6 +118,9 @@ __global__ __launch_bounds__(256) void k_theta2(Task2* tasks, const Ent* ents) {
 // A pair whose off-diagonal entries are all below tol * sqrt(G_pp G_qq) is left
 // alone; a task whose previous sweep rotated nothing is converged and skipped.
 __device__ __forceinline__ int rr_player(int i, int r, int np) { return i == 0 ? 0 : 1 + (i - 1 + r) % (np - 1); }
+// accumulator of v_mfma_f64_16x16x4f64: element r of lane l is D[l / 16 + 4 r][l % 16]
+// (A operand: lane l holds A[l % 16][l / 16]; B operand: B[l / 16][l % 16])
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
 // Newton-refined reciprocal and reciprocal square root (the hardware estimates
 // v_rcp_f64 / v_rsq_f64 are not correctly rounded; two Newton steps bring them to
 // binary64 accuracy, with a much shorter dependency chain than div / sqrt).
@@ -273,7 +276,6 @@ __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* en
   if (sweep > 0 && flags[(sweep + 2) % 3] == 0) return;
 
   __shared__ int cols[W2];
-  __shared__ double2 Ch[2][CR][W2 + 1];
   __shared__ double2 Gb[2][W2][W2 + 1];
   __shared__ double2 Rb[2][W2][W2 + 1];
   __shared__ InnerLds<W2> L;
@@ -288,68 +290,113 @@ __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* en
   }
   __syncthreads();
 
-  // 1. Gram: element e = tid + NT q of a chunk -> row e % CR, pair column e / CR
+  // 1. Gram
   const double2* __restrict__ A = T.thw;
-  auto load_chunk = [&](int r0, double2 (&v)[LPT]) {
-#pragma unroll
-    for (int q = 0; q < LPT; ++q) {
-      const int e = tid + NT * q;
-      const int c = cols[e / CR], r = r0 + e % CR;
-      v[q] = (c >= 0 && r < M) ? A[(long)c * M + r] : cmk(0.0, 0.0);
-    }
-  };
   const int wave = tid >> 6, lane = tid & 63;
-  const int bi = lane >> 3, bj = lane & 7;
-  double2 acc[TB][TB];
+  if constexpr (W2 == 16) {
+    // by MFMA over k-steps of 4 rows, wave w taking k-steps w, w + NW, ...: lane l
+    // holds X[4 ks + l / 16][column l % 16], the same element for both operands;
+    // Re G = Xr^T Xr + Xi^T Xi and, with P = Xr^T Xi, Im G = P - P^T
+    __shared__ double Gw[NW][2][W2][W2 + 1];
+    constexpr int KB = 16;  // k-steps of loads in flight per wave
+    mfma_d4 gr = {0.0, 0.0, 0.0, 0.0}, gp = {0.0, 0.0, 0.0, 0.0};
+    const int c = cols[lane & 15];
+    const int roff = lane >> 4;
+    const int nks = (M + 3) / 4;
+    for (int ks0 = wave; ks0 < nks; ks0 += NW * KB) {
+      double2 x[KB];
 #pragma unroll
-  for (int i = 0; i < TB; ++i)
+      for (int t = 0; t < KB; ++t) {
+        const int r = (ks0 + NW * t) * 4 + roff;
+        x[t] = (c >= 0 && r < M) ? A[(long)c * M + r] : cmk(0.0, 0.0);
+      }
 #pragma unroll
-    for (int j = 0; j < TB; ++j) acc[i][j] = cmk(0.0, 0.0);
-  const int nch = (M + CR - 1) / CR;
-  {
-    double2 v[D][LPT];
+      for (int t = 0; t < KB; ++t) {
+        gr = __builtin_amdgcn_mfma_f64_16x16x4f64(x[t].x, x[t].x, gr, 0, 0, 0);
+        gr = __builtin_amdgcn_mfma_f64_16x16x4f64(x[t].y, x[t].y, gr, 0, 0, 0);
+        gp = __builtin_amdgcn_mfma_f64_16x16x4f64(x[t].x, x[t].y, gp, 0, 0, 0);
+      }
+    }
 #pragma unroll
-    for (int d = 0; d < D; ++d)
-      if (d < nch) load_chunk(d * CR, v[d]);
-    for (int c0 = 0; c0 < nch; c0 += D) {
+    for (int r = 0; r < 4; ++r) {
+      Gw[wave][0][roff + 4 * r][lane & 15] = gr[r];
+      Gw[wave][1][roff + 4 * r][lane & 15] = gp[r];
+    }
+    __syncthreads();
+    if (tid < W2 * W2) {  // the waves' sums in wave order
+      const int i = tid / W2, j = tid % W2;
+      double sr = 0.0, pij = 0.0, pji = 0.0;
+      for (int w = 0; w < NW; ++w) {
+        sr += Gw[w][0][i][j];
+        pij += Gw[w][1][i][j];
+        pji += Gw[w][1][j][i];
+      }
+      Gb[0][i][j] = cmk(sr, pij - pji);
+    }
+  } else {
+    // row chunks staged in LDS, D chunks of loads in flight; each wave an eighth of
+    // a chunk's rows, each lane a TB x TB register block of G
+    __shared__ double2 Ch[2][CR][W2 + 1];
+    auto load_chunk = [&](int r0, double2 (&v)[LPT]) {
 #pragma unroll
-      for (int d = 0; d < D; ++d) {
-        const int ch = c0 + d;
-        if (ch >= nch) break;
-        const int b = ch & 1;
-        // buffer b was last read for chunk ch - 2, before chunk ch - 1's barrier
+      for (int q = 0; q < LPT; ++q) {
+        const int e = tid + NT * q;
+        const int c = cols[e / CR], r = r0 + e % CR;
+        v[q] = (c >= 0 && r < M) ? A[(long)c * M + r] : cmk(0.0, 0.0);
+      }
+    };
+    const int bi = lane >> 3, bj = lane & 7;
+    double2 acc[TB][TB];
 #pragma unroll
-        for (int q = 0; q < LPT; ++q) {
-          const int e = tid + NT * q;
-          Ch[b][e % CR][e / CR] = v[d][q];
-        }
-        if (ch + D < nch) load_chunk((ch + D) * CR, v[d]);
-        __syncthreads();
+    for (int i = 0; i < TB; ++i)
+#pragma unroll
+      for (int j = 0; j < TB; ++j) acc[i][j] = cmk(0.0, 0.0);
+    const int nch = (M + CR - 1) / CR;
+    {
+      double2 v[D][LPT];
+#pragma unroll
+      for (int d = 0; d < D; ++d)
+        if (d < nch) load_chunk(d * CR, v[d]);
+      for (int c0 = 0; c0 < nch; c0 += D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          const int ch = c0 + d;
+          if (ch >= nch) break;
+          const int b = ch & 1;
+          // buffer b was last read for chunk ch - 2, before chunk ch - 1's barrier
+#pragma unroll
+          for (int q = 0; q < LPT; ++q) {
+            const int e = tid + NT * q;
+            Ch[b][e % CR][e / CR] = v[d][q];
+          }
+          if (ch + D < nch) load_chunk((ch + D) * CR, v[d]);
+          __syncthreads();
 #pragma unroll 4
-        for (int rr = wave; rr < CR; rr += NW) {
-          double2 x[TB], y[TB];
+          for (int rr = wave; rr < CR; rr += NW) {
+            double2 x[TB], y[TB];
 #pragma unroll
-          for (int i = 0; i < TB; ++i) x[i] = Ch[b][rr][bi * TB + i];
+            for (int i = 0; i < TB; ++i) x[i] = Ch[b][rr][bi * TB + i];
 #pragma unroll
-          for (int j = 0; j < TB; ++j) y[j] = Ch[b][rr][bj * TB + j];
+            for (int j = 0; j < TB; ++j) y[j] = Ch[b][rr][bj * TB + j];
 #pragma unroll
-          for (int i = 0; i < TB; ++i)
+            for (int i = 0; i < TB; ++i)
 #pragma unroll
-            for (int j = 0; j < TB; ++j) acc[i][j] = cfmac(x[i], y[j], acc[i][j]);
+              for (int j = 0; j < TB; ++j) acc[i][j] = cfmac(x[i], y[j], acc[i][j]);
+          }
         }
       }
     }
-  }
-  for (int w = 0; w < NW; ++w) {  // the waves' sums into Gb[0], in wave order
-    __syncthreads();
-    if (wave == w) {
+    for (int w = 0; w < NW; ++w) {  // the waves' sums into Gb[0], in wave order
+      __syncthreads();
+      if (wave == w) {
 #pragma unroll
-      for (int i = 0; i < TB; ++i)
+        for (int i = 0; i < TB; ++i)
 #pragma unroll
-        for (int j = 0; j < TB; ++j) {
-          const int gi = bi * TB + i, gj = bj * TB + j;
-          Gb[0][gi][gj] = (w == 0) ? acc[i][j] : cadd(Gb[0][gi][gj], acc[i][j]);
-        }
+          for (int j = 0; j < TB; ++j) {
+            const int gi = bi * TB + i, gj = bj * TB + j;
+            Gb[0][gi][gj] = (w == 0) ? acc[i][j] : cadd(Gb[0][gi][gj], acc[i][j]);
+          }
+      }
     }
   }
   __syncthreads();
@@ -366,37 +413,39 @@ __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* en
   const int res_rot = L.any_rot;
   if (clk) phase_clock[2] = wall_clock64();
 
-  // 3. A_P <- A_P R and V_P <- V_P R over the JM + N rows
+  // 3. A_P <- A_P R and V_P <- V_P R over the JM + N rows (W's, then V's)
   if (res_rot) {
-    const double2(*R)[W2 + 1] = Rb[cur];
     const int total = M + N;
-    for (int r0 = 0; r0 < total; r0 += NT * RPT) {
-      double2 x[RPT][W2];
+    {
+      const double2(*R)[W2 + 1] = Rb[cur];
+      for (int r0 = 0; r0 < total; r0 += NT * RPT) {
+        double2 x[RPT][W2];
 #pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        const int rr = r0 + tid + NT * k;
-        const bool inA = rr < M;
-        const double2* X = inA ? T.thw : T.V;
-        const int rows = inA ? M : N;
-        const int r = inA ? rr : rr - M;
+        for (int k = 0; k < RPT; ++k) {
+          const int rr = r0 + tid + NT * k;
+          const bool inA = rr < M;
+          const double2* X = inA ? T.thw : T.V;
+          const int rows = inA ? M : N;
+          const int r = inA ? rr : rr - M;
 #pragma unroll
-        for (int l = 0; l < W2; ++l)
-          x[k][l] = (rr < total && cols[l] >= 0) ? X[(long)cols[l] * rows + r] : cmk(0.0, 0.0);
-      }
+          for (int l = 0; l < W2; ++l)
+            x[k][l] = (rr < total && cols[l] >= 0) ? X[(long)cols[l] * rows + r] : cmk(0.0, 0.0);
+        }
 #pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        const int rr = r0 + tid + NT * k;
-        if (rr >= total) continue;
-        const bool inA = rr < M;
-        double2* X = inA ? T.thw : T.V;
-        const int rows = inA ? M : N;
-        const int r = inA ? rr : rr - M;
+        for (int k = 0; k < RPT; ++k) {
+          const int rr = r0 + tid + NT * k;
+          if (rr >= total) continue;
+          const bool inA = rr < M;
+          double2* X = inA ? T.thw : T.V;
+          const int rows = inA ? M : N;
+          const int r = inA ? rr : rr - M;
 #pragma unroll 4
-        for (int pc = 0; pc < W2; ++pc) {
-          double2 y = cmk(0.0, 0.0);
+          for (int pc = 0; pc < W2; ++pc) {
+            double2 y = cmk(0.0, 0.0);
 #pragma unroll
-          for (int l = 0; l < W2; ++l) y = cfma(x[k][l], R[l][pc], y);
-          if (cols[pc] >= 0) X[(long)cols[pc] * rows + r] = y;
+            for (int l = 0; l < W2; ++l) y = cfma(x[k][l], R[l][pc], y);
+            if (cols[pc] >= 0) X[(long)cols[pc] * rows + r] = y;
+          }
         }
       }
     }

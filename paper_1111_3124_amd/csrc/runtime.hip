@@ -82,6 +82,12 @@ struct Engine {
   int prec = MPS_PREC_FP64;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // the Jacobi steps of a tick run as two interleaved launch sequences (half the
+  // iterating updates each) on stream and stream2, so that one half's memory phases
+  // overlap the other half's inner Jacobi
+  hipStream_t stream2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  int jacobi_streams = 2;
   int device = 0;
   bool batch = false;  // a batch engine sizes workspace per update, not per slot
   // options (shared by every state of the engine)
@@ -170,6 +176,8 @@ int bond_capacity(int n, int chi, int b) {
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 // ------------------------------------------------------------------ engines
+void engine_free(Engine* E);
+
 Engine* engine_new(int prec, void* hip_stream, std::string* err) {
   Engine* E = new Engine();
   E->prec = prec;
@@ -183,9 +191,12 @@ Engine* engine_new(int prec, void* hip_stream, std::string* err) {
       E->own_stream = e == hipSuccess;
     }
   }
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&E->stream2, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&E->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&E->ev_join, hipEventDisableTiming);
   if (e != hipSuccess) {
     *err = std::string("engine: ") + hipGetErrorString(e);
-    delete E;
+    engine_free(E);
     return nullptr;
   }
   if (const char* dbg = std::getenv("MPS_DEBUG_PHASES"))
@@ -196,6 +207,12 @@ Engine* engine_new(int prec, void* hip_stream, std::string* err) {
 void engine_free(Engine* E) {
   if (!E) return;
   if (E->stream) (void)hipStreamSynchronize(E->stream);
+  if (E->stream2) {
+    (void)hipStreamSynchronize(E->stream2);
+    (void)hipStreamDestroy(E->stream2);
+  }
+  if (E->ev_fork) (void)hipEventDestroy(E->ev_fork);
+  if (E->ev_join) (void)hipEventDestroy(E->ev_join);
   if (E->d_phase) (void)hipFree(E->d_phase);
   if (E->ws) (void)hipFree(E->ws);
   if (E->d_small) (void)hipFree(E->d_small);
@@ -554,7 +571,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
   const size_t o_u8 = o_dims + align_up(sizeof(int) * dims_total);
   const size_t o_g1 = o_u8 + align_up(sizeof(double2) * 128 * S);
   const size_t o_ents = o_g1 + align_up(sizeof(Task1) * nsites);
-  constexpr int kLists = 11;  // new2, new3, jacobi, dd, dd-enter, final, final3, mid, znorm, ref, polish
+  constexpr int kLists = 12;  // new2, new3, jacobi (two), dd, dd-enter, final, final3, mid, znorm, ref, polish
   const size_t list_bytes = align_up(sizeof(mpsk::Ent) * S);
   rc = ensure_small(E, o_ents + kLists * list_bytes, err);
   if (rc) return rc;
@@ -568,7 +585,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
   int* hdims = (int*)(E->h_stage + o_dims);
   double2* hu8 = (double2*)(E->h_stage + o_u8);
   double2* du8 = (double2*)(E->d_small + o_u8);
-  enum { LN2 = 0, LN3, LJ, LD, LENTER, LFIN, LFIN3, LMID, LZN, LR, LPOL };
+  enum { LN2 = 0, LN3, LJ, LD, LENTER, LFIN, LFIN3, LMID, LZN, LR, LPOL, LJ2 };
   auto hlist = [&](int i) { return E->h_stage + o_ents + i * list_bytes; };
   auto dlist = [&](int i) { return E->d_small + o_ents + i * list_bytes; };
 
@@ -808,18 +825,42 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
       }
     }
     if (!jl.empty()) {
-      mpsk::Ent* el = upload_list(LJ, ents_of(jl));
-      if (!el) return fail(err, MPS_EDEVICE, "list upload failed");
-      int mN = 0;
-      for (int si : jl) mN = std::max(mN, slot[si].N);
+      // two halves (alternate updates) on two streams when there are at least two
+      const bool two = E->jacobi_streams == 2 && jl.size() >= 2;
+      std::vector<int> ja, jb;
+      for (size_t i = 0; i < jl.size(); ++i) ((two && (i & 1)) ? jb : ja).push_back(jl[i]);
+      mpsk::Ent* ea = upload_list(LJ, ents_of(ja));
+      mpsk::Ent* eb = two ? upload_list(LJ2, ents_of(jb)) : nullptr;
+      if (!ea || (two && !eb)) return fail(err, MPS_EDEVICE, "list upload failed");
+      int mNa = 0, mNb = 0;
+      for (int si : ja) mNa = std::max(mNa, slot[si].N);
+      for (int si : jb) mNb = std::max(mNb, slot[si].N);
+      const int mN = std::max(mNa, mNb);
       const int nb = (mN + bw - 1) / bw;
       const int nsteps = nb + (nb & 1) - 1;
+      const int nba = (mNa + bw - 1) / bw, nbb = (mNb + bw - 1) / bw;
+      const int nsa = nba + (nba & 1) - 1, nsb = two ? nbb + (nbb & 1) - 1 : 0;
       Timed tm(E, 1, nsteps);
       E->slot_sweeps += (long)jl.size();
+      if (two) {
+        HIPCHK(err, hipEventRecord(E->ev_fork, st));
+        HIPCHK(err, hipStreamWaitEvent(E->stream2, E->ev_fork, 0));
+      }
       for (int stp = 0; stp < nsteps; ++stp) {
         long long* pc = (E->d_phase && stp == nsteps / 2) ? E->d_phase : nullptr;
-        e = mpsk::launch_jacobi_step(dt, el, (int)jl.size(), mN, bw, stp, E->tol_mult, E->max_inner, st, pc);
-        if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("jacobi: ") + hipGetErrorString(e));
+        if (stp < nsa) {
+          e = mpsk::launch_jacobi_step(dt, ea, (int)ja.size(), mNa, bw, stp, E->tol_mult, E->max_inner, st, pc);
+          if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("jacobi: ") + hipGetErrorString(e));
+        }
+        if (stp < nsb) {
+          e = mpsk::launch_jacobi_step(dt, eb, (int)jb.size(), mNb, bw, stp, E->tol_mult, E->max_inner, E->stream2,
+                                       nullptr);
+          if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("jacobi: ") + hipGetErrorString(e));
+        }
+      }
+      if (two) {
+        HIPCHK(err, hipEventRecord(E->ev_join, E->stream2));
+        HIPCHK(err, hipStreamWaitEvent(st, E->ev_join, 0));
       }
     }
     if (!rl.empty()) {
@@ -1101,6 +1142,10 @@ int set_option(Engine* E, int prec, int key, double value, std::string* err) {
     case MPS_OPT_MAX_SLOTS:
       if (!(value >= 1 && value <= 65536)) return fail(err, MPS_EINVAL, "slot limit out of range");
       E->max_slots = (int)value;
+      return MPS_OK;
+    case MPS_OPT_JACOBI_STREAMS:
+      if (!(value == 1 || value == 2)) return fail(err, MPS_EINVAL, "Jacobi stream count must be 1 or 2");
+      E->jacobi_streams = (int)value;
       return MPS_OK;
     case MPS_OPT_DD_REFINE:
       if (!(value == 0 || value == 1)) return fail(err, MPS_EINVAL, "dd refinement switch must be 0 or 1");
