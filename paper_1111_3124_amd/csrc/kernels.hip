@@ -121,16 +121,9 @@ __device__ __forceinline__ int rr_player(int i, int r, int np) { return i == 0 ?
 // accumulator of v_mfma_f64_16x16x4f64: element r of lane l is D[l / 16 + 4 r][l % 16]
 // (A operand: lane l holds A[l % 16][l / 16]; B operand: B[l / 16][l % 16])
 typedef double mfma_d4 __attribute__((ext_vector_type(4)));
-// Newton-refined reciprocal and reciprocal square root (the hardware estimates
-// v_rcp_f64 / v_rsq_f64 are not correctly rounded; two Newton steps bring them to
-// binary64 accuracy, with a much shorter dependency chain than div / sqrt).
-__device__ __forceinline__ double rcp_nr(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, y, 1.0);
-  y = fma(y, e, y);
-  e = fma(-x, y, 1.0);
-  return fma(y, e, y);
-}
+// Newton-refined reciprocal square root (the hardware estimate v_rsq_f64 is not
+// correctly rounded; two Newton steps bring it to binary64 accuracy, with a much
+// shorter dependency chain than div / sqrt).
 __device__ __forceinline__ double rsq_nr(double x) {
   double y = __builtin_amdgcn_rsq(x);
   double hx = 0.5 * x;
@@ -143,6 +136,8 @@ __device__ __forceinline__ double rsq_nr(double x) {
 // g = G_pq: the complex form of the symmetric Schur 2x2 (Golub & Van Loan 8.4):
 // with e = conj(g)/|g|, zeta = (be - al) / (2|g|), t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)),
 // c = 1 / sqrt(1 + t^2), s = t c:  (X J)[:, p] = c X_p - s e X_q,  (X J)[:, q] = s X_p + c e X_q.
+// With u = |zeta| + sqrt(1 + zeta^2) = 1 / |t|, c = u / sqrt(u^2 + 1) and |s| = 1 / sqrt(u^2 + 1),
+// which needs no reciprocal; sqrt(x) for x >= 1 is x rsq(x).
 struct PairRot {
   double c, s;
   double2 e;  // e^{-i phi}
@@ -153,11 +148,11 @@ __device__ __forceinline__ bool pair_rot(double al, double be, double2 g, double
   if (!(al > ztol && be > ztol && g2 > tol * tol * al * be)) return false;
   const double ig = rsq_nr(g2);            // 1 / |g|
   const double zeta = 0.5 * (be - al) * ig;
-  const double root = sqrt(fma(zeta, zeta, 1.0));
-  double t = rcp_nr(fabs(zeta) + root);
-  t = zeta < 0.0 ? -t : t;
-  r.c = rsq_nr(fma(t, t, 1.0));
-  r.s = t * r.c;
+  const double x = fma(zeta, zeta, 1.0);
+  const double u = fabs(zeta) + x * rsq_nr(x);
+  const double w = rsq_nr(fma(u, u, 1.0));
+  r.c = u * w;
+  r.s = zeta < 0.0 ? -w : w;
   r.e = cmk(g.x * ig, -g.y * ig);
   return true;
 }
