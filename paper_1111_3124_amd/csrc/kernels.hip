@@ -17,7 +17,8 @@
 namespace mpsk {
 
 // ------------------------------------------------------------------ prep
-// V = I_N, zero the Frobenius accumulator and the rotation flags.
+// V = I_N, the identity column order, zero the Frobenius accumulator and the
+// rotation flags.
 __global__ __launch_bounds__(256) void k_prep2(Task2* tasks, const Ent* ents) {
   const Task2& T = tasks[ents[blockIdx.y].slot];
   const int N = T.N;
@@ -26,6 +27,8 @@ __global__ __launch_bounds__(256) void k_prep2(Task2* tasks, const Ent* ents) {
     const int r = (int)(e % N), c = (int)(e / N);
     T.V[e] = cmk(r == c ? 1.0 : 0.0, 0.0);
   }
+  if (blockIdx.x == 0)
+    for (int j = threadIdx.x; j < N; j += 256) T.perm[j] = j;  // the first sweep's column order
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *T.fro2 = 0.0;
     T.flags[0] = T.flags[1] = T.flags[2] = 0;
@@ -278,10 +281,10 @@ __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* en
   const bool clk = phase_clock && pi == 0 && blockIdx.y == 0 && tid == 0;
   if (clk) phase_clock[0] = wall_clock64();
   const int I = rr_player(pi, step, nbp), J = rr_player(nbp - 1 - pi, step, nbp);
-  if (tid < W2) {
+  if (tid < W2) {  // the pair's columns: positions blk * BW + x of this sweep's order
     const int blk = tid < BW ? I : J;
     const int c = blk * BW + (tid % BW);
-    cols[tid] = (blk < nb && c < N) ? c : -1;
+    cols[tid] = (blk < nb && c < N) ? T.perm[c] : -1;
   }
   __syncthreads();
 
@@ -454,6 +457,50 @@ __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* en
   }
 }
 
+// ------------------------------------------------------------------ ordering
+// In-place bitonic sort of P (a power of two) LDS (key, index) pairs, largest key
+// first, equal keys by ascending index; the whole block takes part.
+__device__ void bitonic_desc(double* key, int* idx, int P) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = tid; i < P; i += nt) {
+        const int l = i ^ stride;
+        if (l > i) {
+          const bool before = key[i] > key[l] || (key[i] == key[l] && idx[i] < idx[l]);
+          const bool dir = (i & size) == 0;
+          if (dir != before) {
+            const double tk = key[i]; key[i] = key[l]; key[l] = tk;
+            const int ti = idx[i]; idx[i] = idx[l]; idx[l] = ti;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Column order of a sweep (de Rijk's pivoting for one-sided Jacobi): the N columns
+// of W sorted by their squared norms at the end of the previous sweep (the Gram
+// diagonals every step leaves in sig2), largest first.  The step kernels pair the
+// blocks of this order; sweep 0 keeps the identity order set by k_prep2.
+__global__ __launch_bounds__(1024) void k_jacobi_order(Task2* tasks, const Ent* ents) {
+  Task2& T = tasks[ents[blockIdx.x].slot];
+  if (ents[blockIdx.x].sweep == 0) return;
+  const int N = T.N;
+  int P = 1;
+  while (P < N) P <<= 1;
+  __shared__ double key[kMaxSort];
+  __shared__ int idx[kMaxSort];
+  for (int j = threadIdx.x; j < P; j += blockDim.x) {
+    key[j] = j < N ? fmax(T.sig2[j], 0.0) : -1.0;
+    idx[j] = j;
+  }
+  __syncthreads();
+  bitonic_desc(key, idx, P);
+  for (int j = threadIdx.x; j < N; j += blockDim.x) T.perm[j] = idx[j];
+}
+
 // ------------------------------------------------------------------ truncation
 // Sort sigma^2 descending (bitonic, ties by column index), suffix sums for the
 // discarded weight, the kept count k = min(chi, k_eps, rank, min(M, N)), the new
@@ -477,22 +524,7 @@ __global__ __launch_bounds__(1024) void k_truncate(Task2* tasks, const Ent* ents
   }
   if (tid == 0) { s_rank = 0; s_keps = N; s_kept = 0.0; }
   __syncthreads();
-  for (int size = 2; size <= P; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = tid; i < P; i += nt) {
-        const int l = i ^ stride;
-        if (l > i) {
-          const bool before = key[i] > key[l] || (key[i] == key[l] && idx[i] < idx[l]);
-          const bool dir = (i & size) == 0;
-          if (dir != before) {
-            const double tk = key[i]; key[i] = key[l]; key[l] = tk;
-            const int ti = idx[i]; idx[i] = idx[l]; idx[l] = ti;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
+  bitonic_desc(key, idx, P);
   // suffix sums: sc[j] = sum_{i >= j} sigma_i^2
   for (int j = tid; j < P; j += nt) sc[j] = j < N ? key[j] : 0.0;
   __syncthreads();
@@ -702,6 +734,12 @@ hipError_t launch_jacobi_step(Task2* d_tasks, const Ent* d_ents, int nent, int m
                                    phase_clock); break;
     default: return hipErrorInvalidValue;
   }
+  MPS_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_jacobi_order(Task2* d_tasks, const Ent* d_ents, int nent, hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobi_order, dim3(nent), dim3(1024), 0, st, d_tasks, d_ents);
   MPS_LAUNCH_CHECK();
   return hipSuccess;
 }

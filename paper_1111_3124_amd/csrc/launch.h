@@ -19,6 +19,8 @@ hipError_t launch_theta2(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, 
 // (start, after Gram, after inner Jacobi, end, rotated?) for phase profiling
 hipError_t launch_jacobi_step(Task2* d_tasks, const Ent* d_ents, int nent, int maxN, int bw, int step, double tol_mult,
                               int maxin, hipStream_t st, long long* phase_clock = nullptr);
+// column order of each task's sweep (sorted by the previous sweep's column norms)
+hipError_t launch_jacobi_order(Task2* d_tasks, const Ent* d_ents, int nent, hipStream_t st);
 // chi_max and eps are read from each task
 hipError_t launch_truncate(Task2* d_tasks, const Ent* d_ents, int nent, double floor_rel, hipStream_t st);
 // right = false: only B_s' (the first split of a three-site gate)

@@ -571,7 +571,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
   const size_t o_u8 = o_dims + align_up(sizeof(int) * dims_total);
   const size_t o_g1 = o_u8 + align_up(sizeof(double2) * 128 * S);
   const size_t o_ents = o_g1 + align_up(sizeof(Task1) * nsites);
-  constexpr int kLists = 12;  // new2, new3, jacobi (two), dd, dd-enter, final, final3, mid, znorm, ref, polish
+  constexpr int kLists = 13;  // new2, new3, jacobi (two + order), dd, dd-enter, final, final3, mid, znorm, ref, polish
   const size_t list_bytes = align_up(sizeof(mpsk::Ent) * S);
   rc = ensure_small(E, o_ents + kLists * list_bytes, err);
   if (rc) return rc;
@@ -585,7 +585,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
   int* hdims = (int*)(E->h_stage + o_dims);
   double2* hu8 = (double2*)(E->h_stage + o_u8);
   double2* du8 = (double2*)(E->d_small + o_u8);
-  enum { LN2 = 0, LN3, LJ, LD, LENTER, LFIN, LFIN3, LMID, LZN, LR, LPOL, LJ2 };
+  enum { LN2 = 0, LN3, LJ, LD, LENTER, LFIN, LFIN3, LMID, LZN, LR, LPOL, LJ2, LJO };
   auto hlist = [&](int i) { return E->h_stage + o_ents + i * list_bytes; };
   auto dlist = [&](int i) { return E->d_small + o_ents + i * list_bytes; };
 
@@ -842,6 +842,12 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
       const int nsa = nba + (nba & 1) - 1, nsb = two ? nbb + (nbb & 1) - 1 : 0;
       Timed tm(E, 1, nsteps);
       E->slot_sweeps += (long)jl.size();
+      {
+        mpsk::Ent* eo = upload_list(LJO, ents_of(jl));
+        if (!eo) return fail(err, MPS_EDEVICE, "list upload failed");
+        e = mpsk::launch_jacobi_order(dt, eo, (int)jl.size(), st);
+        if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("jacobi order: ") + hipGetErrorString(e));
+      }
       if (two) {
         HIPCHK(err, hipEventRecord(E->ev_fork, st));
         HIPCHK(err, hipStreamWaitEvent(E->stream2, E->ev_fork, 0));
