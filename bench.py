@@ -122,11 +122,13 @@ def measured_traffic():
 
 
 def roofline(res):
-    """Dominant kernel: the FP64 Jacobi step (k_jacobi_step<8>).  Per launch it does,
-    for each update it serves, one of the nsteps = N - 1 steps of a sweep: J(M, N) /
-    nsteps flops and step_bytes(M, N) of traffic.  Totals over the timed region:
-    update-sweeps executed x nsteps x those; achieved = total / the step kernels'
-    HIP-event time.  The primary bound is the one the kernel is closer to."""
+    """Dominant kernel: the FP64 Jacobi step (k_jacobi_step<8>).  A step serves each
+    iterating update with one of the nsteps = N/8 - 1 steps of its sweep: J(M, N) /
+    nsteps flops and step_bytes(M, N) of traffic.  The updates of a step are split
+    into two halves whose launches run concurrently on two streams, so a launch
+    lasts about as long as the step.  Totals over the timed region: update-sweeps
+    executed x nsteps x those; achieved = total / the steps' HIP-event time.  The
+    primary bound is the one the kernel is closer to."""
     ms, launches = res["ktimes"]["jacobi"]
     if launches == 0:
         return None
@@ -148,7 +150,7 @@ def roofline(res):
     main, other = (hbm, alu) if f_hbm >= f_alu else (alu, hbm)
     main = dict(main)
     main.update({"kernel": "k_jacobi_step<8>", "avg_launch_us": 1e3 * ms / launches, "launches": launches,
-                 "other_bound": other})
+                 "concurrent_launches": 2, "other_bound": other})
     return main
 
 
