@@ -72,6 +72,30 @@ def test_config1_brickwork_vs_oracle_and_state_vector(B, oracle_mod):
     assert st["splits"] == 1 and abs(st["W"] - 1.0) < 1e-13
 
 
+@pytest.mark.parametrize("bw", [4, 8, 16])
+def test_jacobi_variants_vs_oracle(B, oracle_mod, bw):
+    """The step kernel's block widths (4 and 16: Gram on the vector units, 4 with the
+    cross-block rounds at N = 64; 8: Gram by MFMA) and one or two launch streams:
+    config-1 brickwork (10 qubits, depth 10, chi_max 32), every amplitude vs the
+    oracle; the one- and two-stream runs are bit-identical."""
+    flush(f"jacobi variants: n=10 depth=10 chi=32 seed=5 bw={bw}")
+    n = 10
+    gates = [g for layer in W.brickwork(n, 10, 5) for g in layer]
+    om, _ = oracle_run(oracle_mod, n, 32, 0.0, gates)
+    bits = all_bits(n)
+    want = oracle_amps(om, bits)
+    got = {}
+    for streams in (1, 2):
+        dev = B.MPS(n, 32, 0.0)
+        dev.set_option(B.MPS_OPT_BLOCK_WIDTH, bw)
+        dev.set_option(B.MPS_OPT_JACOBI_STREAMS, streams)
+        dev.apply_gates(gates)
+        assert dev.bond_dims() == om.bond_dims()
+        got[streams] = dev.amplitudes(bits)
+        assert np.max(np.abs(got[streams] - want)) <= TOL
+    assert np.array_equal(got[1], got[2])
+
+
 def test_wave_equals_sequential(B):
     """A brickwork layer applied as one batched wave gives the sequential result."""
     flush("wave: n=12 depth=8 chi=64 seed=3")
