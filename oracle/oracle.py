@@ -106,6 +106,41 @@ class OracleMPS:
     def apply_gate(self, g) -> None:
         self.apply(g.first, g.k, g.u_hi, g.u_lo)
 
+    def apply_gate2(self, q0: int, q1: int, u_hi, u_lo=None) -> None:
+        """Two-qubit gate on qubits q0 != q1, U's first index bit on q0 (the paper's
+        applyU(U, q0, q1), Section 3.2).  Adjacent: one U(4) on min(q0, q1) (for
+        q0 > q1 the gate with its two qubits exchanged, S U S with S = SWAP).
+        Otherwise, a = min, b = max: SWAPs on sites (b-1, b) down to (a+2, a+3) bring
+        qubit b next but one to a, the U(8) (U on the window's outer sites) (x) the
+        identity on the middle one acts on a..a+2, and SWAPs on (a+2, a+3) up to
+        (b-1, b) take it back (the routing the paper leaves open, read as the one
+        that needs the fewest swaps with three-qubit gates elementary)."""
+        if q0 == q1 or not (0 <= q0 < self.n and 0 <= q1 < self.n):
+            raise ValueError("qubits must be distinct and in range")
+        S = np.zeros((4, 4), dtype=np.complex128)
+        S[0, 0] = S[1, 2] = S[2, 1] = S[3, 3] = 1.0
+        mats = [np.asarray(u_hi, dtype=np.complex128)]
+        if u_lo is not None:
+            mats.append(np.asarray(u_lo, dtype=np.complex128))
+        a, b = min(q0, q1), max(q0, q1)
+        if b == a + 1:
+            g = [m if q0 < q1 else S @ m @ S for m in mats]  # permutations: exact
+            self.apply(a, 2, g[0], g[1] if len(g) > 1 else None)
+            return
+        # U(8) index (x_a, x_mid, x_b): U acts on (x_q0, x_q1), the identity on x_mid
+        eye = np.eye(2)
+        g8 = []
+        for m in mats:
+            t = m.reshape(2, 2, 2, 2)  # [out q0, out q1, in q0, in q1]
+            if q0 > q1:
+                t = t.transpose(1, 0, 3, 2)  # -> [out a, out b, in a, in b]
+            g8.append(np.einsum("ikIK,jJ->ijkIJK", t, eye).reshape(8, 8))
+        for p in range(b - 1, a + 1, -1):
+            self.apply(p, 2, S)
+        self.apply(a, 3, g8[0], g8[1] if len(g8) > 1 else None)
+        for p in range(a + 2, b):
+            self.apply(p, 2, S)
+
     def bond_dim(self, bond: int) -> int:
         return int(_load().omps_bond_dim(self._h, bond))
 
