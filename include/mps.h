@@ -126,6 +126,22 @@ int mps_apply_gate(mps_handle h, int first, int k, const double* U);
  * handle U_lo is ignored. */
 int mps_apply_gate_dd(mps_handle h, int first, int k, const double* U_hi, const double* U_lo);
 
+/* Two-qubit gate on any two distinct qubits q0, q1 (the paper's applyU(U, q0, q1);
+ * its Section 3.2 example applies CNOT to qubits 0 and 2).  U is 4 x 4 (2 * 16
+ * doubles, see Conventions); the first (most significant) bit of its index belongs
+ * to q0.  Adjacent qubits: one U(4) update on min(q0, q1), with U's qubits
+ * exchanged when q0 > q1.  Otherwise, with a = min(q0, q1), b = max(q0, q1): SWAP
+ * updates on sites (b-1, b), (b-2, b-1), ..., (a+2, a+3) carry qubit b's state to
+ * site a+2, one U(8) update on sites a..a+2 applies U to the two outer sites (the
+ * identity on site a+1), and SWAP updates on (a+2, a+3), ..., (b-1, b) carry it
+ * back: 2 (b - a - 2) + 1 updates, each truncated like any other.  The input is
+ * copied before return.  Errors: MPS_EINVAL (q0 == q1, a qubit outside [0, n),
+ * U NULL), MPS_ENONFINITE, and those of mps_apply_gates. */
+int mps_apply_gate2(mps_handle h, int q0, int q1, const double* U);
+
+/* Double-double form of mps_apply_gate2 (U = U_hi + U_lo); U_lo ignored on FP64. */
+int mps_apply_gate2_dd(mps_handle h, int q0, int q1, const double* U_hi, const double* U_lo);
+
 /* Apply `count` gates in order.  The library's scheduler admits a gate as soon as
  * none of its sites is held by an unfinished update and no earlier, still
  * waiting gate touches them; admitted updates iterate together, one batched

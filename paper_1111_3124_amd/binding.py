@@ -55,6 +55,8 @@ _lib.mps_destroy.argtypes = [_h]
 _lib.mps_apply_gate.argtypes = [_h, C.c_int, C.c_int, _dp]
 _lib.mps_apply_gate_dd.argtypes = [_h, C.c_int, C.c_int, _dp, _dp]
 _lib.mps_apply_gates.argtypes = [_h, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), _dp, _dp]
+_lib.mps_apply_gate2.argtypes = [_h, C.c_int, C.c_int, _dp]
+_lib.mps_apply_gate2_dd.argtypes = [_h, C.c_int, C.c_int, _dp, _dp]
 _lib.mps_bond_dim.argtypes = [_h, C.c_int, C.POINTER(C.c_int)]
 _lib.mps_schmidt.argtypes = [_h, C.c_int, _dp, C.c_int, C.POINTER(C.c_int)]
 _lib.mps_schmidt_dd.argtypes = [_h, C.c_int, _dp, _dp, C.c_int, C.POINTER(C.c_int)]
@@ -86,7 +88,7 @@ _lib.mps_batch_last_error.argtypes = [_b]
 _lib.mps_batch_destroy.argtypes = [_b]
 
 EXPORTED = ["mps_create", "mps_create_ex", "mps_destroy", "mps_apply_gate", "mps_apply_gate_dd",
-            "mps_apply_gates", "mps_bond_dim", "mps_schmidt", "mps_schmidt_dd", "mps_amplitude",
+            "mps_apply_gates", "mps_apply_gate2", "mps_apply_gate2_dd", "mps_bond_dim", "mps_schmidt", "mps_schmidt_dd", "mps_amplitude",
             "mps_amplitude_dd", "mps_amplitudes", "mps_stats", "mps_load", "mps_get_site",
             "mps_set_option", "mps_sync", "mps_kernel_time", "mps_last_error", "mps_version",
             "mps_rdo", "mps_rdo_dd", "mps_rdo_block", "mps_batch_create", "mps_batch_run", "mps_batch_get", "mps_batch_set_option",
@@ -145,6 +147,17 @@ def mps_apply_gate(h, first: int, k: int, U) -> int:
 def mps_apply_gate_dd(h, first: int, k: int, U_hi, U_lo) -> int:
     uh, ul = _gate_doubles(U_hi, k), _gate_doubles(U_lo, k)
     return _check(h, _lib.mps_apply_gate_dd(h, first, k, _ptr(uh), _ptr(ul)))
+
+
+def mps_apply_gate2(h, q0: int, q1: int, U) -> int:
+    """Two-qubit gate on any two distinct qubits (U's first index bit is q0)."""
+    u = _gate_doubles(U, 2)
+    return _check(h, _lib.mps_apply_gate2(h, q0, q1, _ptr(u)))
+
+
+def mps_apply_gate2_dd(h, q0: int, q1: int, U_hi, U_lo) -> int:
+    uh, ul = _gate_doubles(U_hi, 2), _gate_doubles(U_lo, 2)
+    return _check(h, _lib.mps_apply_gate2_dd(h, q0, q1, _ptr(uh), _ptr(ul)))
 
 
 def _pack(gates):
@@ -381,6 +394,12 @@ class MPS:
 
     def apply_gate(self, g):
         return self.apply(g.first, g.k, g.u_hi, getattr(g, "u_lo", None))
+
+    def apply_gate2(self, q0, q1, u_hi, u_lo=None):
+        """U(4) on qubits q0 and q1, adjacent or not (SWAP routing in the library)."""
+        if u_lo is not None:
+            return mps_apply_gate2_dd(self.h, q0, q1, u_hi, u_lo)
+        return mps_apply_gate2(self.h, q0, q1, u_hi)
 
     def apply_gates(self, gates, allow_noconv=False):
         return mps_apply_gates(self.h, gates, allow_noconv)

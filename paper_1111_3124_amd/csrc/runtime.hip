@@ -1169,6 +1169,42 @@ int set_option(Engine* E, int prec, int key, double value, std::string* err) {
 }  // namespace
 
 // ====================================================================== C ABI
+// helpers of mps_apply_gate2 (non-adjacent gates)
+namespace {
+
+// entry (r, c) of a 4 x 4 complex row-major matrix, as doubles
+inline double& at4(double* u, int r, int c, int part) { return u[(r * 4 + c) * 2 + part]; }
+
+void swap_gate(double* u) {  // |xy> -> |yx>
+  std::memset(u, 0, sizeof(double) * 32);
+  at4(u, 0, 0, 0) = at4(u, 1, 2, 0) = at4(u, 2, 1, 0) = at4(u, 3, 3, 0) = 1.0;
+}
+
+// U with its two qubits exchanged: U'[(y x), (y' x')] = U[(x y), (x' y')]
+void reversed_gate(const double* u, double* out) {
+  auto sw = [](int i) { return ((i & 1) << 1) | (i >> 1); };
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c)
+      for (int part = 0; part < 2; ++part) out[(sw(r) * 4 + sw(c)) * 2 + part] = u[(r * 4 + c) * 2 + part];
+}
+
+// U acting on window positions p0 (its first qubit) and p1 of three sites (position 0
+// = the window's first site = the most significant bit), identity on the third.
+void outer_gate8(const double* u, int p0, int p1, double* out) {
+  std::memset(out, 0, sizeof(double) * 128);
+  const int pm = 3 - p0 - p1;
+  auto bit = [](int x, int p) { return (x >> (2 - p)) & 1; };
+  for (int r = 0; r < 8; ++r)
+    for (int c = 0; c < 8; ++c) {
+      if (bit(r, pm) != bit(c, pm)) continue;
+      const int ur = bit(r, p0) * 2 + bit(r, p1), uc = bit(c, p0) * 2 + bit(c, p1);
+      out[(r * 8 + c) * 2] = u[(ur * 4 + uc) * 2];
+      out[(r * 8 + c) * 2 + 1] = u[(ur * 4 + uc) * 2 + 1];
+    }
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* mps_version(void) { return "mps-mi355x 0.2 (gfx950)"; }
@@ -1246,6 +1282,58 @@ int mps_apply_gates(mps_handle h, int count, const int* first, const int* k, con
 
 int mps_apply_gate(mps_handle h, int first, int k, const double* U) {
   return mps_apply_gates(h, 1, &first, &k, U, nullptr);
+}
+
+
+// ------------------------------------------------------------------ non-adjacent gates
+// A two-qubit gate on qubits q0, q1 (U's first index bit is q0).  Adjacent qubits
+// take one U(4) update (U conjugated by SWAP when q0 > q1: an index permutation).
+// Otherwise, with a < b the two qubits: SWAP updates carry qubit b's state from
+// site b to site a + 2, one U(8) update on sites a..a+2 applies U to the outer
+// sites (identity on the middle one), and SWAP updates carry it back.  All gates
+// go to the scheduler as one list; each update is truncated like any other.
+int mps_apply_gate2_dd(mps_handle h, int q0, int q1, const double* U_hi, const double* U_lo) {
+  if (!h) return MPS_EINVAL;
+  if (q0 < 0 || q1 < 0 || q0 >= h->n || q1 >= h->n || q0 == q1)
+    return fail(h, MPS_EINVAL, "qubits must be distinct and in [0, n)");
+  if (!U_hi) return fail(h, MPS_EINVAL, "null gate matrix");
+  const bool dd = h->prec == MPS_PREC_DD;
+  const double* lo_in = dd ? U_lo : nullptr;
+  if (!finite_gate(2, U_hi) || (lo_in && !finite_gate(2, lo_in)))
+    return fail(h, MPS_ENONFINITE, "gate matrix has a NaN or infinite entry");
+  const int a = std::min(q0, q1), b = std::max(q0, q1);
+  const int nswap = b - a >= 2 ? b - a - 2 : 0;
+  // every matrix the list points at, hi then lo, allocated once (stable addresses)
+  const size_t n4 = 32, n8 = 128;
+  std::vector<double> hi(2 * nswap * n4 + n8 + n4), lo(hi.size(), 0.0);
+  std::vector<GateRef> gates;
+  double* sw_hi = hi.data();
+  double* sw_lo = lo.data();
+  swap_gate(sw_hi);  // one SWAP matrix serves every swap (its lo plane stays zero)
+  double* g_hi = hi.data() + n4;
+  double* g_lo = lo.data() + n4;
+  if (b == a + 1) {
+    if (q0 < q1) {
+      std::memcpy(g_hi, U_hi, sizeof(double) * n4);
+      if (lo_in) std::memcpy(g_lo, lo_in, sizeof(double) * n4);
+    } else {
+      reversed_gate(U_hi, g_hi);
+      if (lo_in) reversed_gate(lo_in, g_lo);
+    }
+    gates.push_back(GateRef{0, a, 2, g_hi, dd ? g_lo : nullptr});
+  } else {
+    const int p0 = q0 == a ? 0 : 2, p1 = 2 - p0;
+    outer_gate8(U_hi, p0, p1, g_hi);
+    if (lo_in) outer_gate8(lo_in, p0, p1, g_lo);
+    for (int p = b - 1; p >= a + 2; --p) gates.push_back(GateRef{0, p, 2, sw_hi, dd ? sw_lo : nullptr});
+    gates.push_back(GateRef{0, a, 3, g_hi, dd ? g_lo : nullptr});
+    for (int p = a + 2; p <= b - 1; ++p) gates.push_back(GateRef{0, p, 2, sw_hi, dd ? sw_lo : nullptr});
+  }
+  return run_state(h, gates);
+}
+
+int mps_apply_gate2(mps_handle h, int q0, int q1, const double* U) {
+  return mps_apply_gate2_dd(h, q0, q1, U, nullptr);
 }
 
 int mps_apply_gate_dd(mps_handle h, int first, int k, const double* U_hi, const double* U_lo) {
