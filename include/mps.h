@@ -213,6 +213,23 @@ int mps_load(mps_handle h, const int* dims, const double* const* B, const double
 /* Copy site tensor s (m_{s-1} * 2 * m_s complex) to host; lo may be NULL. */
 int mps_get_site(mps_handle h, int s, double* hi, double* lo, long cap_doubles);
 
+/* --- checkpoint and resume --------------------------------------------------------- */
+
+/* Write the state as a self-contained byte image into buf (cap bytes): n, chi_max,
+ * eps, precision, the bond dims, every bond's Schmidt values and every site tensor
+ * (lo planes included on dd handles), then a 64-bit FNV-1a hash of the image.
+ * *size receives the image size; with buf NULL only the size is computed.  Engine
+ * options are not part of the image.  Synchronises the handle's stream.
+ * Errors: MPS_EINVAL (h or size NULL), MPS_ERANGE (cap too small), MPS_EDEVICE. */
+int mps_export(mps_handle h, void* buf, long cap, long* size);
+
+/* A new handle holding the state of an image written by mps_export (of this or
+ * another process), with the image's n, chi_max, eps and precision, on hip_stream
+ * (NULL: a stream of its own).  Applying the same gates to it and to the exported
+ * handle gives bit-identical results.  NULL on error (bad magic, version, header,
+ * size or hash); the message is mps_last_error(NULL).  The caller keeps buf. */
+mps_handle mps_import(const void* buf, long size, void* hip_stream);
+
 /* --- control --------------------------------------------------------------------- */
 
 /* Options (enum mps_option) apply to the handle's engine: for a member of a

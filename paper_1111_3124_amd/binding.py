@@ -57,6 +57,9 @@ _lib.mps_apply_gate_dd.argtypes = [_h, C.c_int, C.c_int, _dp, _dp]
 _lib.mps_apply_gates.argtypes = [_h, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), _dp, _dp]
 _lib.mps_apply_gate2.argtypes = [_h, C.c_int, C.c_int, _dp]
 _lib.mps_apply_gate2_dd.argtypes = [_h, C.c_int, C.c_int, _dp, _dp]
+_lib.mps_export.argtypes = [_h, C.c_void_p, C.c_long, C.POINTER(C.c_long)]
+_lib.mps_import.restype = _h
+_lib.mps_import.argtypes = [C.c_void_p, C.c_long, C.c_void_p]
 _lib.mps_bond_dim.argtypes = [_h, C.c_int, C.POINTER(C.c_int)]
 _lib.mps_schmidt.argtypes = [_h, C.c_int, _dp, C.c_int, C.POINTER(C.c_int)]
 _lib.mps_schmidt_dd.argtypes = [_h, C.c_int, _dp, _dp, C.c_int, C.POINTER(C.c_int)]
@@ -90,6 +93,7 @@ _lib.mps_batch_destroy.argtypes = [_b]
 EXPORTED = ["mps_create", "mps_create_ex", "mps_destroy", "mps_apply_gate", "mps_apply_gate_dd",
             "mps_apply_gates", "mps_apply_gate2", "mps_apply_gate2_dd", "mps_bond_dim", "mps_schmidt", "mps_schmidt_dd", "mps_amplitude",
             "mps_amplitude_dd", "mps_amplitudes", "mps_stats", "mps_load", "mps_get_site",
+            "mps_export", "mps_import",
             "mps_set_option", "mps_sync", "mps_kernel_time", "mps_last_error", "mps_version",
             "mps_rdo", "mps_rdo_dd", "mps_rdo_block", "mps_batch_create", "mps_batch_run", "mps_batch_get", "mps_batch_set_option",
             "mps_batch_last_error", "mps_batch_destroy"]
@@ -137,6 +141,24 @@ def mps_create_ex(n: int, chi_max: int, eps: float, prec: int = MPS_PREC_FP64, h
 
 def mps_destroy(h) -> int:
     return _lib.mps_destroy(h)
+
+
+def mps_export(h) -> bytes:
+    """The state as a checkpoint image (bytes)."""
+    size = C.c_long(0)
+    _check(h, _lib.mps_export(h, None, 0, C.byref(size)))
+    buf = C.create_string_buffer(size.value)
+    _check(h, _lib.mps_export(h, buf, size.value, C.byref(size)))
+    return buf.raw[: size.value]
+
+
+def mps_import(image: bytes, hip_stream=None):
+    """A new handle from a checkpoint image written by mps_export."""
+    buf = C.create_string_buffer(bytes(image), len(image))
+    h = _lib.mps_import(buf, len(image), hip_stream)
+    if not h:
+        raise MPSError(MPS_EINVAL, mps_last_error(None))
+    return h
 
 
 def mps_apply_gate(h, first: int, k: int, U) -> int:
@@ -370,6 +392,23 @@ class MPS:
         if self.h and self._owned:
             mps_destroy(self.h)
         self.h = None
+
+    def export(self) -> bytes:
+        """Checkpoint image of the state (mps_export)."""
+        return mps_export(self.h)
+
+    @classmethod
+    def from_image(cls, image: bytes) -> "MPS":
+        """Resume from a checkpoint image (mps_import); n, chi_max, eps and the
+        precision come from the image."""
+        import struct
+        _, n, chi, prec = struct.unpack_from("<4i", image, 8)
+        (eps,) = struct.unpack_from("<d", image, 24)
+        m = cls.__new__(cls)
+        m.n, m.chi_max, m.eps, m.prec = n, chi, eps, prec
+        m._owned = True
+        m.h = mps_import(image)
+        return m
 
     def __del__(self):
         try:

@@ -1644,6 +1644,149 @@ int mps_get_site(mps_handle h, int s, double* hi, double* lo, long cap_doubles) 
   return MPS_OK;
 }
 
+// ------------------------------------------------------------------ checkpoint image
+// Layout (little-endian): magic "MPSCKPT1" | int32 version, n, chi_max, prec |
+// double eps | int32 dims[n + 1] (padded to 8 bytes) | per bond 0..n-2 the Schmidt
+// values (hi, then lo on dd) | per site the tensor [alpha][i][beta] as interleaved
+// complex (hi, then lo on dd) | uint64 FNV-1a hash of everything before it.
+namespace {
+
+constexpr char kCkptMagic[8] = {'M', 'P', 'S', 'C', 'K', 'P', 'T', '1'};
+constexpr int kCkptVersion = 1;
+
+uint64_t fnv1a(const unsigned char* p, size_t n) {
+  uint64_t h = 1469598103934665603ull;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+size_t ckpt_size(int n, int prec, const std::vector<int>& dims) {
+  const size_t P = prec == MPS_PREC_DD ? 2 : 1;
+  size_t b = 8 + 4 * 4 + 8 + ((size_t)(n + 1) * 4 + 7) / 8 * 8;
+  for (int s = 1; s < n; ++s) b += P * 8 * (size_t)dims[s];
+  for (int s = 0; s < n; ++s) b += P * 16 * (size_t)dims[s] * 2 * dims[s + 1];
+  return b + 8;
+}
+
+}  // namespace
+
+int mps_export(mps_handle h, void* buf, long cap, long* size) {
+  if (!h || !size) return MPS_EINVAL;
+  const size_t need = ckpt_size(h->n, h->prec, h->dimx);
+  *size = (long)need;
+  if (!buf) return MPS_OK;
+  if (cap < (long)need) return fail(h, MPS_ERANGE, "checkpoint buffer too small");
+  const bool dd = h->prec == MPS_PREC_DD;
+  unsigned char* p = (unsigned char*)buf;
+  size_t o = 0;
+  auto put = [&](const void* src, size_t n) {
+    std::memcpy(p + o, src, n);
+    o += n;
+  };
+  put(kCkptMagic, 8);
+  const int hdr[4] = {kCkptVersion, h->n, h->chi, h->prec};
+  put(hdr, sizeof(hdr));
+  put(&h->eps, 8);
+  put(h->dimx.data(), sizeof(int) * (h->n + 1));
+  while (o % 8) p[o++] = 0;
+  for (int b = 0; b + 1 < h->n; ++b) {
+    const int m = h->dimx[b + 1];
+    int got = 0;
+    double* hi = (double*)(p + o);
+    double* lo = dd ? hi + m : nullptr;
+    const int rc = mps_schmidt_dd(h, b, hi, lo, m, &got);
+    if (rc) return rc;
+    o += (dd ? 2 : 1) * 8 * (size_t)m;
+  }
+  for (int s = 0; s < h->n; ++s) {
+    const long nd = (long)h->dimx[s] * 2 * h->dimx[s + 1] * 2;
+    double* hi = (double*)(p + o);
+    double* lo = dd ? hi + nd : nullptr;
+    const int rc = mps_get_site(h, s, hi, lo, nd);
+    if (rc) return rc;
+    o += (dd ? 2 : 1) * 8 * (size_t)nd;
+  }
+  const uint64_t hsh = fnv1a(p, o);
+  put(&hsh, 8);
+  return o == need ? MPS_OK : fail(h, MPS_EDEVICE, "checkpoint size mismatch");
+}
+
+mps_handle mps_import(const void* buf, long size, void* hip_stream) {
+  g_create_error.clear();
+  const unsigned char* p = (const unsigned char*)buf;
+  auto bad = [](const char* why) -> mps_handle {
+    g_create_error = std::string("mps_import: ") + why;
+    return nullptr;
+  };
+  if (!p || size < 48) return bad("no image");
+  if (std::memcmp(p, kCkptMagic, 8) != 0) return bad("not a checkpoint image");
+  int hdr[4];
+  std::memcpy(hdr, p + 8, sizeof(hdr));
+  if (hdr[0] != kCkptVersion) return bad("unknown image version");
+  const int n = hdr[1], chi = hdr[2], prec = hdr[3];
+  if (n < 1 || n > (1 << 20) || chi < 1 || (prec != MPS_PREC_FP64 && prec != MPS_PREC_DD)) return bad("bad header");
+  double eps;
+  std::memcpy(&eps, p + 24, 8);
+  if ((size_t)size < 32 + ((size_t)(n + 1) * 4 + 7) / 8 * 8 + 8) return bad("image truncated");
+  std::vector<int> dims(n + 1);
+  std::memcpy(dims.data(), p + 32, sizeof(int) * (n + 1));
+  if (dims[0] != 1 || dims[n] != 1) return bad("bad bond dims");
+  for (int s = 1; s < n; ++s)
+    if (dims[s] < 1 || dims[s] > chi) return bad("bad bond dims");
+  const size_t need = ckpt_size(n, prec, dims);
+  if ((size_t)size != need) return bad("image size does not match its header");
+  uint64_t hsh;
+  std::memcpy(&hsh, p + need - 8, 8);
+  if (fnv1a(p, need - 8) != hsh) return bad("checksum mismatch");
+  mps_handle h = mps_create_ex(n, chi, eps, prec, hip_stream);
+  if (!h) return nullptr;
+  const bool dd = prec == MPS_PREC_DD;
+  const size_t P = dd ? 2 : 1;
+  size_t o = 32 + ((size_t)(n + 1) * 4 + 7) / 8 * 8;
+  // the image's arrays may be unaligned for double: copy them out
+  std::vector<std::vector<double>> lh(n), ll(n), bh(n), bl(n);
+  for (int b = 0; b + 1 < n; ++b) {
+    const int m = dims[b + 1];
+    lh[b].resize(m);
+    std::memcpy(lh[b].data(), p + o, 8 * (size_t)m);
+    if (dd) {
+      ll[b].resize(m);
+      std::memcpy(ll[b].data(), p + o + 8 * (size_t)m, 8 * (size_t)m);
+    }
+    o += P * 8 * (size_t)m;
+  }
+  for (int s = 0; s < n; ++s) {
+    const size_t nd = (size_t)dims[s] * 2 * dims[s + 1] * 2;
+    bh[s].resize(nd);
+    std::memcpy(bh[s].data(), p + o, 8 * nd);
+    if (dd) {
+      bl[s].resize(nd);
+      std::memcpy(bl[s].data(), p + o + 8 * nd, 8 * nd);
+    }
+    o += P * 8 * nd;
+  }
+  std::vector<const double*> Bp(n), Blp(n), lp(std::max(1, n - 1)), llp(std::max(1, n - 1));
+  for (int s = 0; s < n; ++s) {
+    Bp[s] = bh[s].data();
+    Blp[s] = dd ? bl[s].data() : nullptr;
+  }
+  for (int b = 0; b + 1 < n; ++b) {
+    lp[b] = lh[b].data();
+    llp[b] = dd ? ll[b].data() : nullptr;
+  }
+  const int rc = mps_load(h, dims.data() + 1, Bp.data(), dd ? Blp.data() : nullptr, lp.data(),
+                          dd ? llp.data() : nullptr);
+  if (rc) {
+    g_create_error = std::string("mps_import: ") + h->err;
+    mps_destroy(h);
+    return nullptr;
+  }
+  return h;
+}
+
 int mps_set_option(mps_handle h, int key, double value) {
   if (!h) return MPS_EINVAL;
   return set_option(h->E, h->prec, key, value, &h->err);
