@@ -75,9 +75,16 @@ enum mps_option {
   MPS_OPT_DD_REFINE = 9,      /* dd: 1 (default) simultaneous first-order corrections,
                                  then the pairwise polish only where those do not apply;
                                  0: the pairwise dd Jacobi polish alone                  */
-  MPS_OPT_JACOBI_STREAMS = 10 /* 2 (default): the FP64 Jacobi steps of concurrent updates
+  MPS_OPT_JACOBI_STREAMS = 10,/* 2 (default): the FP64 Jacobi steps of concurrent updates
                                  run as two launch sequences on two internal streams,
                                  joined into the handle's stream; 1: one sequence        */
+  MPS_OPT_FUSE = 11           /* 1 (default): mps_apply_gates and mps_batch_run multiply
+                                 a single-site gate into the latest earlier gate
+                                 touching its site, and latest earlier single-site
+                                 gates into a later gate on their sites (products in
+                                 double-double; the same state up to rounding, since a
+                                 one-site unitary keeps every cut's Schmidt values);
+                                 multi-site gates are never merged.  0: off             */
 };
 
 /* Diagnostics of the most recent split (the last one of a three-qubit gate). */

@@ -21,6 +21,7 @@
 
 #include "../../include/mps.h"
 #include "common.h"
+#include "dd.h"
 #include "dd_kernels.h"
 #include "ddref.h"
 #include "kernels3.h"
@@ -88,6 +89,7 @@ struct Engine {
   hipStream_t stream2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int jacobi_streams = 2;
+  bool fuse = true;  // mps_apply_gates multiplies contained gates into one another
   int device = 0;
   bool batch = false;  // a batch engine sizes workspace per update, not per slot
   // options (shared by every state of the engine)
@@ -1149,6 +1151,10 @@ int set_option(Engine* E, int prec, int key, double value, std::string* err) {
       if (!(value >= 1 && value <= 65536)) return fail(err, MPS_EINVAL, "slot limit out of range");
       E->max_slots = (int)value;
       return MPS_OK;
+    case MPS_OPT_FUSE:
+      if (!(value == 0 || value == 1)) return fail(err, MPS_EINVAL, "fusion switch must be 0 or 1");
+      E->fuse = value != 0;
+      return MPS_OK;
     case MPS_OPT_JACOBI_STREAMS:
       if (!(value == 1 || value == 2)) return fail(err, MPS_EINVAL, "Jacobi stream count must be 1 or 2");
       E->jacobi_streams = (int)value;
@@ -1169,6 +1175,148 @@ int set_option(Engine* E, int prec, int key, double value, std::string* err) {
 }  // namespace
 
 // ====================================================================== C ABI
+// ------------------------------------------------------------------ gate fusion
+// Scanning a gate list in order: a single-site gate whose site lies inside the
+// latest earlier gate touching it is multiplied into that gate (it acts after it:
+// U' = G U, G embedded in U's window); latest earlier single-site gates on sites of
+// a new gate are multiplied into it (U' = U F) and leave the list.  The gates in
+// between act on other sites and commute with the moved one, and a unitary on one
+// site of a window leaves the Schmidt values of every cut of the window unchanged,
+// so truncation picks the same subspace: the state is the same up to rounding.
+// (Multi-site gates are never merged: truncating once after their product is not
+// truncating after each.)  Each fusion saves a single-site launch.  The products
+// are formed in double-double (and rounded to binary64 for FP64 handles).
+namespace {
+
+struct FGate {
+  int first, k;
+  std::vector<dd::ddr> re, im;  // 4^k entries, row-major
+  long pos = 0;                 // list position of the gate that holds this slot
+};
+
+FGate fgate_from(int first, int k, const double* hi, const double* lo, long pos) {
+  FGate g{first, k, {}, {}, pos};
+  const int n = 1 << (2 * k);
+  g.re.resize(n);
+  g.im.resize(n);
+  for (int e = 0; e < n; ++e) {
+    g.re[e] = dd::ddr{hi[2 * e], lo ? lo[2 * e] : 0.0};
+    g.im[e] = dd::ddr{hi[2 * e + 1], lo ? lo[2 * e + 1] : 0.0};
+  }
+  return g;
+}
+
+// g (k_g sites from g.first) as a 2^K x 2^K matrix on the window of K sites from w0
+FGate fgate_embed(const FGate& g, int w0, int K) {
+  FGate e{w0, K, {}, {}, g.pos};
+  const int D = 1 << K, off = g.first - w0, kg = g.k;
+  e.re.assign((size_t)D * D, dd::ddr{0.0, 0.0});
+  e.im.assign((size_t)D * D, dd::ddr{0.0, 0.0});
+  const int sh = K - off - kg, mask = ((1 << kg) - 1) << sh;
+  for (int r = 0; r < D; ++r)
+    for (int c = 0; c < D; ++c) {
+      if ((r & ~mask) != (c & ~mask)) continue;
+      const int gr = (r & mask) >> sh, gc = (c & mask) >> sh;
+      e.re[(size_t)r * D + c] = g.re[(size_t)gr * (1 << kg) + gc];
+      e.im[(size_t)r * D + c] = g.im[(size_t)gr * (1 << kg) + gc];
+    }
+  return e;
+}
+
+// a * b (same window), complex double-double
+FGate fgate_mul(const FGate& a, const FGate& b) {
+  FGate c{a.first, a.k, {}, {}, a.pos};
+  const int D = 1 << a.k;
+  c.re.resize((size_t)D * D);
+  c.im.resize((size_t)D * D);
+  for (int r = 0; r < D; ++r)
+    for (int j = 0; j < D; ++j) {
+      dd::ddr sr{0.0, 0.0}, si{0.0, 0.0};
+      for (int t = 0; t < D; ++t) {
+        const dd::ddr ar = a.re[(size_t)r * D + t], ai = a.im[(size_t)r * D + t];
+        const dd::ddr br = b.re[(size_t)t * D + j], bi = b.im[(size_t)t * D + j];
+        sr = dd::add(sr, dd::add(dd::mul(ar, br), dd::neg(dd::mul(ai, bi))));
+        si = dd::add(si, dd::add(dd::mul(ar, bi), dd::mul(ai, br)));
+      }
+      c.re[(size_t)r * D + j] = sr;
+      c.im[(size_t)r * D + j] = si;
+    }
+  return c;
+}
+
+bool overlaps(const FGate& a, const FGate& b) { return a.first < b.first + b.k && b.first < a.first + a.k; }
+bool contains(const FGate& outer, const FGate& inner) {
+  return outer.first <= inner.first && inner.first + inner.k <= outer.first + outer.k;
+}
+
+std::vector<FGate> fuse_gates(std::vector<FGate> in) {
+  std::vector<FGate> out;
+  for (FGate& g : in) {
+    bool absorbed = false;
+    while (true) {
+      int f = (int)out.size() - 1;
+      while (f >= 0 && !overlaps(out[f], g)) --f;
+      if (f < 0) break;
+      if (g.k == 1 && contains(out[f], g)) {  // g acts after out[f]
+        const long keep = out[f].pos;
+        out[f] = fgate_mul(fgate_embed(g, out[f].first, out[f].k), out[f]);
+        out[f].pos = keep;
+        absorbed = true;
+        break;
+      }
+      if (out[f].k == 1 && contains(g, out[f])) {  // out[f] acts before g: fold it in, look again
+        const long keep = g.pos;
+        g = fgate_mul(g, fgate_embed(out[f], g.first, g.k));
+        g.pos = keep;
+        out.erase(out.begin() + f);
+        continue;
+      }
+      break;
+    }
+    if (!absorbed) out.push_back(std::move(g));
+  }
+  return out;
+}
+
+// A gate list (of one or several states), fused state by state and returned in the
+// list's order (a fused gate takes the position of the gate whose slot it holds);
+// the fused matrices live in hi / lo, which must outlive the returned list.
+std::vector<GateRef> fuse_list(const std::vector<GateRef>& gates, bool dd, std::vector<double>& hi,
+                               std::vector<double>& lo) {
+  if (gates.size() < 2) return gates;
+  std::map<int, std::vector<FGate>> per;
+  for (size_t i = 0; i < gates.size(); ++i)
+    per[gates[i].unit].push_back(fgate_from(gates[i].first, gates[i].k, gates[i].U, gates[i].Ulo, (long)i));
+  std::vector<FGate> fg;
+  for (auto& kv : per)
+    for (FGate& g : fuse_gates(std::move(kv.second))) fg.push_back(std::move(g));
+  if (fg.size() == gates.size()) return gates;
+  std::sort(fg.begin(), fg.end(), [](const FGate& x, const FGate& y) { return x.pos < y.pos; });
+  size_t total = 0;
+  for (const FGate& g : fg) total += (size_t)2 << (2 * g.k);
+  hi.assign(total, 0.0);
+  lo.assign(dd ? total : 0, 0.0);
+  std::vector<GateRef> fused;
+  fused.reserve(fg.size());
+  size_t o = 0;
+  for (const FGate& g : fg) {
+    const int ne = 1 << (2 * g.k);
+    for (int e = 0; e < ne; ++e) {
+      hi[o + 2 * e] = g.re[e].hi;
+      hi[o + 2 * e + 1] = g.im[e].hi;
+      if (dd) {
+        lo[o + 2 * e] = g.re[e].lo;
+        lo[o + 2 * e + 1] = g.im[e].lo;
+      }
+    }
+    fused.push_back(GateRef{gates[g.pos].unit, g.first, g.k, hi.data() + o, dd ? lo.data() + o : nullptr});
+    o += (size_t)2 * ne;
+  }
+  return fused;
+}
+
+}  // namespace
+
 // helpers of mps_apply_gate2 (non-adjacent gates)
 namespace {
 
@@ -1277,7 +1425,9 @@ int mps_apply_gates(mps_handle h, int count, const int* first, const int* k, con
     gates.push_back(GateRef{0, first[i], k[i], U + off, lo});
     off += (size_t)2 << (2 * k[i]);
   }
-  return run_state(h, gates);
+  if (!h->E->fuse) return run_state(h, gates);
+  std::vector<double> hi, lo;
+  return run_state(h, fuse_list(gates, dd, hi, lo));
 }
 
 int mps_apply_gate(mps_handle h, int first, int k, const double* U) {
@@ -1912,7 +2062,9 @@ int mps_batch_run(mps_batch_handle b, long ngates, const int* circuit, const int
     dims_off.push_back(o);
     o += h->n + 1;
   }
-  return run_sched(b->E, b->units, b->d_dims, b->dims_total, dims_off, gates, &b->err);
+  if (!b->E->fuse) return run_sched(b->E, b->units, b->d_dims, b->dims_total, dims_off, gates, &b->err);
+  std::vector<double> hi, lo;  // fusion circuit by circuit, the list's order kept
+  return run_sched(b->E, b->units, b->d_dims, b->dims_total, dims_off, fuse_list(gates, dd, hi, lo), &b->err);
 }
 
 int mps_batch_set_option(mps_batch_handle b, int key, double value) {
