@@ -78,13 +78,18 @@ enum mps_option {
   MPS_OPT_JACOBI_STREAMS = 10,/* 2 (default): the FP64 Jacobi steps of concurrent updates
                                  run as two launch sequences on two internal streams,
                                  joined into the handle's stream; 1: one sequence        */
-  MPS_OPT_FUSE = 11           /* 1 (default): mps_apply_gates and mps_batch_run multiply
+  MPS_OPT_FUSE = 11,          /* 1 (default): mps_apply_gates and mps_batch_run multiply
                                  a single-site gate into the latest earlier gate
                                  touching its site, and latest earlier single-site
                                  gates into a later gate on their sites (products in
                                  double-double; the same state up to rounding, since a
                                  one-site unitary keeps every cut's Schmidt values);
                                  multi-site gates are never merged.  0: off             */
+  MPS_OPT_QR = 12             /* 1 (default): two-site Jacobi problems with 64 <= N and
+                                 M <= 1024 (dd: square only) are preconditioned by a
+                                 Householder QR of theta_w with its columns in norm
+                                 order, and the Jacobi runs on R^H (fewer sweeps);
+                                 0: the Jacobi runs on theta_w                           */
 };
 
 /* Diagnostics of the most recent split (the last one of a three-qubit gate). */

@@ -96,6 +96,17 @@ struct Task2 {
   const double2* U8_lo;
   double2* T1;          // scratch: B_s B_{s+1} as (4a x c), column-major
   double2* T1_lo;
+  // the Jacobi step's operands: W (JR x N, column-major) and, when jvec, V (N x N);
+  // W = thw, V = V, JR = JM unless the problem is preconditioned by QR
+  double2* JW;
+  double2* JV;
+  int JR, jvec;
+  // QR preconditioning (qr = 1): column order, reflector heads, scales, panel factors
+  int qr;
+  int* qperm;
+  double2* qvd;
+  double* qt;
+  double2* qT;
 };
 
 // One entry of a launch list: the task slot a block row works on and, for the

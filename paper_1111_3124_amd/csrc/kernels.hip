@@ -261,7 +261,7 @@ __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* en
   static_assert(W2 == 8 || W2 == 16 || W2 == 32, "block width");
   const Task2& T = tasks[ents[blockIdx.y].slot];
   const int sweep = ents[blockIdx.y].sweep;
-  const int N = T.N, M = T.JM;
+  const int N = T.N, M = T.JR;
   const int nb = (N + BW - 1) / BW;
   const int nbp = nb + (nb & 1);
   const int pi = blockIdx.x;
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* en
   __syncthreads();
 
   // 1. Gram
-  const double2* __restrict__ A = T.thw;
+  const double2* __restrict__ A = T.JW;
   const int wave = tid >> 6, lane = tid & 63;
   if constexpr (W2 == 16) {
     // by MFMA over k-steps of 4 rows, wave w taking k-steps w, w + NW, ...: lane l
@@ -411,9 +411,10 @@ __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* en
   const int res_rot = L.any_rot;
   if (clk) phase_clock[2] = wall_clock64();
 
-  // 3. A_P <- A_P R and V_P <- V_P R over the JM + N rows (W's, then V's)
+  // 3. A_P <- A_P R and V_P <- V_P R over the JR + N rows (W's, then V's; W's alone
+  //    when V is not accumulated)
   if (res_rot) {
-    const int total = M + N;
+    const int total = M + (T.jvec ? N : 0);
     {
       const double2(*R)[W2 + 1] = Rb[cur];
       for (int r0 = 0; r0 < total; r0 += NT * RPT) {
@@ -422,7 +423,7 @@ __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* en
         for (int k = 0; k < RPT; ++k) {
           const int rr = r0 + tid + NT * k;
           const bool inA = rr < M;
-          const double2* X = inA ? T.thw : T.V;
+          const double2* X = inA ? T.JW : T.JV;
           const int rows = inA ? M : N;
           const int r = inA ? rr : rr - M;
 #pragma unroll
@@ -434,7 +435,7 @@ __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* en
           const int rr = r0 + tid + NT * k;
           if (rr >= total) continue;
           const bool inA = rr < M;
-          double2* X = inA ? T.thw : T.V;
+          double2* X = inA ? T.JW : T.JV;
           const int rows = inA ? M : N;
           const int r = inA ? rr : rr - M;
 #pragma unroll 4
@@ -499,6 +500,25 @@ __global__ __launch_bounds__(1024) void k_jacobi_order(Task2* tasks, const Ent* 
   __syncthreads();
   bitonic_desc(key, idx, P);
   for (int j = threadIdx.x; j < N; j += blockDim.x) T.perm[j] = idx[j];
+}
+
+// Column order of a QR-preconditioned task: theta_w's columns by descending norm
+// (sig2 holds their squared norms), into qperm.
+__global__ __launch_bounds__(1024) void k_qr_order(Task2* tasks, const Ent* ents) {
+  Task2& T = tasks[ents[blockIdx.x].slot];
+  if (!T.qr) return;
+  const int N = T.N;
+  int P = 1;
+  while (P < N) P <<= 1;
+  __shared__ double key[kMaxSort];
+  __shared__ int idx[kMaxSort];
+  for (int j = threadIdx.x; j < P; j += blockDim.x) {
+    key[j] = j < N ? fmax(T.sig2[j], 0.0) : -1.0;
+    idx[j] = j;
+  }
+  __syncthreads();
+  bitonic_desc(key, idx, P);
+  for (int j = threadIdx.x; j < N; j += blockDim.x) T.qperm[j] = idx[j];
 }
 
 // ------------------------------------------------------------------ truncation
@@ -734,6 +754,12 @@ hipError_t launch_jacobi_step(Task2* d_tasks, const Ent* d_ents, int nent, int m
                                    phase_clock); break;
     default: return hipErrorInvalidValue;
   }
+  MPS_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_qr_order(Task2* d_tasks, const Ent* d_ents, int nent, hipStream_t st) {
+  hipLaunchKernelGGL(k_qr_order, dim3(nent), dim3(1024), 0, st, d_tasks, d_ents);
   MPS_LAUNCH_CHECK();
   return hipSuccess;
 }

@@ -21,6 +21,14 @@ hipError_t launch_jacobi_step(Task2* d_tasks, const Ent* d_ents, int nent, int m
                               int maxin, hipStream_t st, long long* phase_clock = nullptr);
 // column order of each task's sweep (sorted by the previous sweep's column norms)
 hipError_t launch_jacobi_order(Task2* d_tasks, const Ent* d_ents, int nent, hipStream_t st);
+// QR preconditioning (tasks with qr set): theta_w's columns ordered by norm, the
+// blocked Householder QR in place, X = R^H into the Jacobi's W operand
+hipError_t launch_qr_order(Task2* d_tasks, const Ent* d_ents, int nent, hipStream_t st);
+hipError_t launch_qr_factor(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, int maxN, hipStream_t st);
+// after the Jacobi: the Jacobi's V (N x N) <- Q V (the left singular vectors)
+hipError_t launch_qr_left(Task2* d_tasks, const Ent* d_ents, int nent, int maxN, hipStream_t st);
+// after the truncation: Z's kept columns from the normalised columns of W, rows by qperm
+hipError_t launch_qr_z(Task2* d_tasks, const Ent* d_ents, int nent, int maxN, int maxK, hipStream_t st);
 // chi_max and eps are read from each task
 hipError_t launch_truncate(Task2* d_tasks, const Ent* d_ents, int nent, double floor_rel, hipStream_t st);
 // right = false: only B_s' (the first split of a three-site gate)

@@ -88,8 +88,13 @@ struct Engine {
   // overlap the other half's inner Jacobi
   hipStream_t stream2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // QR factorisations of newly admitted updates run on stream3, overlapping the
+  // tick's Jacobi sweep of the updates already iterating
+  hipStream_t stream3 = nullptr;
+  hipEvent_t ev_qr = nullptr;
   int jacobi_streams = 2;
-  bool fuse = true;  // mps_apply_gates multiplies contained gates into one another
+  bool fuse = true;  // mps_apply_gates multiplies single-site gates into neighbours
+  bool qr = true;   // QR preconditioning of two-site Jacobi problems
   int device = 0;
   bool batch = false;  // a batch engine sizes workspace per update, not per slot
   // options (shared by every state of the engine)
@@ -176,6 +181,7 @@ int bond_capacity(int n, int chi, int b) {
 }
 
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+constexpr int kQrMaxN = 1024;
 
 // ------------------------------------------------------------------ engines
 void engine_free(Engine* E);
@@ -196,6 +202,8 @@ Engine* engine_new(int prec, void* hip_stream, std::string* err) {
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&E->stream2, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&E->ev_fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&E->ev_join, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&E->stream3, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&E->ev_qr, hipEventDisableTiming);
   if (e != hipSuccess) {
     *err = std::string("engine: ") + hipGetErrorString(e);
     engine_free(E);
@@ -213,6 +221,11 @@ void engine_free(Engine* E) {
     (void)hipStreamSynchronize(E->stream2);
     (void)hipStreamDestroy(E->stream2);
   }
+  if (E->stream3) {
+    (void)hipStreamSynchronize(E->stream3);
+    (void)hipStreamDestroy(E->stream3);
+  }
+  if (E->ev_qr) (void)hipEventDestroy(E->ev_qr);
   if (E->ev_fork) (void)hipEventDestroy(E->ev_fork);
   if (E->ev_join) (void)hipEventDestroy(E->ev_join);
   if (E->d_phase) (void)hipFree(E->d_phase);
@@ -433,6 +446,9 @@ size_t task_ws_bytes(bool dd, int M, int Nt, int t1) {
   if (dd) b += 2 * align_up(NN * sizeof(double2)) + align_up(MN * sizeof(double2));
   b += align_up(N * sizeof(double)) * P + align_up(N * sizeof(int));
   b += align_up((size_t)t1 * sizeof(double2)) * P;
+  // QR preconditioning: order, reflector heads, scales, panel factors (16 x 16 each)
+  b += align_up(N * sizeof(int)) + align_up(N * sizeof(double2)) + align_up(N * sizeof(double)) +
+       align_up((size_t)((N + 15) / 16) * 256 * sizeof(double2));
   return b;
 }
 
@@ -484,6 +500,19 @@ void carve(bool dd, Task2& t, char* w, int* d_flags, double* d_stats, double* d_
       w += align_up(t1 * sizeof(double2));
     }
   }
+  t.qperm = (int*)w;
+  w += align_up(t.N * sizeof(int));
+  t.qvd = (double2*)w;
+  w += align_up(t.N * sizeof(double2));
+  t.qt = (double*)w;
+  w += align_up(t.N * sizeof(double));
+  t.qT = (double2*)w;
+  w += align_up((size_t)((t.N + 15) / 16) * 256 * sizeof(double2));
+  t.qr = 0;
+  t.JW = t.thw;
+  t.JV = t.V;
+  t.JR = t.JM;
+  t.jvec = 1;
   // the split's right factor: V, or for a wide theta W itself (its kept columns are
   // scaled to unit norm after the truncation)
   t.Z = t.tr ? t.thw : t.V;
@@ -491,6 +520,42 @@ void carve(bool dd, Task2& t, char* w, int* d_flags, double* d_stats, double* d_
   t.flags = d_flags + 3 * slot;
   t.stats = d_stats + 8 * slot;
   t.fro2 = d_fro + slot;
+}
+
+// QR preconditioning of a two-site task (theta_w P = Q R, Jacobi on R^H): tall or
+// square thetas with 64 <= N and M <= 1024 (the panel kernel keeps at most two rows
+// a thread), and for double-double only square ones (their refinement then runs on
+// the transposed problem from the left singular vectors Q V).  FP64: the Jacobi's W
+// is R^H in V's storage, V is not accumulated, Z is formed in theta_w's storage.
+void qr_select(bool dd, Task2& t) {
+  if (t.tr || t.N < 64 || t.M > 1024 || t.N > kQrMaxN || (dd && t.M != t.N)) return;
+  t.qr = 1;
+  t.JR = t.N;
+  if (dd) {
+    t.JW = t.aux1;
+    t.JV = t.V;
+    t.jvec = 1;
+  } else {
+    t.JW = t.V;
+    t.JV = nullptr;
+    t.jvec = 0;
+    t.Z = t.thw;
+  }
+}
+
+// a QR-preconditioned dd task after its FP64 Jacobi (V = Q V_x, the left singular
+// vectors): from here on it is refined as the transposed problem theta_w^H V = W
+void qr_to_transposed(Task2& t) {
+  t.qr = 0;
+  t.tr = 1;
+  t.JM = t.Nt;
+  t.N = t.M;
+  t.Z = t.thw;
+  t.Z_lo = t.thw_lo;
+  t.JW = t.thw;
+  t.JV = t.V;
+  t.JR = t.JM;
+  t.jvec = 1;
 }
 
 // the two-site split of state h between sites s and s+1 with bond dims a | (b) | c
@@ -573,7 +638,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
   const size_t o_u8 = o_dims + align_up(sizeof(int) * dims_total);
   const size_t o_g1 = o_u8 + align_up(sizeof(double2) * 128 * S);
   const size_t o_ents = o_g1 + align_up(sizeof(Task1) * nsites);
-  constexpr int kLists = 13;  // new2, new3, jacobi (two + order), dd, dd-enter, final, final3, mid, znorm, ref, polish
+  constexpr int kLists = 14;  // new2, new3, jacobi (two + order), dd, dd-enter, final, final3, mid, znorm, ref, polish, qr z
   const size_t list_bytes = align_up(sizeof(mpsk::Ent) * S);
   rc = ensure_small(E, o_ents + kLists * list_bytes, err);
   if (rc) return rc;
@@ -587,7 +652,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
   int* hdims = (int*)(E->h_stage + o_dims);
   double2* hu8 = (double2*)(E->h_stage + o_u8);
   double2* du8 = (double2*)(E->d_small + o_u8);
-  enum { LN2 = 0, LN3, LJ, LD, LENTER, LFIN, LFIN3, LMID, LZN, LR, LPOL, LJ2, LJO };
+  enum { LN2 = 0, LN3, LJ, LD, LENTER, LFIN, LFIN3, LMID, LZN, LR, LPOL, LJ2, LJO, LQZ };
   auto hlist = [&](int i) { return E->h_stage + o_ents + i * list_bytes; };
   auto dlist = [&](int i) { return E->d_small + o_ents + i * list_bytes; };
 
@@ -645,6 +710,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
   std::vector<int> active;  // slots not free
 
   bool unsynced = false;  // async copies from the pinned staging may still be pending
+  bool qr_pending = false;  // QR factorisations queued on stream3 this tick
   while (true) {
     // the staging buffers are rewritten below: wait for copies a previous tick left
     if (unsynced) {
@@ -750,6 +816,8 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
               new3.push_back(si);
             }
             carve(dd, t, E->ws + off1, d_flags, d_stats, d_fro, si);
+            if (g.k == 2 && E->qr) qr_select(dd, t);
+            if (t.qr) sl.state = 6;  // waits one tick for its QR factorisation
             mark(si);
             sl.M = t.M;
             sl.N = t.N;
@@ -811,16 +879,25 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
                    : mpsk::launch_theta2(dt, el, (int)nl.size(), mM, mNt, st);
         }
         if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("theta: ") + hipGetErrorString(e));
+        bool anyqr = false;
+        for (int si : nl) anyqr = anyqr || ht[si].qr;
+        if (anyqr) {  // on stream3 after the theta kernels; joined before the tick's readback
+          HIPCHK(err, hipEventRecord(E->ev_qr, st));
+          HIPCHK(err, hipStreamWaitEvent(E->stream3, E->ev_qr, 0));
+          e = mpsk::launch_qr_factor(dt, el, (int)nl.size(), mM, mN, E->stream3);
+          if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("qr: ") + hipGetErrorString(e));
+          qr_pending = true;
+        }
       }
     }
-    // ---- 2. one sweep for every iterating slot
+    // ---- 2. one sweep for every iterating slot (QR-pending slots wait)
     std::vector<int> jl, rl, dl;
     for (int si : active) {
       if (slot[si].state == 1) jl.push_back(si);
       if (slot[si].state == 2) rl.push_back(si);
       if (slot[si].state == 4) dl.push_back(si);
     }
-    if (jl.empty() && rl.empty() && dl.empty()) {
+    if (jl.empty() && rl.empty() && dl.empty() && !qr_pending) {
       if (active.empty()) {
         if (!remaining) break;
         continue;  // only single-site gates were admitted; admit the rest
@@ -895,6 +972,14 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
         if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("dd jacobi: ") + hipGetErrorString(e));
       }
     }
+    // the QR factorisations launched this tick: wait for them (the sweep above is
+    // already queued on the other streams), then their slots start iterating
+    if (qr_pending) {
+      HIPCHK(err, hipStreamSynchronize(E->stream3));
+      for (int si : active)
+        if (slot[si].state == 6) slot[si].state = 1;
+      qr_pending = false;
+    }
     // ---- 3. convergence
     if (!jl.empty() || !rl.empty() || !dl.empty()) {
       HIPCHK(err, hipMemcpyAsync(hflags, d_flags, sizeof(int) * 3 * S, hipMemcpyDeviceToHost, st));
@@ -964,6 +1049,30 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
       unsynced = true;
       mpsk::Ent* el = upload_list(LENTER, ents_of(enter));
       if (!el) return fail(err, MPS_EDEVICE, "list upload failed");
+      // QR-preconditioned tasks: V <- Q V_x, then the refinement of the transposed
+      // problem (square thetas: the shapes stay the same)
+      bool anyqr = false;
+      int qN = 0;
+      for (int si : enter)
+        if (ht[si].qr) {
+          anyqr = true;
+          qN = std::max(qN, ht[si].N);
+        }
+      if (anyqr) {
+        {
+          Timed tq(E, 6);
+          e = mpsk::launch_qr_left(dt, el, (int)enter.size(), qN, st);
+          if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("qr left: ") + hipGetErrorString(e));
+        }
+        for (int si : enter)
+          if (ht[si].qr) {
+            qr_to_transposed(ht[si]);
+            slot[si].JM = ht[si].JM;
+            slot[si].N = ht[si].N;
+            mark(si);
+          }
+        HIPCHK(err, upload_tasks());
+      }
       int mM = 0, mN = 0;
       for (int si : enter) { mM = std::max(mM, slot[si].JM); mN = std::max(mN, slot[si].N); }
       Timed tm(E, 6);
@@ -1002,6 +1111,21 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
           e = dd ? mpsk::launch_znorm_dd(dt, ez, (int)zl.size(), zJM, zK, st)
                  : mpsk::launch_znorm(dt, ez, (int)zl.size(), zJM, zK, st);
           if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("znorm: ") + hipGetErrorString(e));
+        }
+        std::vector<int> ql;  // FP64 tasks preconditioned by QR: Z from W's columns
+        int qN = 0, qK = 1;
+        for (int si : fl)
+          if (ht[si].qr) {
+            ql.push_back(si);
+            qN = std::max(qN, ht[si].N);
+            qK = std::max(qK, std::min(ht[si].chi, ht[si].N));
+          }
+        if (!ql.empty()) {
+          mpsk::Ent* eq = upload_list(LQZ, ents_of(ql));
+          if (!eq) return fail(err, MPS_EDEVICE, "list upload failed");
+          Timed tz(E, 3);
+          e = mpsk::launch_qr_z(dt, eq, (int)ql.size(), qN, qK, st);
+          if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("qr z: ") + hipGetErrorString(e));
         }
       }
       {
@@ -1150,6 +1274,10 @@ int set_option(Engine* E, int prec, int key, double value, std::string* err) {
     case MPS_OPT_MAX_SLOTS:
       if (!(value >= 1 && value <= 65536)) return fail(err, MPS_EINVAL, "slot limit out of range");
       E->max_slots = (int)value;
+      return MPS_OK;
+    case MPS_OPT_QR:
+      if (!(value == 0 || value == 1)) return fail(err, MPS_EINVAL, "QR switch must be 0 or 1");
+      E->qr = value != 0;
       return MPS_OK;
     case MPS_OPT_FUSE:
       if (!(value == 0 || value == 1)) return fail(err, MPS_EINVAL, "fusion switch must be 0 or 1");
