@@ -246,10 +246,15 @@ __global__ __launch_bounds__(512) void k_qr_panel(Task2* tasks, const Ent* ents,
 // Apply a panel's block reflector to 16 columns of a target matrix, one 256-thread
 // block per 16 columns: mode 0, the trailing columns of theta_w (positions p0+16..
 // of qperm): Y <- (I - V T^H V^H) Y = Q_p^H Y; mode 1, the Jacobi's V_x (N x N, all
-// columns): Y <- (I - V T V^H) Y = Q_p Y.  Rows below p0 only.  W = V^H Y is summed
-// over LDS-staged chunks of 64 rows, each thread one (reflector, column) entry.
+// columns): Y <- (I - V T V^H) Y = Q_p Y.  Rows below p0 only.  Both products are
+// FP64 MFMA (v_mfma_f64_16x16x4f64; accumulator element r of lane l is entry
+// (l / 16 + 4 r, l % 16)): W = V^H Y over k-steps of four rows, wave w taking
+// k-steps w, w + 4, ..., the waves' sums added in wave order; then Y - V W' over
+// 16-row tiles with Y as the accumulator's initial value.
+typedef double qr_d4 __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(256) void k_qr_apply(Task2* tasks, const Ent* ents, int p0, int mode) {
-  constexpr int CH = 64;
+  constexpr int NW = 4, KB = 8;  // waves; k-steps of loads in flight
   const Task2& T = tasks[ents[blockIdx.y].slot];
   if (!T.qr) return;
   const int M = T.M, N = T.N;
@@ -260,12 +265,12 @@ __global__ __launch_bounds__(256) void k_qr_apply(Task2* tasks, const Ent* ents,
   const int ncol = N - c0 < 16 ? N - c0 : 16;
   const int rows = mode == 0 ? M : N;  // rows of the target (mode 1: square, M == N)
   double2* Y = mode == 0 ? T.thw : T.JV;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   __shared__ int ycol[16], vcol[kPanel];
-  __shared__ double2 Vs[CH][kPanel + 1], Ys[CH][17];
-  __shared__ double2 Wm[kPanel][17];
-  __shared__ double2 Tm[kPanel][kPanel + 1];
   __shared__ double2 v0s[kPanel];
+  __shared__ double Ws[NW][2][16][17];
+  __shared__ double2 Wm[kPanel][17], Wp[kPanel][17];
+  __shared__ double2 Tm[kPanel][kPanel + 1];
   if (tid < 16) ycol[tid] = tid < ncol ? (mode == 0 ? T.qperm[c0 + tid] : c0 + tid) : -1;
   if (tid < kPanel) {
     vcol[tid] = tid < nb ? T.qperm[p0 + tid] : -1;
@@ -273,52 +278,101 @@ __global__ __launch_bounds__(256) void k_qr_apply(Task2* tasks, const Ent* ents,
   }
   {
     const double2* Tp = T.qT + (long)(p0 / kPanel) * kPanel * kPanel;
-    const int i = tid / kPanel, j = tid % kPanel;
-    Tm[i][j] = Tp[i * kPanel + j];
+    Tm[tid / kPanel][tid % kPanel] = Tp[tid];
   }
   __syncthreads();
   // reflector j at row r: zero above p0 + j, v0 at p0 + j, the stored tail below
   auto vget = [&](int j, int r) -> double2 {
-    if (vcol[j] < 0 || r < p0 + j) return cmk(0.0, 0.0);
+    if (r >= rows || vcol[j] < 0 || r < p0 + j) return cmk(0.0, 0.0);
     if (r == p0 + j) return v0s[j];
     return T.thw[(long)vcol[j] * M + r];
   };
-  const int wi = tid / 16, wc = tid % 16;  // this thread's entry of W
-  double2 acc = cmk(0.0, 0.0);
-  for (int r0 = p0; r0 < rows; r0 += CH) {
-    for (int e = tid; e < CH * kPanel; e += 256) {
-      const int rr = e % CH, j = e / CH, r = r0 + rr;
-      Vs[rr][j] = r < rows ? vget(j, r) : cmk(0.0, 0.0);
+  auto yget = [&](int cc, int r) -> double2 {
+    return (r < rows && ycol[cc] >= 0) ? Y[(long)ycol[cc] * rows + r] : cmk(0.0, 0.0);
+  };
+  const int li = lane & 15, lk = lane >> 4;
+  // 1. W = V^H Y: Re W = Vr^T Yr + Vi^T Yi, Im W = Vr^T Yi - Vi^T Yr
+  {
+    qr_d4 wr = {0.0, 0.0, 0.0, 0.0}, wi = {0.0, 0.0, 0.0, 0.0};
+    const int nks = (rows - p0 + 3) / 4;
+    for (int ks0 = wave; ks0 < nks; ks0 += NW * KB) {
+      double2 v[KB], y[KB];
+#pragma unroll
+      for (int t = 0; t < KB; ++t) {
+        const int r = p0 + (ks0 + NW * t) * 4 + lk;
+        v[t] = vget(li, r);
+        y[t] = yget(li, r);
+      }
+#pragma unroll
+      for (int t = 0; t < KB; ++t) {
+        wr = __builtin_amdgcn_mfma_f64_16x16x4f64(v[t].x, y[t].x, wr, 0, 0, 0);
+        wr = __builtin_amdgcn_mfma_f64_16x16x4f64(v[t].y, y[t].y, wr, 0, 0, 0);
+        wi = __builtin_amdgcn_mfma_f64_16x16x4f64(v[t].x, y[t].y, wi, 0, 0, 0);
+        wi = __builtin_amdgcn_mfma_f64_16x16x4f64(-v[t].y, y[t].x, wi, 0, 0, 0);
+      }
     }
-    for (int e = tid; e < CH * 16; e += 256) {
-      const int rr = e % CH, cc = e / CH, r = r0 + rr;
-      Ys[rr][cc] = (r < rows && ycol[cc] >= 0) ? Y[(long)ycol[cc] * rows + r] : cmk(0.0, 0.0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      Ws[wave][0][lk + 4 * r][li] = wr[r];
+      Ws[wave][1][lk + 4 * r][li] = wi[r];
     }
-    __syncthreads();
-#pragma unroll 8
-    for (int rr = 0; rr < CH; ++rr) acc = cfmac(Vs[rr][wi], Ys[rr][wc], acc);
-    __syncthreads();
   }
-  Wm[wi][wc] = acc;
   __syncthreads();
-  // W' = T^H W (mode 0) or T W (mode 1)
-  double2 wp = cmk(0.0, 0.0);
-  for (int l = 0; l < kPanel; ++l)
-    wp = mode == 0 ? cfmac(Tm[l][wi], Wm[l][wc], wp) : cfma(Tm[wi][l], Wm[l][wc], wp);
+  {
+    const int i = tid / 16, j = tid % 16;
+    double sr = 0.0, si = 0.0;
+    for (int w = 0; w < NW; ++w) {
+      sr += Ws[w][0][i][j];
+      si += Ws[w][1][i][j];
+    }
+    Wm[i][j] = cmk(sr, si);
+  }
   __syncthreads();
-  Wm[wi][wc] = wp;
+  // 2. W' = T^H W (mode 0) or T W (mode 1)
+  {
+    const int wi_ = tid / 16, wc = tid % 16;
+    double2 wp = cmk(0.0, 0.0);
+    for (int l = 0; l < kPanel; ++l)
+      wp = mode == 0 ? cfmac(Tm[l][wi_], Wm[l][wc], wp) : cfma(Tm[wi_][l], Wm[l][wc], wp);
+    Wp[wi_][wc] = wp;
+  }
   __syncthreads();
-  // Y -= V W'
-  for (int r = p0 + tid; r < rows; r += 256) {
-    double2 v[kPanel];
+  // 3. Y <- Y - V W' per 16-row tile: Re -= Vr W'r - Vi W'i, Im -= Vr W'i + Vi W'r
+  double br[4], bi[4], nbr[4], nbi[4];
 #pragma unroll
-    for (int j = 0; j < kPanel; ++j) v[j] = vget(j, r);
-    for (int cc = 0; cc < ncol; ++cc) {
-      double2 s = cmk(0.0, 0.0);
+  for (int ks = 0; ks < 4; ++ks) {
+    const double2 w = Wp[4 * ks + lk][li];
+    br[ks] = w.x;
+    bi[ks] = w.y;
+    nbr[ks] = -w.x;
+    nbi[ks] = -w.y;
+  }
+  const int ntile = (rows - p0 + 15) / 16;
+  for (int tl = wave; tl < ntile; tl += NW) {
+    const int t0 = p0 + 16 * tl;
+    double2 a[4];
 #pragma unroll
-      for (int j = 0; j < kPanel; ++j) s = cfma(v[j], Wm[j][cc], s);
-      double2* p = Y + (long)ycol[cc] * rows + r;
-      *p = csub(*p, s);
+    for (int ks = 0; ks < 4; ++ks) a[ks] = vget(4 * ks + lk, t0 + li);
+    qr_d4 yr, yi;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double2 yv = yget(li, t0 + lk + 4 * r);
+      yr[r] = yv.x;
+      yi[r] = yv.y;
+    }
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      yr = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks].x, nbr[ks], yr, 0, 0, 0);
+      yr = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks].y, bi[ks], yr, 0, 0, 0);
+      yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks].x, nbi[ks], yi, 0, 0, 0);
+      yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks].y, nbr[ks], yi, 0, 0, 0);
+    }
+    if (ycol[li] >= 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = t0 + lk + 4 * r;
+        if (row < rows) Y[(long)ycol[li] * rows + row] = cmk(yr[r], yi[r]);
+      }
     }
   }
 }
