@@ -509,9 +509,13 @@ __global__ __launch_bounds__(1024) void k_truncate_dd(Task2* tasks, const Ent* e
   const ddr W = sc[0];
   const double s0 = sqrt(key[0].hi);
   const ddr epsW = dd::mul_d(W, eps);
+  // as in the FP64 truncation: with Z formed from W's columns (wide theta, or a QR
+  // task refined as the transposed problem), columns the dd Jacobi treated as zero
+  // (|w|^2 <= 2^-192 ||theta_w||^2) are dropped
+  const double zfloor = (T.tr || T.qr) ? *T.fro2 * 0x1p-190 : -1.0;
   int myrank = 0;
   for (int j = tid; j < N; j += nt) {
-    if (sqrt(key[j].hi) > floor_rel * s0) ++myrank;
+    if (sqrt(key[j].hi) > floor_rel * s0 && key[j].hi > zfloor) ++myrank;
     const int kk = j + 1;
     const ddr tailk = kk < N ? sc[kk] : ddr{0.0, 0.0};
     if (!dd::lt(epsW, tailk)) atomicMin(&s_keps, kk);

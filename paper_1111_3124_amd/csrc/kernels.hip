@@ -560,9 +560,13 @@ __global__ __launch_bounds__(1024) void k_truncate(Task2* tasks, const Ent* ents
   const double W = sc[0];
   const double s0 = sqrt(key[0]);
   const double epsW = eps * W;
+  // Where Z is formed from W's columns (wide theta, QR), a column the Jacobi treated
+  // as zero (|w|^2 <= 2^-88 ||theta_w||^2, never rotated) has no meaningful direction:
+  // it is dropped whatever the rank floor keeps (with a factor 4 of margin).
+  const double zfloor = (T.tr || T.qr) ? *T.fro2 * 0x1p-86 : -1.0;
   int myrank = 0;
   for (int j = tid; j < N; j += nt) {
-    if (sqrt(key[j]) > floor_rel * s0) ++myrank;
+    if (sqrt(key[j]) > floor_rel * s0 && key[j] > zfloor) ++myrank;
     const int kk = j + 1;  // candidate kept count
     const double tailk = kk < N ? sc[kk] : 0.0;
     if (tailk <= epsW) atomicMin(&s_keps, kk);
