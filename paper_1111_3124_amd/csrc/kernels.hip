@@ -160,84 +160,99 @@ __device__ __forceinline__ bool pair_rot(double al, double be, double2 g, double
   return true;
 }
 
-// Block-wide inner two-sided Jacobi on the pair's W2 x W2 Gram (NT threads): per
-// round, one thread per pair forms the rotation, then every thread forms its elements
-// of J^H G J and R J from the 2 x 2 neighbourhood of the old values (double-buffered).
-// G[0] holds the Gram on entry; returns the buffer with the result, any_rot is set
-// when something rotated.  The LDS scratch comes from the caller.
+// Block-wide inner two-sided Jacobi on the pair's W2 x W2 Gram (NT threads).  Per
+// round every thread takes elements (i, j): it forms the rotations of i's and of j's
+// pair itself from the old G (each pair's rotation is computed identically by every
+// thread that needs it), then its elements of J^H G J and R J from the 2 x 2
+// neighbourhood of the old values (double-buffered): one barrier a round.  G[0] holds
+// the Gram on entry; returns the buffer with the result; any_rot is set when
+// something rotated.
 template <int W2>
 struct InnerLds {
-  double2 ra[W2], rb[W2];      // (X J)[:, x] = ra[x] X_x + rb[x] X_partner(x)
-  int rpart[W2], rrot[W2];
-  int rnd_rot[2];              // did any pair of the round rotate (alternating slots)
-  int swf[3];                  // did any pair of the inner sweep rotate
   int any_rot;
 };
+
+// Partner of column x in an inner round: cross rounds pair x < H with H + (x + rnd)
+// mod H; the full round-robin holds column 0 at position 0 and column x > 0 at
+// position 1 + (x - 1 - rnd) mod (W2 - 1), position k meeting W2 - 1 - k.
+template <int W2>
+__device__ __forceinline__ int inner_partner(int x, int rnd, bool cross) {
+  constexpr int H = W2 / 2, np1 = W2 - 1;
+  if (cross) return x < H ? H + (x + rnd) % H : (x - rnd) % H;
+  const int k = x == 0 ? 0 : 1 + ((x - 1 - rnd) % np1 + np1) % np1;
+  return rr_player(np1 - k, rnd, W2);
+}
+
+// Column x's coefficients in the round's unitary J, (X J)[:, x] = ra X_x + rb X_px,
+// from its pair's Gram entries al = G_pp, be = G_qq, g = G_pq (p < q) and whether x
+// is p.  Branch-free: the rotation is formed whether or not the pair rotates (the
+// operands are all loaded before), then selected; the same inputs give every thread
+// that needs the pair the same rotation.
+struct RotCoef {
+  double2 ra, rb;
+  int rot;
+};
+
+__device__ __forceinline__ RotCoef inner_coef(double al, double be, double2 g, bool valid, bool xp, double tol,
+                                              double ztol) {
+  const double g2 = g.x * g.x + g.y * g.y;
+  const bool rot = valid & (al > ztol) & (be > ztol) & (g2 > tol * tol * al * be);
+  const double ig = rsq_nr(g2);  // 1 / |g|
+  const double zeta = 0.5 * (be - al) * ig;
+  const double x = fma(zeta, zeta, 1.0);
+  const double u = fabs(zeta) + x * rsq_nr(x);
+  const double w = rsq_nr(fma(u, u, 1.0));
+  const double c = u * w, sn = zeta < 0.0 ? -w : w;
+  const double2 e = cmk(g.x * ig, -g.y * ig);
+  RotCoef k;
+  k.rot = rot ? 1 : 0;
+  k.ra = !rot ? cmk(1.0, 0.0) : (xp ? cmk(c, 0.0) : cscale(e, c));
+  k.rb = !rot ? cmk(0.0, 0.0) : (xp ? cscale(e, -sn) : cmk(sn, 0.0));
+  return k;
+}
 
 // cross: only the (W2/2)^2 pairs between the two column blocks, in W2/2 rounds
 // (round r pairs p with W2/2 + (p + r) mod W2/2); else all pairs, round-robin.
 template <int W2, int NT>
 __device__ int inner_jacobi_block(double2 (&G)[2][W2][W2 + 1], double2 (&R)[2][W2][W2 + 1], InnerLds<W2>& L,
                                   const int (&cols)[W2], int inner, double tol, double ztol, bool cross = false) {
-  constexpr int H = W2 / 2;
   const int tid = threadIdx.x;
   for (int e = tid; e < W2 * W2; e += NT) R[0][e / W2][e % W2] = cmk(e / W2 == e % W2 ? 1.0 : 0.0, 0.0);
-  if (tid < 3) L.swf[tid] = 0;
-  if (tid < 2) L.rnd_rot[tid] = 0;
-  if (tid == 0) L.any_rot = 0;
   __syncthreads();
-  int cur = 0;
+  int cur = 0, any_rot = 0;
+  const int nrnd = cross ? W2 / 2 : W2 - 1;
   for (int isw = 0; isw < inner; ++isw) {
-    // slot isw%3 is written this sweep and read after its last barrier; slot
-    // (isw+1)%3 was last read two sweeps ago (many barriers back): clear it now
-    if (tid == 0) L.swf[(isw + 1) % 3] = 0;
-    const int nrnd = cross ? H : W2 - 1;
+    int mine = 0;  // did a pair this thread used rotate in this inner sweep
     for (int rnd = 0; rnd < nrnd; ++rnd) {
-      if (tid < H) {
-        const int pa = cross ? tid : rr_player(tid, rnd, W2);
-        const int pb = cross ? H + (tid + rnd) % H : rr_player(W2 - 1 - tid, rnd, W2);
-        const int p = pa < pb ? pa : pb, q = pa < pb ? pb : pa;
-        PairRot r;
-        const bool rot = cols[p] >= 0 && cols[q] >= 0 &&
-                         pair_rot(G[cur][p][p].x, G[cur][q][q].x, G[cur][p][q], tol, ztol, r);
-        L.rpart[p] = q; L.rpart[q] = p;
-        L.rrot[p] = rot; L.rrot[q] = rot;
-        if (rot) {
-          L.ra[p] = cmk(r.c, 0.0);          L.rb[p] = cscale(r.e, -r.s);
-          L.ra[q] = cscale(r.e, r.c);       L.rb[q] = cmk(r.s, 0.0);
-          L.swf[isw % 3] = 1;
-          L.rnd_rot[rnd & 1] = 1;
-        } else {
-          L.ra[p] = L.ra[q] = cmk(1.0, 0.0);
-          L.rb[p] = L.rb[q] = cmk(0.0, 0.0);
-        }
-      }
-      __syncthreads();
-      // slot (rnd+1)&1 was last read in the previous round, before its closing barrier
-      if (tid == 0) L.rnd_rot[(rnd + 1) & 1] = 0;
-      if (!L.rnd_rot[rnd & 1]) {  // nothing rotated: G and R are unchanged
-        __syncthreads();
-        continue;
-      }
       for (int e = tid; e < W2 * W2; e += NT) {
         const int i = e / W2, j = e % W2;
-        const int pi_ = L.rpart[i], pj = L.rpart[j];
-        const double2 ai = L.ra[i], bi_ = L.rb[i], aj = L.ra[j], bj_ = L.rb[j];
+        const int pi_ = inner_partner<W2>(i, rnd, cross), pj = inner_partner<W2>(j, rnd, cross);
+        const bool ip = i < pi_, jp = j < pj;
         const double2(*Gc)[W2 + 1] = G[cur];
-        const double2 colj = cadd(cmul(aj, Gc[i][j]), cmul(bj_, Gc[i][pj]));
-        const double2 colpj = cadd(cmul(aj, Gc[pi_][j]), cmul(bj_, Gc[pi_][pj]));
-        double2 v = cadd(cmul(cconj(ai), colj), cmul(cconj(bi_), colpj));
-        if (L.rrot[i] && j == pi_) v = cmk(0.0, 0.0);  // the rotated pair's off-diagonal is zero
+        // every operand of the round first (one LDS round trip)
+        const bool vi = (cols[i] >= 0) & (cols[pi_] >= 0), vj = (cols[j] >= 0) & (cols[pj] >= 0);
+        const double gii = Gc[i][i].x, gpp = Gc[pi_][pi_].x, gjj = Gc[j][j].x, gqq = Gc[pj][pj].x;
+        const double2 gi = ip ? Gc[i][pi_] : Gc[pi_][i], gj = jp ? Gc[j][pj] : Gc[pj][j];
+        const double2 g_ij = Gc[i][j], g_iq = Gc[i][pj], g_pj = Gc[pi_][j], g_pq = Gc[pi_][pj];
+        const double2 r_ij = R[cur][i][j], r_iq = R[cur][i][pj];
+        const RotCoef ci = inner_coef(ip ? gii : gpp, ip ? gpp : gii, gi, vi, ip, tol, ztol);
+        const RotCoef cj = inner_coef(jp ? gjj : gqq, jp ? gqq : gjj, gj, vj, jp, tol, ztol);
+        mine |= ci.rot | cj.rot;
+        const double2 colj = cadd(cmul(cj.ra, g_ij), cmul(cj.rb, g_iq));
+        const double2 colpj = cadd(cmul(cj.ra, g_pj), cmul(cj.rb, g_pq));
+        double2 v = cadd(cmul(cconj(ci.ra), colj), cmul(cconj(ci.rb), colpj));
+        if (ci.rot && j == pi_) v = cmk(0.0, 0.0);  // the rotated pair's off-diagonal is zero
         if (i == j) v.y = 0.0;
         G[cur ^ 1][i][j] = v;
-        R[cur ^ 1][i][j] = cadd(cmul(aj, R[cur][i][j]), cmul(bj_, R[cur][i][pj]));
+        R[cur ^ 1][i][j] = cadd(cmul(cj.ra, r_ij), cmul(cj.rb, r_iq));
       }
       cur ^= 1;
-      __syncthreads();
+      __syncthreads();  // (a round that rotated nothing copied G and R unchanged)
     }
-    if (!L.swf[isw % 3]) break;
-    if (tid == 0) L.any_rot = 1;
+    if (!__syncthreads_or(mine)) break;
+    any_rot = 1;
   }
+  if (tid == 0) L.any_rot = any_rot;
   __syncthreads();
   return cur;
 }
@@ -280,6 +295,8 @@ __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* en
 
   const bool clk = phase_clock && pi == 0 && blockIdx.y == 0 && tid == 0;
   if (clk) phase_clock[0] = wall_clock64();
+  // loaded here, so that its latency under the memory phases' traffic is hidden
+  const double fro2 = *T.fro2;
   const int I = rr_player(pi, step, nbp), J = rr_player(nbp - 1 - pi, step, nbp);
   if (tid < W2) {  // the pair's columns: positions blk * BW + x of this sweep's order
     const int blk = tid < BW ? I : J;
@@ -403,7 +420,7 @@ __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* en
   // 2. inner Jacobi (with many column blocks a single inner sweep per step is enough:
   //    the next steps revisit every column; with few blocks each pair is diagonalised)
   const double tol = tol_mult * (double)(M > 16 ? M : 16) * 0x1p-53;
-  const double ztol = *T.fro2 * 0x1p-88;
+  const double ztol = fro2 * 0x1p-88;
   //    Within a sweep, the pairs inside each block are rotated at its first step; the
   //    later steps rotate only the pairs across the two blocks.
   const bool many = nbp >= 16;
