@@ -135,31 +135,6 @@ __device__ __forceinline__ double rsq_nr(double x) {
   return y;
 }
 
-// Rotation of one column pair (p < q) from the Gram entries al = G_pp, be = G_qq,
-// g = G_pq: the complex form of the symmetric Schur 2x2 (Golub & Van Loan 8.4):
-// with e = conj(g)/|g|, zeta = (be - al) / (2|g|), t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)),
-// c = 1 / sqrt(1 + t^2), s = t c:  (X J)[:, p] = c X_p - s e X_q,  (X J)[:, q] = s X_p + c e X_q.
-// With u = |zeta| + sqrt(1 + zeta^2) = 1 / |t|, c = u / sqrt(u^2 + 1) and |s| = 1 / sqrt(u^2 + 1),
-// which needs no reciprocal; sqrt(x) for x >= 1 is x rsq(x).
-struct PairRot {
-  double c, s;
-  double2 e;  // e^{-i phi}
-};
-
-__device__ __forceinline__ bool pair_rot(double al, double be, double2 g, double tol, double ztol, PairRot& r) {
-  const double g2 = g.x * g.x + g.y * g.y;
-  if (!(al > ztol && be > ztol && g2 > tol * tol * al * be)) return false;
-  const double ig = rsq_nr(g2);            // 1 / |g|
-  const double zeta = 0.5 * (be - al) * ig;
-  const double x = fma(zeta, zeta, 1.0);
-  const double u = fabs(zeta) + x * rsq_nr(x);
-  const double w = rsq_nr(fma(u, u, 1.0));
-  r.c = u * w;
-  r.s = zeta < 0.0 ? -w : w;
-  r.e = cmk(g.x * ig, -g.y * ig);
-  return true;
-}
-
 // Block-wide inner two-sided Jacobi on the pair's W2 x W2 Gram (NT threads).  Per
 // round every thread takes elements (i, j): it forms the rotations of i's and of j's
 // pair itself from the old G (each pair's rotation is computed identically by every
@@ -183,6 +158,14 @@ __device__ __forceinline__ int inner_partner(int x, int rnd, bool cross) {
   return rr_player(np1 - k, rnd, W2);
 }
 
+// Rotation of one column pair (p < q) from the Gram entries al = G_pp, be = G_qq,
+// g = G_pq: the complex form of the symmetric Schur 2x2 (Golub & Van Loan 8.4):
+// with e = conj(g)/|g|, zeta = (be - al) / (2|g|), t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+// c = 1 / sqrt(1 + t^2), s = t c:  (X J)[:, p] = c X_p - s e X_q,  (X J)[:, q] = s X_p + c e X_q.
+// With u = |zeta| + sqrt(1 + zeta^2) = 1 / |t|, c = u / sqrt(u^2 + 1) and |s| = 1 / sqrt(u^2 + 1),
+// which needs no reciprocal; sqrt(x) for x >= 1 is x rsq(x).  A pair is rotated when
+// both columns are above the zero threshold ztol and |g|^2 > tol^2 G_pp G_qq.
+//
 // Column x's coefficients in the round's unitary J, (X J)[:, x] = ra X_x + rb X_px,
 // from its pair's Gram entries al = G_pp, be = G_qq, g = G_pq (p < q) and whether x
 // is p.  Branch-free: the rotation is formed whether or not the pair rotates (the
