@@ -96,10 +96,13 @@ __global__ __launch_bounds__(256) void k_theta2_dd(Task2* tasks, const Ent* ents
 // ------------------------------------------------------------------ Newton-Schulz
 // E = V^H V - I (dd accumulation, stored binary64: E is of the size of V's
 // orthogonality error, so its binary64 rounding is far below dd precision of V).
+// E is Hermitian: only the tiles on and above the diagonal are formed, an
+// off-diagonal tile also writing its conjugate transpose.
 struct GramOpDD {
   static constexpr bool kARowFast = false;
   static constexpr bool kBColFast = false;
   const Task2* t;
+  bool mirror;
   __device__ cdd a(int row, int kk) const { return dd::cconj(ldc(t->V, t->V_lo, (long)row * t->N + kk)); }
   __device__ cdd b(int kk, int col) const { return ldc(t->V, t->V_lo, (long)col * t->N + kk); }
   __device__ void epilogue(int r0, int c0, cdd (&v)[2][2]) const {
@@ -113,6 +116,7 @@ struct GramOpDD {
         cdd e = v[i][j];
         if (r == c) e.re = dd::add_d(e.re, -1.0);
         t->aux1[(long)c * N + r] = make_double2(e.re.hi, e.im.hi);  // column-major
+        if (mirror) t->aux1[(long)r * N + c] = make_double2(e.re.hi, -e.im.hi);
       }
   }
 };
@@ -120,8 +124,8 @@ struct GramOpDD {
 __global__ __launch_bounds__(256) void k_gram_dd(Task2* tasks, const Ent* ents) {
   const Task2* t = &tasks[ents[blockIdx.z].slot];
   const int tm = blockIdx.x * 32, tn = blockIdx.y * 32;
-  if (tm >= t->N || tn >= t->N) return;
-  GramOpDD op{t};
+  if (tm >= t->N || tn >= t->N || tm > tn) return;
+  GramOpDD op{t, tm != tn};
   ddgemm_tile(op, t->N, t->N, t->N, tm, tn);
 }
 
