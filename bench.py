@@ -31,6 +31,8 @@ N_QUBITS, CHI, EPS, SEED = 40, 256, 1e-12, 2
 PEAK_FP64 = 78.6e12  # MI355X FP64 vector (and matrix) peak, FLOP/s
 PEAK_HBM = 8.0e12    # MI355X HBM3E bandwidth, B/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jacobi_step_chi256_traffic.md")
+FP64_OPS_FILE = os.path.join(ROOT, "profiles", "jacobi_step_chi256_fp64_ops.md")
+S_REF = 10  # reference sweep count of the algorithmic work unit
 KERNEL_SRC = os.path.join(ROOT, "paper_1111_3124_amd", "csrc", "kernels.hip")
 
 
@@ -98,60 +100,81 @@ def run_variant(B, W, prec: int, steps: int, warmup: int):
                 slot_sweeps=slot_sweeps, ktimes=ktimes, lam_ok=lam_ok, noconv=rc != 0, steps=steps)
 
 
-def step_bytes(M: int, N: int) -> float:
-    """Memory traffic of one step of one update: every column of W (M x N) and of
-    V (N x N) is read once and written once (complex128)."""
-    return 2.0 * 16.0 * (M * N + N * N)
+def step_bytes(M: int, N: int, jvec: int = 1) -> float:
+    """Memory traffic of one step of one update: every column of W (M x N) and, when
+    V is accumulated (jvec), of V (N x N) is read once and written once (complex128)."""
+    return 2.0 * 16.0 * (M * N + jvec * N * N)
 
 
-def measured_traffic():
-    """Memory-fabric bytes per update-step of the Jacobi step kernel (N = 512) from the
-    committed rocprofv3 counter summary, or None if there is none or the kernel
-    source changed since the counters were taken."""
+def step_flops(M: int, N: int, jvec: int = 1) -> float:
+    """Scalar one-sided Jacobi work of one step of one update: J(M, N) / (N/8 - 1), with
+    the V rotations (the 20 N term) only when V is accumulated."""
+    return N * (N - 1) / 2.0 * (28.0 * M + jvec * 20.0 * N) / (N // 8 - 1)
+
+
+def measured(path, key):
+    """A per-update-step figure of the Jacobi step kernel (N = 512) from a committed
+    rocprofv3 counter summary, or None if there is none or kernels.hip changed since
+    the counters were taken."""
     try:
         import hashlib
-        text = open(TRAFFIC_FILE).read()
-        kv = dict(l.split(":", 1) for l in text.splitlines()
-                  if l.startswith(("bytes_per_update_step:", "kernels_hip_sha256:")))
+        text = open(path).read()
+        kv = dict(l.split(":", 1) for l in text.splitlines() if l.startswith((key + ":", "kernels_hip_sha256:")))
         digest = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
         if kv["kernels_hip_sha256"].strip() != digest:
             return None
-        return float(kv["bytes_per_update_step"].strip())
+        return float(kv[key].strip())
     except (OSError, KeyError, ValueError):
         return None
 
 
-def roofline(res):
+def roofline(res, jvec: int):
     """Dominant kernel: the FP64 Jacobi step (k_jacobi_step<8>).  A step serves each
-    iterating update with one of the nsteps = N/8 - 1 steps of its sweep: J(M, N) /
-    nsteps flops and step_bytes(M, N) of traffic.  The updates of a step are split
-    into two halves whose launches run concurrently on two streams, so a launch
-    lasts about as long as the step.  Totals over the timed region: update-sweeps
-    executed x nsteps x those; achieved = total / the steps' HIP-event time.  The
-    primary bound is the one the kernel is closer to."""
+    iterating update with one of the nsteps = N/8 - 1 steps of its sweep:
+    step_flops(M, N) and step_bytes(M, N) of algorithmic work (jvec: V accumulated,
+    as in the dd variant; the FP64 variant's QR-preconditioned updates accumulate no
+    V).  The updates of a step are split into two halves whose launches run
+    concurrently on two streams, so a launch lasts about as long as the step.  Totals
+    over the timed region: update-sweeps executed x nsteps x those; achieved = total /
+    the steps' HIP-event time.  The primary bound is the one the kernel is closer to.
+    The counter-based figures (memory-fabric traffic, executed FP64 flops: VALU adds,
+    multiplies, 2 x FMAs, and MFMA operations) were taken on the dd variant."""
     ms, launches = res["ktimes"]["jacobi"]
     if launches == 0:
         return None
     M = N = 2 * CHI
     nsteps = N // 8 - 1
     sec = ms * 1e-3
-    flops = res["slot_sweeps"] * jacobi_flops(M, N)
-    nbytes = res["slot_sweeps"] * nsteps * step_bytes(M, N)
+    usteps = res["slot_sweeps"] * nsteps  # update-steps in the timed region
+    flops = usteps * step_flops(M, N, jvec)
+    nbytes = usteps * step_bytes(M, N, jvec)
     f_alu = flops / sec / PEAK_FP64
     f_hbm = nbytes / sec / PEAK_HBM
-    per_step = measured_traffic()
-    # measured bytes per launch: the per-update-step figure x the update-steps one
-    # launch serves on average in the timed region
-    traffic = per_step * (nbytes / launches) / step_bytes(M, N) if per_step else None
+    per_step = measured(TRAFFIC_FILE, "bytes_per_update_step") if jvec else None
+    traffic = per_step * usteps / launches if per_step else None
     hbm = {"bound": "hbm", "achieved": nbytes / sec / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": f_hbm,
            "traffic": traffic, "bytes_per_launch": nbytes / launches}
     alu = {"bound": "alu", "achieved": flops / sec / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": f_alu,
            "traffic": traffic, "flops_per_launch": flops / launches}
+    ops = measured(FP64_OPS_FILE, "fp64_flops_per_update_step") if jvec else None
+    alu["executed"] = None if ops is None else {
+        "flops_per_launch": ops * usteps / launches, "achieved": ops * usteps / sec / 1e12,
+        "frac": ops * usteps / sec / PEAK_FP64}
     main, other = (hbm, alu) if f_hbm >= f_alu else (alu, hbm)
     main = dict(main)
     main.update({"kernel": "k_jacobi_step<8>", "avg_launch_us": 1e3 * ms / launches, "launches": launches,
                  "concurrent_launches": 2, "other_bound": other})
     return main
+
+
+def work_at_s_ref(rate: float) -> dict:
+    """The algorithmic FP64 work of one update at the reference sweep count (theta
+    GEMM and gate mix, S_REF one-sided Jacobi sweeps with V, split GEMM) times the
+    update rate, against the FP64 peak: a sweep saved shows as speed, not as a lower
+    fraction."""
+    f = update_flops(CHI, CHI, CHI, CHI, S_REF)
+    return {"flops_per_update": f, "sweeps": S_REF, "achieved": rate * f / 1e12, "unit": "TFLOP/s",
+            "frac": rate * f / PEAK_FP64}
 
 
 def calibrate_copy(mib: int = 256, reps: int = 10):
@@ -251,8 +274,10 @@ def main():
         "variants": {k: {"value": v["rate"], "ms_per_step": v["ms_per_step"],
                          "mean_sweeps": v["mean_sweeps"], "mean_dd_sweeps": v["mean_dd_sweeps"],
                          "kernel_ms": {n: t[0] for n, t in v["ktimes"].items()},
-                         "schmidt_normalised": v["lam_ok"]} for k, v in results.items()},
-        "roofline": roofline(r),
+                         "schmidt_normalised": v["lam_ok"],
+                         "roofline": roofline(v, 1 if k == "dd" else 0),
+                         "work_at_s_ref": work_at_s_ref(v["rate"])} for k, v in results.items()},
+        "roofline": roofline(r, 1 if head == "dd" else 0),
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
