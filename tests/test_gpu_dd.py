@@ -1,5 +1,5 @@
 """Parity of the double-double refined device path with the 256-bit oracle and with
-closed forms.  Bar (spec tolerance for the dd path): |amplitude difference|
+closed forms.  Bar (the dd path's tolerance): |amplitude difference|
 <= 1e-26 element by element; seeds whose truncation cut is degenerate at 1e-20
 (relative gap) are excluded."""
 import mpmath

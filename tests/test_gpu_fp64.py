@@ -1,6 +1,6 @@
 """Parity of the FP64 device path (through the C ABI) with the 256-bit oracle.
 
-Bar (spec tolerance for plain FP64): |amplitude difference| <= 1e-12, element
+Bar (the FP64 path's tolerance): |amplitude difference| <= 1e-12, element
 by element, on seeded inputs; Schmidt values compared where both sides keep the
 same count.  Cases with a degenerate cut (relative gap <= 1e-10 at the truncation
 point) are excluded from value comparison, as their kept subspace is not unique.
