@@ -89,7 +89,12 @@ enum mps_option {
                                  M <= 1024 (dd: square only) are preconditioned by a
                                  Householder QR of theta_w with its columns in norm
                                  order, and the Jacobi runs on R^H (fewer sweeps);
-                                 0: the Jacobi runs on theta_w                           */
+                                 0: the Jacobi runs on theta_w                           */,
+  MPS_OPT_STEP_SPLIT = 13     /* block width 8: a Jacobi step launch that serves at most
+                                 this many updates (default 4; 0: none) runs as two
+                                 launches (partial Grams, then rotations and updates) of
+                                 two 256-thread blocks a column-block pair, for more
+                                 parallelism when few updates are in flight             */
 };
 
 /* Diagnostics of the most recent split (the last one of a three-qubit gate). */

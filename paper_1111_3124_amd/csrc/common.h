@@ -101,6 +101,9 @@ struct Task2 {
   double2* JW;
   double2* JV;
   int JR, jvec;
+  // the split Jacobi step's partial Grams: per column-block pair and row half, the
+  // 16 x 16 Re part and P = Xr^T Xi part (2 x 2 x 256 doubles a pair)
+  double* JG;
   // QR preconditioning (qr = 1): column order, reflector heads, scales, panel factors
   int qr;
   int* qperm;

@@ -292,21 +292,27 @@ __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* en
   const double2* __restrict__ A = T.JW;
   const int wave = tid >> 6, lane = tid & 63;
   if constexpr (W2 == 16) {
-    // by MFMA over k-steps of 4 rows, wave w taking k-steps w, w + NW, ...: lane l
+    // by MFMA over k-steps of 4 rows: waves 0-3 take the first half of the rows,
+    // waves 4-7 the second, wave w of a half its k-steps w, w + 4, ... (exactly as the
+    // blocks of the split step, so both forms give the same G bit for bit); lane l
     // holds X[4 ks + l / 16][column l % 16], the same element for both operands;
     // Re G = Xr^T Xr + Xi^T Xi and, with P = Xr^T Xi, Im G = P - P^T
+    static_assert(NW == 8, "two halves of four waves");
     __shared__ double Gw[NW][2][W2][W2 + 1];
     constexpr int KB = 16;  // k-steps of loads in flight per wave
     mfma_d4 gr = {0.0, 0.0, 0.0, 0.0}, gp = {0.0, 0.0, 0.0, 0.0};
     const int c = cols[lane & 15];
     const int roff = lane >> 4;
-    const int nks = (M + 3) / 4;
-    for (int ks0 = wave; ks0 < nks; ks0 += NW * KB) {
+    const int hh = wave >> 2, wl = wave & 3;
+    const int Mh = (M + 1) / 2;
+    const int r_lo = hh * Mh, r_hi = min(M, r_lo + Mh);
+    const int nks = (r_hi - r_lo + 3) / 4;
+    for (int ks0 = wl; ks0 < nks; ks0 += 4 * KB) {
       double2 x[KB];
 #pragma unroll
       for (int t = 0; t < KB; ++t) {
-        const int r = (ks0 + NW * t) * 4 + roff;
-        x[t] = (c >= 0 && r < M) ? A[(long)c * M + r] : cmk(0.0, 0.0);
+        const int r = r_lo + (ks0 + 4 * t) * 4 + roff;
+        x[t] = (c >= 0 && r < r_hi) ? A[(long)c * M + r] : cmk(0.0, 0.0);
       }
 #pragma unroll
       for (int t = 0; t < KB; ++t) {
@@ -321,15 +327,18 @@ __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* en
       Gw[wave][1][roff + 4 * r][lane & 15] = gp[r];
     }
     __syncthreads();
-    if (tid < W2 * W2) {  // the waves' sums in wave order
+    if (tid < W2 * W2) {  // each half's sums in wave order, then the two halves
       const int i = tid / W2, j = tid % W2;
-      double sr = 0.0, pij = 0.0, pji = 0.0;
-      for (int w = 0; w < NW; ++w) {
-        sr += Gw[w][0][i][j];
-        pij += Gw[w][1][i][j];
-        pji += Gw[w][1][j][i];
+      double sr[2], pij[2], pji[2];
+      for (int h = 0; h < 2; ++h) {
+        sr[h] = pij[h] = pji[h] = 0.0;
+        for (int w = 4 * h; w < 4 * h + 4; ++w) {
+          sr[h] += Gw[w][0][i][j];
+          pij[h] += Gw[w][1][i][j];
+          pji[h] += Gw[w][1][j][i];
+        }
       }
-      Gb[0][i][j] = cmk(sr, pij - pji);
+      Gb[0][i][j] = cmk(sr[0] + sr[1], (pij[0] + pij[1]) - (pji[0] + pji[1]));
     }
   } else {
     // row chunks staged in LDS, D chunks of loads in flight; each wave an eighth of
@@ -456,6 +465,152 @@ __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* en
     phase_clock[3] = wall_clock64();
     phase_clock[4] = res_rot;
   }
+}
+
+// ------------------------------------------------------------------ split Jacobi step
+// The step of k_jacobi_step<8> as two launches of 256-thread blocks, two a column-block
+// pair (row halves h = 0, 1), for launches that serve few updates: twice the blocks
+// of half the size.
+//   k_jacobi_gram: the half's partial Gram of the pair's columns of W over its rows
+//     (MFMA as in the fused kernel; Re part and P = Xr^T Xi part) into JG;
+//   k_jacobi_rot: both halves' partials added (h = 0 first), so that both blocks of a
+//     pair form the same G, the same inner Jacobi and the same R; each block updates
+//     its half of the W and V rows.
+// The launch boundary orders every Gram read of a step before its updates.
+namespace {
+constexpr int kSplitNT = 256;
+
+// the pair's columns (blockIdx.x = pair + P * half); false: nothing to do
+__device__ __forceinline__ bool split_pair(const Task2& T, int step, int P, int sweep, int (&cols)[16], int& pi,
+                                           int& h, int& nbp) {
+  constexpr int BW = 8;
+  const int N = T.N;
+  const int nb = (N + BW - 1) / BW;
+  nbp = nb + (nb & 1);
+  pi = blockIdx.x % P;
+  h = blockIdx.x / P;
+  if (step >= nbp - 1 || pi >= nbp / 2) return false;
+  if (sweep > 0 && T.flags[(sweep + 2) % 3] == 0) return false;
+  const int I = rr_player(pi, step, nbp), J = rr_player(nbp - 1 - pi, step, nbp);
+  const int tid = threadIdx.x;
+  if (tid < 16) {
+    const int blk = tid < BW ? I : J;
+    const int c = blk * BW + (tid % BW);
+    cols[tid] = (blk < nb && c < N) ? T.perm[c] : -1;
+  }
+  __syncthreads();
+  return true;
+}
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_jacobi_gram(Task2* tasks, const Ent* ents, int step, int P) {
+  constexpr int W2 = 16, NT = kSplitNT, NW = NT / 64, KB = 16;
+  const Task2& T = tasks[ents[blockIdx.y].slot];
+  const int sweep = ents[blockIdx.y].sweep;
+  const int tid = threadIdx.x;
+  // slot (sweep+1)%3 is neither read nor written during this sweep: clear it for the
+  // next one (also for converged tasks, whose later sweeps must read 0)
+  if (step == 0 && blockIdx.x == 0 && tid == 0) T.flags[(sweep + 1) % 3] = 0;
+  __shared__ int cols[W2];
+  __shared__ double Gw[NW][2][W2][W2 + 1];
+  int pi, h, nbp;
+  if (!split_pair(T, step, P, sweep, cols, pi, h, nbp)) return;
+  const int M = T.JR;
+  const int Mh = (M + 1) / 2;
+  const int r_lo = h * Mh, r_hi = min(M, r_lo + Mh);
+  const double2* __restrict__ A = T.JW;
+  const int wave = tid >> 6, lane = tid & 63;
+  mfma_d4 gr = {0.0, 0.0, 0.0, 0.0}, gp = {0.0, 0.0, 0.0, 0.0};
+  const int c = cols[lane & 15];
+  const int roff = lane >> 4;
+  const int nks = (r_hi - r_lo + 3) / 4;
+  for (int ks0 = wave; ks0 < nks; ks0 += NW * KB) {
+    double2 x[KB];
+#pragma unroll
+    for (int t = 0; t < KB; ++t) {
+      const int r = r_lo + (ks0 + NW * t) * 4 + roff;
+      x[t] = (c >= 0 && r < r_hi) ? A[(long)c * M + r] : cmk(0.0, 0.0);
+    }
+#pragma unroll
+    for (int t = 0; t < KB; ++t) {
+      gr = __builtin_amdgcn_mfma_f64_16x16x4f64(x[t].x, x[t].x, gr, 0, 0, 0);
+      gr = __builtin_amdgcn_mfma_f64_16x16x4f64(x[t].y, x[t].y, gr, 0, 0, 0);
+      gp = __builtin_amdgcn_mfma_f64_16x16x4f64(x[t].x, x[t].y, gp, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    Gw[wave][0][roff + 4 * r][lane & 15] = gr[r];
+    Gw[wave][1][roff + 4 * r][lane & 15] = gp[r];
+  }
+  __syncthreads();
+  double* out = T.JG + ((long)pi * 2 + h) * 2 * W2 * W2;
+  for (int e = tid; e < W2 * W2; e += NT) {  // the waves' sums in wave order
+    const int i = e / W2, j = e % W2;
+    double sr = 0.0, sp = 0.0;
+    for (int w = 0; w < NW; ++w) {
+      sr += Gw[w][0][i][j];
+      sp += Gw[w][1][i][j];
+    }
+    out[e] = sr;
+    out[W2 * W2 + e] = sp;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_jacobi_rot(Task2* tasks, const Ent* ents, int step, int P, double tol_mult,
+                                                    int maxin) {
+  constexpr int W2 = 16, NT = kSplitNT;
+  const Task2& T = tasks[ents[blockIdx.y].slot];
+  const int sweep = ents[blockIdx.y].sweep;
+  const int tid = threadIdx.x;
+  __shared__ int cols[W2];
+  __shared__ double2 Gb[2][W2][W2 + 1];
+  __shared__ double2 Rb[2][W2][W2 + 1];
+  __shared__ InnerLds<W2> L;
+  const double fro2 = *T.fro2;
+  int pi, h, nbp;
+  if (!split_pair(T, step, P, sweep, cols, pi, h, nbp)) return;
+  const int N = T.N, M = T.JR;
+  {  // G from the two halves' partials (h = 0 first)
+    const double* g = T.JG + (long)pi * 2 * 2 * W2 * W2;
+    constexpr int H1 = 2 * W2 * W2, PP = W2 * W2;
+    for (int e = tid; e < W2 * W2; e += NT) {
+      const int i = e / W2, j = e % W2, et = j * W2 + i;
+      const double sr = g[e] + g[H1 + e];
+      const double pij = g[PP + e] + g[H1 + PP + e];
+      const double pji = g[PP + et] + g[H1 + PP + et];
+      Gb[0][i][j] = cmk(sr, pij - pji);
+    }
+  }
+  __syncthreads();
+  const double tol = tol_mult * (double)(M > 16 ? M : 16) * 0x1p-53;
+  const double ztol = fro2 * 0x1p-88;
+  const bool many = nbp >= 16;
+  const int cur = inner_jacobi_block<W2, NT>(Gb, Rb, L, cols, many ? maxin : 12, tol, ztol, many && step > 0);
+  if (L.any_rot) {
+    const int total = M + (T.jvec ? N : 0);
+    const int Th = (total + 1) / 2;
+    const int r_beg = h * Th, r_end = min(total, r_beg + Th);
+    const double2(*R)[W2 + 1] = Rb[cur];
+    for (int rr = r_beg + tid; rr < r_end; rr += NT) {
+      const bool inA = rr < M;
+      double2* X = inA ? T.JW : T.JV;
+      const int rows = inA ? M : N;
+      const int r = inA ? rr : rr - M;
+      double2 x[W2];
+#pragma unroll
+      for (int l = 0; l < W2; ++l) x[l] = cols[l] >= 0 ? X[(long)cols[l] * rows + r] : cmk(0.0, 0.0);
+#pragma unroll 4
+      for (int pc = 0; pc < W2; ++pc) {
+        double2 y = cmk(0.0, 0.0);
+#pragma unroll
+        for (int l = 0; l < W2; ++l) y = cfma(x[l], R[l][pc], y);
+        if (cols[pc] >= 0) X[(long)cols[pc] * rows + r] = y;
+      }
+    }
+    if (tid == 0) T.flags[sweep % 3] = 1;
+  }
+  if (h == 0 && tid < W2 && cols[tid] >= 0) T.sig2[cols[tid]] = Gb[cur][tid][tid].x;
 }
 
 // ------------------------------------------------------------------ ordering
@@ -758,6 +913,18 @@ hipError_t launch_jacobi_step(Task2* d_tasks, const Ent* d_ents, int nent, int m
                                    phase_clock); break;
     default: return hipErrorInvalidValue;
   }
+  MPS_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_jacobi_split(Task2* d_tasks, const Ent* d_ents, int nent, int maxN, int step, double tol_mult,
+                               int maxin, hipStream_t st) {
+  const int nb = (maxN + 7) / 8;
+  const int P = (nb + (nb & 1)) / 2;
+  const dim3 grid(2 * P, nent);
+  hipLaunchKernelGGL(k_jacobi_gram, grid, dim3(kSplitNT), 0, st, d_tasks, d_ents, step, P);
+  MPS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_jacobi_rot, grid, dim3(kSplitNT), 0, st, d_tasks, d_ents, step, P, tol_mult, maxin);
   MPS_LAUNCH_CHECK();
   return hipSuccess;
 }

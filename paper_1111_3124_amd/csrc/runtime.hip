@@ -95,6 +95,9 @@ struct Engine {
   int jacobi_streams = 2;
   bool fuse = true;  // mps_apply_gates multiplies single-site gates into neighbours
   bool qr = true;   // QR preconditioning of two-site Jacobi problems
+  // block width 8: a step launch serving at most this many updates runs as two launches
+  // of half-sized blocks (more blocks for few updates); 0: never
+  int split_max = 4;
   int device = 0;
   bool batch = false;  // a batch engine sizes workspace per update, not per slot
   // options (shared by every state of the engine)
@@ -439,6 +442,10 @@ struct Slot {
 // Workspace of a task with an M x Nt theta: theta and theta_w (later W; for a wide
 // theta theta_w^H, then Z), V (N x N, N = min(M, Nt)), the dd scratch (two N x N, one
 // M x N), sigma^2, the order and T1 (three-site first split).
+// partial Grams of the split Jacobi step (block width 8): the pairs of the padded
+// block count, two row halves, two 16 x 16 parts
+size_t jg_doubles(int N) { return (size_t)((N + 7) / 8 + 2) / 2 * 2 * 2 * 256; }
+
 size_t task_ws_bytes(bool dd, int M, int Nt, int t1) {
   const int N = std::min(M, Nt), P = dd ? 2 : 1;
   const size_t MN = (size_t)M * Nt, NN = (size_t)N * N;
@@ -449,6 +456,7 @@ size_t task_ws_bytes(bool dd, int M, int Nt, int t1) {
   // QR preconditioning: order, reflector heads, scales, panel factors (16 x 16 each)
   b += align_up(N * sizeof(int)) + align_up(N * sizeof(double2)) + align_up(N * sizeof(double)) +
        align_up((size_t)((N + 15) / 16) * 256 * sizeof(double2));
+  b += align_up(jg_doubles(N) * sizeof(double));  // split Jacobi step: partial Grams
   return b;
 }
 
@@ -508,6 +516,8 @@ void carve(bool dd, Task2& t, char* w, int* d_flags, double* d_stats, double* d_
   w += align_up(t.N * sizeof(double));
   t.qT = (double2*)w;
   w += align_up((size_t)((t.N + 15) / 16) * 256 * sizeof(double2));
+  t.JG = (double*)w;
+  w += align_up(jg_doubles(t.N) * sizeof(double));
   t.qr = 0;
   t.JW = t.thw;
   t.JV = t.V;
@@ -933,13 +943,19 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
       }
       for (int stp = 0; stp < nsteps; ++stp) {
         long long* pc = (E->d_phase && stp == nsteps / 2) ? E->d_phase : nullptr;
+        const bool split_a = bw == 8 && !pc && (int)ja.size() <= E->split_max;
+        const bool split_b = bw == 8 && (int)jb.size() <= E->split_max;
         if (stp < nsa) {
-          e = mpsk::launch_jacobi_step(dt, ea, (int)ja.size(), mNa, bw, stp, E->tol_mult, E->max_inner, st, pc);
+          e = split_a ? mpsk::launch_jacobi_split(dt, ea, (int)ja.size(), mNa, stp, E->tol_mult, E->max_inner, st)
+                      : mpsk::launch_jacobi_step(dt, ea, (int)ja.size(), mNa, bw, stp, E->tol_mult, E->max_inner, st,
+                                                 pc);
           if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("jacobi: ") + hipGetErrorString(e));
         }
         if (stp < nsb) {
-          e = mpsk::launch_jacobi_step(dt, eb, (int)jb.size(), mNb, bw, stp, E->tol_mult, E->max_inner, E->stream2,
-                                       nullptr);
+          e = split_b ? mpsk::launch_jacobi_split(dt, eb, (int)jb.size(), mNb, stp, E->tol_mult, E->max_inner,
+                                                  E->stream2)
+                      : mpsk::launch_jacobi_step(dt, eb, (int)jb.size(), mNb, bw, stp, E->tol_mult, E->max_inner,
+                                                 E->stream2, nullptr);
           if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("jacobi: ") + hipGetErrorString(e));
         }
       }
@@ -1274,6 +1290,11 @@ int set_option(Engine* E, int prec, int key, double value, std::string* err) {
     case MPS_OPT_MAX_SLOTS:
       if (!(value >= 1 && value <= 65536)) return fail(err, MPS_EINVAL, "slot limit out of range");
       E->max_slots = (int)value;
+      return MPS_OK;
+    case MPS_OPT_STEP_SPLIT:
+      if (!(value >= 0 && value <= 1 << 20 && value == (double)(int)value))
+        return fail(err, MPS_EINVAL, "step split limit must be a non-negative integer");
+      E->split_max = (int)value;
       return MPS_OK;
     case MPS_OPT_QR:
       if (!(value == 0 || value == 1)) return fail(err, MPS_EINVAL, "QR switch must be 0 or 1");
