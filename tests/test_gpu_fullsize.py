@@ -54,3 +54,26 @@ def test_update_chi256(B, fixture, prec, tol):
         err = float(np.max(np.abs(d.amplitudes(inp["bits"]) - (ah + al))))
     print(f"max |amplitude error| = {err:.3e} (scale {scale:.3e})", flush=True)
     assert err <= tol * scale
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_update_chi256_split_step_bit_identical(B, fixture, prec):
+    """The Jacobi step as one fused launch or as the two-launch split form (used for
+    launches of few updates) forms the same Gram in the same order: the update's
+    Schmidt values and amplitudes agree bit for bit."""
+    _, inp = fixture
+    print(f"split vs fused step: prec={prec} n={inp['n']} site={inp['first']}", flush=True)
+    out = []
+    for limit in (0, 4):
+        d = B.MPS(inp["n"], inp["chi"], inp["eps"], prec)
+        d.set_option(B.MPS_OPT_STEP_SPLIT, limit)
+        d.load(inp["B"], inp["lam"])
+        d.apply(inp["first"], 2, inp["U"])
+        lam = d.schmidt_dd(inp["first"]) if prec else (d.schmidt(inp["first"]),)
+        amp = d.amplitudes(inp["bits"], dd=True) if prec else (d.amplitudes(inp["bits"]),)
+        out.append((d.bond_dims(), lam, amp, d.stats()["sweeps"]))
+        d.close()
+    (dims0, lam0, amp0, sw0), (dims1, lam1, amp1, sw1) = out
+    assert dims0 == dims1 and sw0 == sw1
+    for a, b in zip(lam0 + amp0, lam1 + amp1):
+        assert np.array_equal(a, b)
