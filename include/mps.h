@@ -94,7 +94,11 @@ enum mps_option {
                                  this many updates (default 4; 0: none) runs as two
                                  launches (partial Grams, then rotations and updates) of
                                  two 256-thread blocks a column-block pair, for more
-                                 parallelism when few updates are in flight             */
+                                 parallelism when few updates are in flight             */,
+  MPS_OPT_DD_STREAM = 14      /* 1 (default): dd refinement passes, dd polish sweeps and
+                                 the dd promotion of converged updates run on a stream of
+                                 their own, overlapping the FP64 sweeps of the others;
+                                 0: on the handle's stream                              */
 };
 
 /* Diagnostics of the most recent split (the last one of a three-qubit gate). */

@@ -92,6 +92,12 @@ struct Engine {
   // tick's Jacobi sweep of the updates already iterating
   hipStream_t stream3 = nullptr;
   hipEvent_t ev_qr = nullptr;
+  // dd refinement passes, dd polish sweeps and the dd promotion of converged updates
+  // run on stream4, overlapping the FP64 sweeps of the others; joined before every
+  // readback of the rotation flags
+  hipStream_t stream4 = nullptr;
+  hipEvent_t ev_dd_fork = nullptr, ev_dd_join = nullptr;
+  bool dd_stream = true;
   int jacobi_streams = 2;
   bool fuse = true;  // mps_apply_gates multiplies single-site gates into neighbours
   bool qr = true;   // QR preconditioning of two-site Jacobi problems
@@ -207,6 +213,9 @@ Engine* engine_new(int prec, void* hip_stream, std::string* err) {
   if (e == hipSuccess) e = hipEventCreateWithFlags(&E->ev_join, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&E->stream3, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&E->ev_qr, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&E->stream4, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&E->ev_dd_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&E->ev_dd_join, hipEventDisableTiming);
   if (e != hipSuccess) {
     *err = std::string("engine: ") + hipGetErrorString(e);
     engine_free(E);
@@ -228,6 +237,12 @@ void engine_free(Engine* E) {
     (void)hipStreamSynchronize(E->stream3);
     (void)hipStreamDestroy(E->stream3);
   }
+  if (E->stream4) {
+    (void)hipStreamSynchronize(E->stream4);
+    (void)hipStreamDestroy(E->stream4);
+  }
+  if (E->ev_dd_fork) (void)hipEventDestroy(E->ev_dd_fork);
+  if (E->ev_dd_join) (void)hipEventDestroy(E->ev_dd_join);
   if (E->ev_qr) (void)hipEventDestroy(E->ev_qr);
   if (E->ev_fork) (void)hipEventDestroy(E->ev_fork);
   if (E->ev_join) (void)hipEventDestroy(E->ev_join);
@@ -256,19 +271,22 @@ struct Timed {
   Engine* E;
   EvPair p{};
   bool on;
-  // `launches` kernels are enqueued between the two events
-  Timed(Engine* EE, int cls, int launches = 1) : E(EE), on(EE->timing) {
+  hipStream_t s;
+  // `launches` kernels are enqueued on stream `ss` (default: the engine's) between
+  // the two events
+  Timed(Engine* EE, int cls, int launches = 1, hipStream_t ss = nullptr)
+      : E(EE), on(EE->timing), s(ss ? ss : EE->stream) {
     if (on) {
       p.a = ev_get(E);
       p.b = ev_get(E);
       p.cls = cls;
       p.n = launches;
-      (void)hipEventRecord(p.a, E->stream);
+      (void)hipEventRecord(p.a, s);
     }
   }
   ~Timed() {
     if (on) {
-      (void)hipEventRecord(p.b, E->stream);
+      (void)hipEventRecord(p.b, s);
       E->pending.push_back(p);
     }
   }
@@ -677,6 +695,24 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
   int rot0 = 0;  // first state scanned at admission (rotates for fairness)
   hipError_t e;
   hipStream_t st = E->stream;
+  // the dd work's stream; its launches follow everything queued on st so far (fork)
+  // and st waits for them before reading flags back (join)
+  hipStream_t sd = (dd && E->dd_stream) ? E->stream4 : st;
+  bool sd_pending = false;
+  auto fork_dd = [&]() -> hipError_t {
+    if (sd == st) return hipSuccess;
+    hipError_t ee = hipEventRecord(E->ev_dd_fork, st);
+    if (ee == hipSuccess) ee = hipStreamWaitEvent(sd, E->ev_dd_fork, 0);
+    sd_pending = true;
+    return ee;
+  };
+  auto join_dd = [&]() -> hipError_t {
+    if (!sd_pending) return hipSuccess;
+    sd_pending = false;
+    hipError_t ee = hipEventRecord(E->ev_dd_join, sd);
+    if (ee == hipSuccess) ee = hipStreamWaitEvent(st, E->ev_dd_join, 0);
+    return ee;
+  };
   int dirty_lo = S, dirty_hi = -1;  // task descriptors changed since the last upload
   auto mark = [&](int si) { dirty_lo = std::min(dirty_lo, si); dirty_hi = std::max(dirty_hi, si); };
   auto upload_tasks = [&]() -> hipError_t {
@@ -913,6 +949,34 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
         continue;  // only single-site gates were admitted; admit the rest
       }
     }
+    // dd refinement passes and polish sweeps first, on the dd stream, so that they
+    // overlap the FP64 sweeps launched below
+    if (!rl.empty() || !dl.empty()) {
+      mpsk::Ent* elr = rl.empty() ? nullptr : upload_list(LR, ents_of(rl));
+      mpsk::Ent* eld = dl.empty() ? nullptr : upload_list(LD, ents_of(dl));
+      if ((!rl.empty() && !elr) || (!dl.empty() && !eld)) return fail(err, MPS_EDEVICE, "list upload failed");
+      HIPCHK(err, fork_dd());
+      if (!rl.empty()) {
+        int mM = 0, mN = 0;
+        for (int si : rl) { mM = std::max(mM, slot[si].JM); mN = std::max(mN, slot[si].N); }
+        Timed tm(E, 6, 1, sd);
+        E->slot_sweeps_dd += (long)rl.size();
+        e = mpsk::launch_ddref_pass(dt, elr, (int)rl.size(), mM, mN, E->tol_mult, sd);
+        if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("dd refinement: ") + hipGetErrorString(e));
+      }
+      if (!dl.empty()) {
+        int mN = 0;
+        for (int si : dl) mN = std::max(mN, slot[si].N);
+        const int nb = (mN + 7) / 8;
+        const int nsteps = nb + (nb & 1) - 1;
+        Timed tm(E, 6, nsteps, sd);
+        E->slot_sweeps_dd += (long)dl.size();
+        for (int stp = 0; stp < nsteps; ++stp) {
+          e = mpsk::launch_jacobi_step_dd(dt, eld, (int)dl.size(), mN, stp, E->tol_mult, E->max_inner, sd);
+          if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("dd jacobi: ") + hipGetErrorString(e));
+        }
+      }
+    }
     if (!jl.empty()) {
       // two halves (alternate updates) on two streams when there are at least two
       const bool two = E->jacobi_streams == 2 && jl.size() >= 2;
@@ -964,30 +1028,6 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
         HIPCHK(err, hipStreamWaitEvent(st, E->ev_join, 0));
       }
     }
-    if (!rl.empty()) {
-      mpsk::Ent* el = upload_list(LR, ents_of(rl));
-      if (!el) return fail(err, MPS_EDEVICE, "list upload failed");
-      int mM = 0, mN = 0;
-      for (int si : rl) { mM = std::max(mM, slot[si].JM); mN = std::max(mN, slot[si].N); }
-      Timed tm(E, 6);
-      E->slot_sweeps_dd += (long)rl.size();
-      e = mpsk::launch_ddref_pass(dt, el, (int)rl.size(), mM, mN, E->tol_mult, st);
-      if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("dd refinement: ") + hipGetErrorString(e));
-    }
-    if (!dl.empty()) {
-      mpsk::Ent* el = upload_list(LD, ents_of(dl));
-      if (!el) return fail(err, MPS_EDEVICE, "list upload failed");
-      int mN = 0;
-      for (int si : dl) mN = std::max(mN, slot[si].N);
-      const int nb = (mN + 7) / 8;
-      const int nsteps = nb + (nb & 1) - 1;
-      Timed tm(E, 6, nsteps);
-      E->slot_sweeps_dd += (long)dl.size();
-      for (int stp = 0; stp < nsteps; ++stp) {
-        e = mpsk::launch_jacobi_step_dd(dt, el, (int)dl.size(), mN, stp, E->tol_mult, E->max_inner, st);
-        if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("dd jacobi: ") + hipGetErrorString(e));
-      }
-    }
     // the QR factorisations launched this tick: wait for them (the sweep above is
     // already queued on the other streams), then their slots start iterating
     if (qr_pending) {
@@ -997,6 +1037,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
       qr_pending = false;
     }
     // ---- 3. convergence
+    HIPCHK(err, join_dd());
     if (!jl.empty() || !rl.empty() || !dl.empty()) {
       HIPCHK(err, hipMemcpyAsync(hflags, d_flags, sizeof(int) * 3 * S, hipMemcpyDeviceToHost, st));
       HIPCHK(err, hipStreamSynchronize(st));
@@ -1058,7 +1099,8 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
       unsynced = true;
       mpsk::Ent* el = upload_list(LPOL, ents_of(to_polish));
       if (!el) return fail(err, MPS_EDEVICE, "list upload failed");
-      e = mpsk::launch_flags_clear(dt, el, (int)to_polish.size(), st);
+      HIPCHK(err, fork_dd());
+      e = mpsk::launch_flags_clear(dt, el, (int)to_polish.size(), sd);
       if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("flags: ") + hipGetErrorString(e));
     }
     if (!enter.empty()) {
@@ -1091,8 +1133,12 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
       }
       int mM = 0, mN = 0;
       for (int si : enter) { mM = std::max(mM, slot[si].JM); mN = std::max(mN, slot[si].N); }
-      Timed tm(E, 6);
-      e = mpsk::launch_dd_enter(dt, el, (int)enter.size(), mM, mN, st);
+      // the QR step and the descriptor changes above stay on st (a descriptor upload
+      // must not overtake a kernel that reads the old one); the promotion after them
+      // runs on the dd stream
+      HIPCHK(err, fork_dd());
+      Timed tm(E, 6, 1, sd);
+      e = mpsk::launch_dd_enter(dt, el, (int)enter.size(), mM, mN, sd);
       if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("dd enter: ") + hipGetErrorString(e));
     }
     // ---- 4. finalise converged slots
@@ -1229,6 +1275,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
                    active.end());
     }
   }
+  HIPCHK(err, join_dd());
   HIPCHK(err, hipStreamSynchronize(st));
   harvest_timing(E);
   // per state: diagnostics of its last multi-site gate in queue order
@@ -1290,6 +1337,10 @@ int set_option(Engine* E, int prec, int key, double value, std::string* err) {
     case MPS_OPT_MAX_SLOTS:
       if (!(value >= 1 && value <= 65536)) return fail(err, MPS_EINVAL, "slot limit out of range");
       E->max_slots = (int)value;
+      return MPS_OK;
+    case MPS_OPT_DD_STREAM:
+      if (!(value == 0 || value == 1)) return fail(err, MPS_EINVAL, "dd stream switch must be 0 or 1");
+      E->dd_stream = value != 0;
       return MPS_OK;
     case MPS_OPT_STEP_SPLIT:
       if (!(value >= 0 && value <= 1 << 20 && value == (double)(int)value))
