@@ -71,6 +71,25 @@ def test_brickwork_dd_gates_vs_oracle(B, oracle_mod):
         assert dd_diff(lh, ll, oh2, ol2) <= TOL
 
 
+def test_dd_stream_bit_identical(B):
+    """The dd work on its own stream (the default) or on the handle's stream: the same
+    kernels on the same inputs, so the same state bit for bit (truncated brickwork)."""
+    flush("dd stream on/off: n=12 depth=12 chi=16 eps=1e-10 seed=7")
+    n = 12
+    gates = [g for layer in W.brickwork_dd(n, 12, 7) for g in layer]
+    out = []
+    for on in (0, 1):
+        d = B.MPS(n, 16, 1e-10, B.MPS_PREC_DD)
+        d.set_option(B.MPS_OPT_DD_STREAM, on)
+        d.apply_gates(gates)
+        out.append((d.bond_dims(), d.amplitudes(all_bits(n), dd=True), [d.schmidt_dd(b) for b in range(n - 1)]))
+        d.close()
+    (d0, a0, s0), (d1, a1, s1) = out
+    assert d0 == d1
+    assert all(np.array_equal(x, y) for x, y in zip(a0, a1))
+    assert all(np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1]) for x, y in zip(s0, s1))
+
+
 def test_config1_fp64_gates_on_dd_path(B, oracle_mod):
     """Config-1 circuit (binary64 Haar gates taken as exact values) on the dd path."""
     flush("dd config1: n=10 depth=10 chi=32 seed=1 (binary64 gates)")
