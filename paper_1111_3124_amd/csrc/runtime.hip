@@ -226,6 +226,13 @@ Engine* engine_new(int prec, void* hip_stream, std::string* err) {
   return E;
 }
 
+// wait for every stream of the engine (before memory that kernels may touch is freed)
+void engine_sync(Engine* E) {
+  if (!E) return;
+  for (hipStream_t q : {E->stream, E->stream2, E->stream3, E->stream4})
+    if (q) (void)hipStreamSynchronize(q);
+}
+
 void engine_free(Engine* E) {
   if (!E) return;
   if (E->stream) (void)hipStreamSynchronize(E->stream);
@@ -310,6 +317,7 @@ void harvest_timing(Engine* E) {
 int ensure_ws(Engine* E, size_t bytes, std::string* err) {
   if (bytes > E->ws_size) {
     HIPCHK(err, hipStreamSynchronize(E->stream));
+    HIPCHK(err, hipStreamSynchronize(E->stream4));
     if (E->ws) HIPCHK(err, hipFree(E->ws));
     E->ws = nullptr;
     E->ws_size = 0;
@@ -698,6 +706,9 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
   // the dd work's stream; its launches follow everything queued on st so far (fork)
   // and st waits for them before reading flags back (join)
   hipStream_t sd = (dd && E->dd_stream) ? E->stream4 : st;
+  // a previous run that ended in an error may have left dd work queued: let it drain
+  // before any slot or workspace is reused
+  HIPCHK(err, hipStreamSynchronize(E->stream4));
   bool sd_pending = false;
   auto fork_dd = [&]() -> hipError_t {
     if (sd == st) return hipSuccess;
@@ -1604,7 +1615,7 @@ mps_handle mps_create(int n, int chi_max, double eps) {
 int mps_destroy(mps_handle h) {
   if (!h) return MPS_EINVAL;
   if (h->batch) return fail(h, MPS_ESTATE, "a batch member is destroyed with its batch");
-  if (h->E && h->E->stream) (void)hipStreamSynchronize(h->E->stream);
+  engine_sync(h->E);
   if (h->mem) (void)hipFree(h->mem);
   if (h->own_engine) engine_free(h->E);
   delete h;
@@ -2223,7 +2234,7 @@ mps_batch_handle mps_batch_create(int count, const int* n, const int* chi_max, c
 
 int mps_batch_destroy(mps_batch_handle b) {
   if (!b) return MPS_EINVAL;
-  if (b->E && b->E->stream) (void)hipStreamSynchronize(b->E->stream);
+  engine_sync(b->E);
   for (mps_state* h : b->units) delete h;
   if (b->mem) (void)hipFree(b->mem);
   engine_free(b->E);
