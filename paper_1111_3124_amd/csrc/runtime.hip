@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <deque>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -632,6 +633,10 @@ size_t gate_need_cap(bool dd, const mps_state* h, int first, int k) {
 int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, int dims_total,
               const std::vector<int>& dims_off, const std::vector<GateRef>& gates, std::string* err) {
   if (gates.empty()) return MPS_OK;
+  // a previous run that ended in an error may have left QR factorisations or dd work
+  // queued: let them drain before any slot, list or workspace is reused
+  HIPCHK(err, hipStreamSynchronize(E->stream3));
+  HIPCHK(err, hipStreamSynchronize(E->stream4));
   const bool dd = E->prec == MPS_PREC_DD;
   const int nu = (int)U.size();
   std::vector<int> site_base(nu + 1, 0);
@@ -674,7 +679,10 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
   const size_t o_u8 = o_dims + align_up(sizeof(int) * dims_total);
   const size_t o_g1 = o_u8 + align_up(sizeof(double2) * 128 * S);
   const size_t o_ents = o_g1 + align_up(sizeof(Task1) * nsites);
-  constexpr int kLists = 14;  // new2, new3, jacobi (two + order), dd, dd-enter, final, final3, mid, znorm, ref, polish, qr z
+  // new2, new3, jacobi (two + order), dd, dd-enter, final, final3, mid, znorm, ref,
+  // polish, qr z, and a ring of kQrRing lists of QR factorisations in flight
+  constexpr int kQrRing = 4;
+  constexpr int kLists = 14 + kQrRing;
   const size_t list_bytes = align_up(sizeof(mpsk::Ent) * S);
   rc = ensure_small(E, o_ents + kLists * list_bytes, err);
   if (rc) return rc;
@@ -688,7 +696,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
   int* hdims = (int*)(E->h_stage + o_dims);
   double2* hu8 = (double2*)(E->h_stage + o_u8);
   double2* du8 = (double2*)(E->d_small + o_u8);
-  enum { LN2 = 0, LN3, LJ, LD, LENTER, LFIN, LFIN3, LMID, LZN, LR, LPOL, LJ2, LJO, LQZ };
+  enum { LN2 = 0, LN3, LJ, LD, LENTER, LFIN, LFIN3, LMID, LZN, LR, LPOL, LJ2, LJO, LQZ, LQR0 };
   auto hlist = [&](int i) { return E->h_stage + o_ents + i * list_bytes; };
   auto dlist = [&](int i) { return E->d_small + o_ents + i * list_bytes; };
 
@@ -706,9 +714,6 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
   // the dd work's stream; its launches follow everything queued on st so far (fork)
   // and st waits for them before reading flags back (join)
   hipStream_t sd = (dd && E->dd_stream) ? E->stream4 : st;
-  // a previous run that ended in an error may have left dd work queued: let it drain
-  // before any slot or workspace is reused
-  HIPCHK(err, hipStreamSynchronize(E->stream4));
   bool sd_pending = false;
   auto fork_dd = [&]() -> hipError_t {
     if (sd == st) return hipSuccess;
@@ -767,7 +772,29 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
   std::vector<int> active;  // slots not free
 
   bool unsynced = false;  // async copies from the pinned staging may still be pending
-  bool qr_pending = false;  // QR factorisations queued on stream3 this tick
+  // QR factorisations in flight on stream3, oldest first: completion event, list ring
+  // slot, the slots waiting (state 6); polled at the end of each tick, so that a
+  // factorisation longer than a sweep does not hold up the other updates' sweeps
+  struct QrBatch {
+    hipEvent_t ev;
+    std::vector<int> slots;
+  };
+  std::deque<QrBatch> qr_inflight;
+  int qr_ring = 0;
+  auto qr_poll = [&](bool block) -> hipError_t {
+    while (!qr_inflight.empty()) {
+      QrBatch& b = qr_inflight.front();
+      const hipError_t q = block ? hipEventSynchronize(b.ev) : hipEventQuery(b.ev);
+      if (q == hipErrorNotReady) break;
+      if (q != hipSuccess) return q;
+      for (int si : b.slots)
+        if (slot[si].state == 6) slot[si].state = 1;
+      E->evpool.push_back(b.ev);
+      qr_inflight.pop_front();
+      if (block) block = false;  // one finished batch is progress enough
+    }
+    return hipSuccess;
+  };
   while (true) {
     // the staging buffers are rewritten below: wait for copies a previous tick left
     if (unsynced) {
@@ -936,14 +963,22 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
                    : mpsk::launch_theta2(dt, el, (int)nl.size(), mM, mNt, st);
         }
         if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("theta: ") + hipGetErrorString(e));
-        bool anyqr = false;
-        for (int si : nl) anyqr = anyqr || ht[si].qr;
-        if (anyqr) {  // on stream3 after the theta kernels; joined before the tick's readback
+        std::vector<int> qrs;
+        for (int si : nl)
+          if (ht[si].qr) qrs.push_back(si);
+        if (!qrs.empty()) {  // on stream3 after the theta kernels, with a list of its own
+          if ((int)qr_inflight.size() >= kQrRing) HIPCHK(err, qr_poll(true));  // frees the oldest ring slot
+          mpsk::Ent* eq = upload_list(LQR0 + qr_ring, ents_of(qrs));
+          if (!eq) return fail(err, MPS_EDEVICE, "list upload failed");
+          qr_ring = (qr_ring + 1) % kQrRing;
           HIPCHK(err, hipEventRecord(E->ev_qr, st));
           HIPCHK(err, hipStreamWaitEvent(E->stream3, E->ev_qr, 0));
-          e = mpsk::launch_qr_factor(dt, el, (int)nl.size(), mM, mN, E->stream3);
+          e = mpsk::launch_qr_factor(dt, eq, (int)qrs.size(), mM, mN, E->stream3);
           if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("qr: ") + hipGetErrorString(e));
-          qr_pending = true;
+          hipEvent_t done = ev_get(E);
+          if (!done) return fail(err, MPS_EDEVICE, "event creation failed");
+          HIPCHK(err, hipEventRecord(done, E->stream3));
+          qr_inflight.push_back(QrBatch{done, qrs});
         }
       }
     }
@@ -954,7 +989,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
       if (slot[si].state == 2) rl.push_back(si);
       if (slot[si].state == 4) dl.push_back(si);
     }
-    if (jl.empty() && rl.empty() && dl.empty() && !qr_pending) {
+    if (jl.empty() && rl.empty() && dl.empty() && qr_inflight.empty()) {
       if (active.empty()) {
         if (!remaining) break;
         continue;  // only single-site gates were admitted; admit the rest
@@ -1039,14 +1074,9 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
         HIPCHK(err, hipStreamWaitEvent(st, E->ev_join, 0));
       }
     }
-    // the QR factorisations launched this tick: wait for them (the sweep above is
-    // already queued on the other streams), then their slots start iterating
-    if (qr_pending) {
-      HIPCHK(err, hipStreamSynchronize(E->stream3));
-      for (int si : active)
-        if (slot[si].state == 6) slot[si].state = 1;
-      qr_pending = false;
-    }
+    // finished QR factorisations: their slots start iterating at the next tick; when
+    // this tick has no sweep work at all, wait for the oldest
+    HIPCHK(err, qr_poll(jl.empty() && rl.empty() && dl.empty()));
     // ---- 3. convergence
     HIPCHK(err, join_dd());
     if (!jl.empty() || !rl.empty() || !dl.empty()) {
@@ -1288,6 +1318,11 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
   }
   HIPCHK(err, join_dd());
   HIPCHK(err, hipStreamSynchronize(st));
+  for (QrBatch& b : qr_inflight) {  // (none is left once every slot has finished)
+    HIPCHK(err, hipEventSynchronize(b.ev));
+    E->evpool.push_back(b.ev);
+  }
+  qr_inflight.clear();
   harvest_timing(E);
   // per state: diagnostics of its last multi-site gate in queue order
   for (int u = 0; u < nu; ++u) {
