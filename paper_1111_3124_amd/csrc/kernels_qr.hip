@@ -256,7 +256,9 @@ typedef double qr_d4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_qr_apply(Task2* tasks, const Ent* ents, int p0, int mode) {
   constexpr int NW = 4, KB = 8;  // waves; k-steps of loads in flight
   const Task2& T = tasks[ents[blockIdx.y].slot];
-  if (!T.qr) return;
+  // mode 1 is given QR tasks only, and reads no field that the conversion to the
+  // transposed problem changes (the descriptor may already be converted)
+  if (mode == 0 && !T.qr) return;
   const int M = T.M, N = T.N;
   if (p0 >= N) return;
   const int nb = N - p0 < kPanel ? N - p0 : kPanel;

@@ -680,9 +680,10 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
   const size_t o_g1 = o_u8 + align_up(sizeof(double2) * 128 * S);
   const size_t o_ents = o_g1 + align_up(sizeof(Task1) * nsites);
   // new2, new3, jacobi (two + order), dd, dd-enter, final, final3, mid, znorm, ref,
-  // polish, qr z, and a ring of kQrRing lists of QR factorisations in flight
+  // polish, qr z, dd-enter QR tasks, and a ring of kQrRing lists of QR factorisations
+  // in flight
   constexpr int kQrRing = 4;
-  constexpr int kLists = 14 + kQrRing;
+  constexpr int kLists = 15 + kQrRing;
   const size_t list_bytes = align_up(sizeof(mpsk::Ent) * S);
   rc = ensure_small(E, o_ents + kLists * list_bytes, err);
   if (rc) return rc;
@@ -696,7 +697,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
   int* hdims = (int*)(E->h_stage + o_dims);
   double2* hu8 = (double2*)(E->h_stage + o_u8);
   double2* du8 = (double2*)(E->d_small + o_u8);
-  enum { LN2 = 0, LN3, LJ, LD, LENTER, LFIN, LFIN3, LMID, LZN, LR, LPOL, LJ2, LJO, LQZ, LQR0 };
+  enum { LN2 = 0, LN3, LJ, LD, LENTER, LFIN, LFIN3, LMID, LZN, LR, LPOL, LJ2, LJO, LQZ, LQL, LQR0 };
   auto hlist = [&](int i) { return E->h_stage + o_ents + i * list_bytes; };
   auto dlist = [&](int i) { return E->d_small + o_ents + i * list_bytes; };
 
@@ -1149,35 +1150,36 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
       mpsk::Ent* el = upload_list(LENTER, ents_of(enter));
       if (!el) return fail(err, MPS_EDEVICE, "list upload failed");
       // QR-preconditioned tasks: V <- Q V_x, then the refinement of the transposed
-      // problem (square thetas: the shapes stay the same)
-      bool anyqr = false;
+      // problem (square thetas: the shapes stay the same).  The descriptors are
+      // converted first; the Q application reads none of the converted fields, so it
+      // and the promotion both follow the upload on the dd stream.
+      std::vector<int> qrl;
       int qN = 0;
       for (int si : enter)
         if (ht[si].qr) {
-          anyqr = true;
+          qrl.push_back(si);
           qN = std::max(qN, ht[si].N);
         }
-      if (anyqr) {
-        {
-          Timed tq(E, 6);
-          e = mpsk::launch_qr_left(dt, el, (int)enter.size(), qN, st);
-          if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("qr left: ") + hipGetErrorString(e));
+      mpsk::Ent* eql = nullptr;
+      if (!qrl.empty()) {
+        eql = upload_list(LQL, ents_of(qrl));
+        if (!eql) return fail(err, MPS_EDEVICE, "list upload failed");
+        for (int si : qrl) {
+          qr_to_transposed(ht[si]);
+          slot[si].JM = ht[si].JM;
+          slot[si].N = ht[si].N;
+          mark(si);
         }
-        for (int si : enter)
-          if (ht[si].qr) {
-            qr_to_transposed(ht[si]);
-            slot[si].JM = ht[si].JM;
-            slot[si].N = ht[si].N;
-            mark(si);
-          }
         HIPCHK(err, upload_tasks());
       }
       int mM = 0, mN = 0;
       for (int si : enter) { mM = std::max(mM, slot[si].JM); mN = std::max(mN, slot[si].N); }
-      // the QR step and the descriptor changes above stay on st (a descriptor upload
-      // must not overtake a kernel that reads the old one); the promotion after them
-      // runs on the dd stream
       HIPCHK(err, fork_dd());
+      if (eql) {
+        Timed tq(E, 6, 1, sd);
+        e = mpsk::launch_qr_left(dt, eql, (int)qrl.size(), qN, sd);
+        if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("qr left: ") + hipGetErrorString(e));
+      }
       Timed tm(E, 6, 1, sd);
       e = mpsk::launch_dd_enter(dt, el, (int)enter.size(), mM, mN, sd);
       if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("dd enter: ") + hipGetErrorString(e));
