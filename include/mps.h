@@ -98,7 +98,11 @@ enum mps_option {
   MPS_OPT_DD_STREAM = 14      /* 1 (default): dd refinement passes, dd polish sweeps and
                                  the dd promotion of converged updates run on a stream of
                                  their own, overlapping the FP64 sweeps of the others;
-                                 0: on the handle's stream                              */
+                                 0: on the handle's stream                              */,
+  MPS_OPT_MAX_INNER_FEW = 15  /* inner sweeps per block pair for tasks with fewer than 16
+                                 column blocks (default 1 FP64, 12 dd; up to that many
+                                 sweeps over all the pair's column pairs, ending early
+                                 once one rotates nothing)                              */
 };
 
 /* Diagnostics of the most recent split (the last one of a three-qubit gate). */

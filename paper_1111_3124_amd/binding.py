@@ -26,7 +26,7 @@ MPS_PREC_FP64, MPS_PREC_DD = 0, 1
 MPS_OPT_MAX_SWEEPS, MPS_OPT_JACOBI_TOL, MPS_OPT_KERNEL_TIMING, MPS_OPT_RANK_FLOOR = 1, 2, 3, 4
 MPS_OPT_BLOCK_WIDTH, MPS_OPT_MAX_INNER, MPS_OPT_MAX_SLOTS, MPS_OPT_WORKSPACE_MB = 5, 6, 7, 8
 MPS_OPT_DD_REFINE, MPS_OPT_JACOBI_STREAMS, MPS_OPT_FUSE, MPS_OPT_QR, MPS_OPT_STEP_SPLIT = 9, 10, 11, 12, 13
-MPS_OPT_DD_STREAM = 14
+MPS_OPT_DD_STREAM, MPS_OPT_MAX_INNER_FEW = 14, 15
 KERNEL_CLASSES = ["theta", "jacobi", "truncate", "split", "gate1", "amplitude", "dd_refine", "rdo"]
 COUNTER_SWEEPS, COUNTER_SWEEPS_DD = 8, 9
 

@@ -248,7 +248,7 @@ __device__ int inner_jacobi_block(double2 (&G)[2][W2][W2 + 1], double2 (&R)[2][W
 //   3. A_P <- A_P R and V_P <- V_P R (a row a thread), sig2 <- diag(R^H G R).
 template <int BW>
 __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* ents, int step, double tol_mult,
-                                                        int maxin, long long* phase_clock) {
+                                                        int maxin, int maxin_few, long long* phase_clock) {
   constexpr int NT = 512, NW = NT / 64;
   constexpr int W2 = 2 * BW;
   constexpr int TB = W2 / 8;
@@ -416,7 +416,7 @@ __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* en
   //    Within a sweep, the pairs inside each block are rotated at its first step; the
   //    later steps rotate only the pairs across the two blocks.
   const bool many = nbp >= 16;
-  const int cur = inner_jacobi_block<W2, NT>(Gb, Rb, L, cols, many ? maxin : 12, tol, ztol, many && step > 0);
+  const int cur = inner_jacobi_block<W2, NT>(Gb, Rb, L, cols, many ? maxin : maxin_few, tol, ztol, many && step > 0);
   const int res_rot = L.any_rot;
   if (clk) phase_clock[2] = wall_clock64();
 
@@ -558,7 +558,7 @@ __global__ __launch_bounds__(256) void k_jacobi_gram(Task2* tasks, const Ent* en
 }
 
 __global__ __launch_bounds__(256) void k_jacobi_rot(Task2* tasks, const Ent* ents, int step, int P, double tol_mult,
-                                                    int maxin) {
+                                                    int maxin, int maxin_few) {
   constexpr int W2 = 16, NT = kSplitNT;
   const Task2& T = tasks[ents[blockIdx.y].slot];
   const int sweep = ents[blockIdx.y].sweep;
@@ -586,7 +586,7 @@ __global__ __launch_bounds__(256) void k_jacobi_rot(Task2* tasks, const Ent* ent
   const double tol = tol_mult * (double)(M > 16 ? M : 16) * 0x1p-53;
   const double ztol = fro2 * 0x1p-88;
   const bool many = nbp >= 16;
-  const int cur = inner_jacobi_block<W2, NT>(Gb, Rb, L, cols, many ? maxin : 12, tol, ztol, many && step > 0);
+  const int cur = inner_jacobi_block<W2, NT>(Gb, Rb, L, cols, many ? maxin : maxin_few, tol, ztol, many && step > 0);
   if (L.any_rot) {
     const int total = M + (T.jvec ? N : 0);
     const int Th = (total + 1) / 2;
@@ -901,16 +901,16 @@ hipError_t launch_theta2(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, 
 }
 
 hipError_t launch_jacobi_step(Task2* d_tasks, const Ent* d_ents, int nent, int maxN, int bw, int step,
-                              double tol_mult, int maxin, hipStream_t st, long long* phase_clock) {
+                              double tol_mult, int maxin, int maxin_few, hipStream_t st, long long* phase_clock) {
   const int nb = (maxN + bw - 1) / bw;
   const dim3 grid((nb + (nb & 1)) / 2, nent);
   switch (bw) {
     case 4: hipLaunchKernelGGL(k_jacobi_step<4>, grid, dim3(512), 0, st, d_tasks, d_ents, step, tol_mult, maxin,
-                                   phase_clock); break;
+                                   maxin_few, phase_clock); break;
     case 8: hipLaunchKernelGGL(k_jacobi_step<8>, grid, dim3(512), 0, st, d_tasks, d_ents, step, tol_mult, maxin,
-                                   phase_clock); break;
+                                   maxin_few, phase_clock); break;
     case 16: hipLaunchKernelGGL(k_jacobi_step<16>, grid, dim3(512), 0, st, d_tasks, d_ents, step, tol_mult, maxin,
-                                   phase_clock); break;
+                                   maxin_few, phase_clock); break;
     default: return hipErrorInvalidValue;
   }
   MPS_LAUNCH_CHECK();
@@ -918,13 +918,14 @@ hipError_t launch_jacobi_step(Task2* d_tasks, const Ent* d_ents, int nent, int m
 }
 
 hipError_t launch_jacobi_split(Task2* d_tasks, const Ent* d_ents, int nent, int maxN, int step, double tol_mult,
-                               int maxin, hipStream_t st) {
+                               int maxin, int maxin_few, hipStream_t st) {
   const int nb = (maxN + 7) / 8;
   const int P = (nb + (nb & 1)) / 2;
   const dim3 grid(2 * P, nent);
   hipLaunchKernelGGL(k_jacobi_gram, grid, dim3(kSplitNT), 0, st, d_tasks, d_ents, step, P);
   MPS_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_jacobi_rot, grid, dim3(kSplitNT), 0, st, d_tasks, d_ents, step, P, tol_mult, maxin);
+  hipLaunchKernelGGL(k_jacobi_rot, grid, dim3(kSplitNT), 0, st, d_tasks, d_ents, step, P, tol_mult, maxin,
+                     maxin_few);
   MPS_LAUNCH_CHECK();
   return hipSuccess;
 }

@@ -18,11 +18,11 @@ hipError_t launch_theta2(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, 
 // phase_clock: NULL, or 5 long longs receiving wall_clock64() stamps of block (0, 0)
 // (start, after Gram, after inner Jacobi, end, rotated?) for phase profiling
 hipError_t launch_jacobi_step(Task2* d_tasks, const Ent* d_ents, int nent, int maxN, int bw, int step, double tol_mult,
-                              int maxin, hipStream_t st, long long* phase_clock = nullptr);
+                              int maxin, int maxin_few, hipStream_t st, long long* phase_clock = nullptr);
 // the same step as two launches (partial Grams, then rotations and updates) of two
 // 256-thread blocks a column-block pair; block width 8
 hipError_t launch_jacobi_split(Task2* d_tasks, const Ent* d_ents, int nent, int maxN, int step, double tol_mult,
-                               int maxin, hipStream_t st);
+                               int maxin, int maxin_few, hipStream_t st);
 // column order of each task's sweep (sorted by the previous sweep's column norms)
 hipError_t launch_jacobi_order(Task2* d_tasks, const Ent* d_ents, int nent, hipStream_t st);
 // QR preconditioning (tasks with qr set): theta_w's columns ordered by norm, the

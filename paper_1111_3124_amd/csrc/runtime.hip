@@ -111,6 +111,10 @@ struct Engine {
   int max_sweeps = 40;
   int max_sweeps_dd = 16;
   int max_inner = 1;
+  // inner sweeps per block pair, tasks with fewer than 16 blocks: one for FP64 (the
+  // cheapest overall); dd engines keep every pair diagonalised per step (12), the
+  // starting point their refinement and polish expect on rank-deficient thetas
+  int max_inner_few = 1;
   int block_width = 8;
   int max_slots = 32;
   double ws_limit = 16.0 * (1ull << 30);  // batch engines: workspace arena cap, bytes
@@ -199,6 +203,7 @@ void engine_free(Engine* E);
 Engine* engine_new(int prec, void* hip_stream, std::string* err) {
   Engine* E = new Engine();
   E->prec = prec;
+  if (prec == MPS_PREC_DD) E->max_inner_few = 12;
   if (const char* dbg = std::getenv("MPS_DEBUG_SWEEPS")) E->debug_sweeps = dbg[0] == '1';
   hipError_t e = hipGetDevice(&E->device);
   if (e == hipSuccess) {
@@ -1057,15 +1062,18 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
         const bool split_a = bw == 8 && !pc && (int)ja.size() <= E->split_max;
         const bool split_b = bw == 8 && (int)jb.size() <= E->split_max;
         if (stp < nsa) {
-          e = split_a ? mpsk::launch_jacobi_split(dt, ea, (int)ja.size(), mNa, stp, E->tol_mult, E->max_inner, st)
-                      : mpsk::launch_jacobi_step(dt, ea, (int)ja.size(), mNa, bw, stp, E->tol_mult, E->max_inner, st,
+          e = split_a ? mpsk::launch_jacobi_split(dt, ea, (int)ja.size(), mNa, stp, E->tol_mult, E->max_inner,
+                                                  E->max_inner_few, st)
+                      : mpsk::launch_jacobi_step(dt, ea, (int)ja.size(), mNa, bw, stp, E->tol_mult, E->max_inner,
+                                                 E->max_inner_few, st,
                                                  pc);
           if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("jacobi: ") + hipGetErrorString(e));
         }
         if (stp < nsb) {
           e = split_b ? mpsk::launch_jacobi_split(dt, eb, (int)jb.size(), mNb, stp, E->tol_mult, E->max_inner,
-                                                  E->stream2)
+                                                  E->max_inner_few, E->stream2)
                       : mpsk::launch_jacobi_step(dt, eb, (int)jb.size(), mNb, bw, stp, E->tol_mult, E->max_inner,
+                                                 E->max_inner_few,
                                                  E->stream2, nullptr);
           if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("jacobi: ") + hipGetErrorString(e));
         }
@@ -1377,6 +1385,10 @@ int set_option(Engine* E, int prec, int key, double value, std::string* err) {
     case MPS_OPT_MAX_INNER:
       if (!(value >= 1 && value <= 64)) return fail(err, MPS_EINVAL, "inner sweep limit out of range");
       E->max_inner = (int)value;
+      return MPS_OK;
+    case MPS_OPT_MAX_INNER_FEW:
+      if (!(value >= 1 && value <= 64)) return fail(err, MPS_EINVAL, "inner sweep limit out of range");
+      E->max_inner_few = (int)value;
       return MPS_OK;
     case MPS_OPT_RANK_FLOOR:
       if (!(value >= 0 && value < 1)) return fail(err, MPS_EINVAL, "rank floor out of range");
