@@ -410,7 +410,7 @@ __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* en
   if (clk) phase_clock[1] = wall_clock64();
 
   // 2. inner Jacobi (with many column blocks a single inner sweep per step is enough:
-  //    the next steps revisit every column; with few blocks each pair is diagonalised)
+  //    the next steps revisit every column; with few blocks up to maxin_few sweeps)
   const double tol = tol_mult * (double)(M > 16 ? M : 16) * 0x1p-53;
   const double ztol = fro2 * 0x1p-88;
   //    Within a sweep, the pairs inside each block are rotated at its first step; the
