@@ -30,10 +30,11 @@ METRIC = "MPS gate updates/s at χ=256: FP64 vs dd-refined, error vs 256-bit ora
 N_QUBITS, CHI, EPS, SEED = 40, 256, 1e-12, 2
 PEAK_FP64 = 78.6e12  # MI355X FP64 vector (and matrix) peak, FLOP/s
 PEAK_HBM = 8.0e12    # MI355X HBM3E bandwidth, B/s
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jacobi_step_chi256_traffic.md")
-FP64_OPS_FILE = os.path.join(ROOT, "profiles", "jacobi_step_chi256_fp64_ops.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jacobi_step_chi256_{}_traffic.md")
+FP64_OPS_FILE = os.path.join(ROOT, "profiles", "jacobi_step_chi256_{}_fp64_ops.md")
 S_REF = 10  # reference sweep count of the algorithmic work unit
 KERNEL_SRC = os.path.join(ROOT, "paper_1111_3124_amd", "csrc", "kernels.hip")
+GOLDEN = os.path.join(ROOT, "tests", "golden", "update_chi256.json")
 
 
 def jacobi_flops(M: int, N: int) -> float:
@@ -81,7 +82,7 @@ def run_variant(B, W, prec: int, steps: int, warmup: int):
     for g in timed:
         assert dims[g.first - 1] == dims[g.first] == dims[g.first + 1] == CHI
     m.set_option(B.MPS_OPT_KERNEL_TIMING, 1)
-    for c in list(range(len(B.KERNEL_CLASSES))) + [B.COUNTER_SWEEPS, B.COUNTER_SWEEPS_DD]:
+    for c in list(range(len(B.KERNEL_CLASSES))) + [B.COUNTER_SWEEPS, B.COUNTER_SWEEPS_DD, B.COUNTER_NOCONV]:
         m.kernel_time(c, reset=True)
     m.sync()
     t0 = time.perf_counter()
@@ -91,13 +92,15 @@ def run_variant(B, W, prec: int, steps: int, warmup: int):
     ktimes = {name: m.kernel_time(c) for c, name in enumerate(B.KERNEL_CLASSES)}
     slot_sweeps = m.kernel_time(B.COUNTER_SWEEPS)[1]
     slot_sweeps_dd = m.kernel_time(B.COUNTER_SWEEPS_DD)[1]
+    noconv = m.kernel_time(B.COUNTER_NOCONV)[1]
     dims = m.bond_dims()
     assert all(dims[g.first] == CHI for g in timed)
     lam_ok = all(abs(float((m.schmidt(b) ** 2).sum()) - 1.0) < 1e-12 for b in range(N_QUBITS - 1))
     m.close()
     return dict(rate=len(timed) / dt, ms_per_step=1e3 * dt / steps, gates=len(timed), seconds=dt,
                 mean_sweeps=slot_sweeps / len(timed), mean_dd_sweeps=slot_sweeps_dd / len(timed),
-                slot_sweeps=slot_sweeps, ktimes=ktimes, lam_ok=lam_ok, noconv=rc != 0, steps=steps)
+                slot_sweeps=slot_sweeps, ktimes=ktimes, lam_ok=lam_ok, noconv=noconv, noconv_rc=rc != 0,
+                steps=steps)
 
 
 def step_bytes(M: int, N: int, jvec: int = 1) -> float:
@@ -128,17 +131,30 @@ def measured(path, key):
         return None
 
 
-def roofline(res, jvec: int):
-    """Dominant kernel: the FP64 Jacobi step (k_jacobi_step<8>).  A step serves each
-    iterating update with one of the nsteps = N/8 - 1 steps of its sweep:
-    step_flops(M, N) and step_bytes(M, N) of algorithmic work (jvec: V accumulated,
-    as in the dd variant; the FP64 variant's QR-preconditioned updates accumulate no
-    V).  The updates of a step are split into two halves whose launches run
-    concurrently on two streams, so a launch lasts about as long as the step.  Totals
-    over the timed region: update-sweeps executed x nsteps x those; achieved = total /
-    the steps' HIP-event time.  The primary bound is the one the kernel is closer to.
-    The counter-based figures (memory-fabric traffic, executed FP64 flops: VALU adds,
-    multiplies, 2 x FMAs, and MFMA operations) were taken on the dd variant."""
+def update_bytes(chi: int, dd: bool) -> float:
+    """Algorithmic HBM bytes of one two-site update at a = b = c = k = chi: the site
+    tensors read and written and the Schmidt values, 16 (2ab + 2bc + 2ak + 2kc) + 8a
+    + 256 bytes (x2 for double-double)."""
+    a = b = c = k = chi
+    return (16.0 * (2 * a * b + 2 * b * c + 2 * a * k + 2 * k * c) + 8.0 * a + 256.0) * (2 if dd else 1)
+
+
+def roofline(res, jvec: int, dd: bool):
+    """Dominant kernel: the Jacobi step (k_jacobi_step<8>), an FP64 contraction (the
+    pair Grams on the matrix cores, the rotations on the vector units; MI355X's FP64
+    matrix and vector peaks are both 78.6 TFLOP/s).  A step serves each iterating
+    update with one of the nsteps = N/8 - 1 steps of its sweep, and is credited with
+    the scalar method's work for it, J(M, N) / nsteps (step_flops; jvec: V
+    accumulated, as in the dd variant; the FP64 variant's QR-preconditioned updates
+    accumulate no V).  The updates of a step are split into two halves whose launches
+    run concurrently on two streams, so a launch lasts about as long as the step.
+    Totals over the timed region: update-sweeps executed x nsteps x step_flops;
+    achieved = total / the steps' HIP-event time.
+    `traffic`: memory-fabric bytes per launch from the committed FETCH_SIZE and
+    WRITE_SIZE counter summary of this variant (null once kernels.hip has changed);
+    `traffic_per_update` compares them, summed over an update's steps, with the
+    update's algorithmic bytes (update_bytes), and `hbm_algorithmic` gives those bytes
+    at the measured update rate against the HBM peak."""
     ms, launches = res["ktimes"]["jacobi"]
     if launches == 0:
         return None
@@ -147,24 +163,57 @@ def roofline(res, jvec: int):
     sec = ms * 1e-3
     usteps = res["slot_sweeps"] * nsteps  # update-steps in the timed region
     flops = usteps * step_flops(M, N, jvec)
-    nbytes = usteps * step_bytes(M, N, jvec)
-    f_alu = flops / sec / PEAK_FP64
-    f_hbm = nbytes / sec / PEAK_HBM
-    per_step = measured(TRAFFIC_FILE, "bytes_per_update_step") if jvec else None
+    tag = "dd" if dd else "fp64"
+    per_step = measured(TRAFFIC_FILE.format(tag), "bytes_per_update_step")
     traffic = per_step * usteps / launches if per_step else None
-    hbm = {"bound": "hbm", "achieved": nbytes / sec / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": f_hbm,
-           "traffic": traffic, "bytes_per_launch": nbytes / launches}
-    alu = {"bound": "alu", "achieved": flops / sec / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": f_alu,
-           "traffic": traffic, "flops_per_launch": flops / launches}
-    ops = measured(FP64_OPS_FILE, "fp64_flops_per_update_step") if jvec else None
-    alu["executed"] = None if ops is None else {
+    ub = update_bytes(CHI, dd)
+    out = {"bound": "mfma", "achieved": flops / sec / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+           "frac": flops / sec / PEAK_FP64, "traffic": traffic,
+           "kernel": "k_jacobi_step<8>", "dtype": "f64", "flops_per_launch": flops / launches,
+           "avg_launch_us": 1e3 * ms / launches, "launches": launches, "concurrent_launches": 2,
+           "update_steps_per_launch": usteps / launches}
+    if per_step:
+        steps_per_update = res["mean_sweeps"] * nsteps
+        out["traffic_per_update"] = {"bytes": per_step * steps_per_update, "algorithmic_bytes": ub,
+                                     "ratio": per_step * steps_per_update / ub}
+    out["hbm_algorithmic"] = {"bytes_per_update": ub, "achieved_GBps": res["rate"] * ub / 1e9,
+                              "frac": res["rate"] * ub / PEAK_HBM}
+    ops = measured(FP64_OPS_FILE.format(tag), "fp64_flops_per_update_step")
+    out["executed"] = None if ops is None else {
         "flops_per_launch": ops * usteps / launches, "achieved": ops * usteps / sec / 1e12,
         "frac": ops * usteps / sec / PEAK_FP64}
-    main, other = (hbm, alu) if f_hbm >= f_alu else (alu, hbm)
-    main = dict(main)
-    main.update({"kernel": "k_jacobi_step<8>", "avg_launch_us": 1e3 * ms / launches, "launches": launches,
-                 "concurrent_launches": 2, "other_bound": other})
-    return main
+    return out
+
+
+def golden_error(B, W, prec: int) -> dict:
+    """Untimed accuracy check in the same process: the chi = 256 update of the stored
+    256-bit oracle result (tests/golden/update_chi256.json: a 20-qubit random state,
+    one Haar U(4) on sites 9, 10, theta 512 x 512, chi_max binding) run through the
+    library at this precision; worst absolute error of its 24 amplitudes and of the
+    256 Schmidt values of the updated bond against the oracle's."""
+    import numpy as np
+    g = json.load(open(GOLDEN))
+    inp = W.update_chi256_inputs()
+    d = B.MPS(inp["n"], inp["chi"], inp["eps"], prec)
+    d.load(inp["B"], inp["lam"])
+    rc = d.apply_gates([W.Gate(inp["first"], 2, inp["U"])], allow_noconv=True)
+    oh, ol = np.array(g["schmidt_hi"]), np.array(g["schmidt_lo"])
+    ah = np.array(g["amp_re_hi"]) + 1j * np.array(g["amp_im_hi"])
+    al = np.array(g["amp_re_lo"]) + 1j * np.array(g["amp_im_lo"])
+    dims_ok = d.bond_dims() == g["dims_after"]
+    if prec:
+        lh, ll = d.schmidt_dd(inp["first"])
+        lam_err = float(np.max(np.abs((lh - oh) + (ll - ol)))) if dims_ok else float("inf")
+        gh, gl = d.amplitudes(inp["bits"], dd=True)
+        amp_err = float(np.max(np.abs((gh - ah) + (gl - al))))
+    else:
+        lam_err = float(np.max(np.abs(d.schmidt(inp["first"]) - (oh + ol)))) if dims_ok else float("inf")
+        amp_err = float(np.max(np.abs(d.amplitudes(inp["bits"]) - (ah + al))))
+    d.close()
+    bound = 1e-26 if prec else 1e-12
+    return {"max_abs_amplitude_error": amp_err, "max_abs_schmidt_error": lam_err, "bound": bound,
+            "within_bound": bool(dims_ok and rc == 0 and amp_err <= bound and lam_err <= bound),
+            "reference": "256-bit oracle, one chi=256 update (theta 512x512), 24 amplitudes"}
 
 
 def work_at_s_ref(rate: float) -> dict:
@@ -192,27 +241,51 @@ def calibrate_copy(mib: int = 256, reps: int = 10):
 
 
 def cpu_baseline():
-    """The 256-bit oracle on the host cores: one two-site update at a = b = c = 128
-    (theta 256 x 256) of a seeded 40-qubit state, scaled to a = b = c = 256 by the
-    paper's O(m^3) cost of one U(4) update (x 8)."""
+    """The 256-bit oracle as it stands, on all host threads (OpenMP), on a bounded
+    sample of the workload:
+      * the chi = 256 update of tests/golden/update_chi256.json (a = b = c = 256,
+        theta 512 x 512, the bench's shape), run twice with the oracle's sweep limit
+        at 1 and at 2: t1 = theta + one Jacobi sweep + truncation and split, t2 - t1 =
+        one sweep.  The update's time is t1 + (S - 1)(t2 - t1) with S the oracle's own
+        sweep count for that update (stored with the golden values);
+      * configuration 1 in full (10 qubits, brickwork depth 10, chi_max = 32), timed
+        end to end."""
     import oracle
     from paper_1111_3124_amd import workloads as W
-    n, chi = N_QUBITS, 128
-    dims = [min(chi, 2 ** (b + 1), 2 ** (n - 1 - b)) for b in range(n - 1)]
-    rng = W.rng_for(1000)
-    Bt, lam = W.random_mps_B(dims, rng, spread=2.0)
-    om = oracle.OracleMPS(n, chi, EPS)
-    om.load(Bt, lam)
-    U = W.haar_unitary(4, rng)
+    g = json.load(open(GOLDEN))
+    S = int(g["split"]["sweeps"])
+    inp = W.update_chi256_inputs()
+    t = []
+    try:
+        for limit in (1, 2):
+            om = oracle.OracleMPS(inp["n"], inp["chi"], inp["eps"])
+            om.load(inp["B"], inp["lam"])
+            oracle.set_max_sweeps(limit)
+            t0 = time.perf_counter()
+            try:
+                om.apply(inp["first"], 2, inp["U"])
+            except RuntimeError:  # stopped at the sweep limit, as intended
+                pass
+            t.append(time.perf_counter() - t0)
+            om.close()
+    finally:
+        oracle.set_max_sweeps(80)
+    sweep = t[1] - t[0]
+    est = t[0] + (S - 1) * sweep
+    gates = [gg for layer in W.brickwork(10, 10, 1) for gg in layer]
+    om = oracle.OracleMPS(10, 32, 0.0)
     t0 = time.perf_counter()
-    om.apply(19, 2, U)
-    dt = time.perf_counter() - t0
-    scale = (CHI / chi) ** 3
-    return {"value": 1.0 / (dt * scale), "unit": "gate updates/s", "cores": oracle.oracle_threads(),
-            "kind": "oracle",
-            "sample": f"1 two-site update at a=b=c={chi} (theta {2*chi}x{2*chi}), 256-bit MPFR, "
-                      f"{dt:.1f} s measured; scaled x{scale:.0f} to a=b=c={CHI} by the O(m^3) per-gate cost",
-            "measured_s": dt}
+    for gg in gates:
+        om.apply_gate(gg)
+    t_c1 = time.perf_counter() - t0
+    om.close()
+    return {"value": 1.0 / est, "unit": "gate updates/s", "cores": oracle.oracle_threads(), "kind": "oracle",
+            "sample": f"one chi=256 update (a=b=c=256, theta 512x512) at 256 bits: theta+1 sweep+split "
+                      f"{t[0]:.1f} s, one more sweep {sweep:.1f} s measured; x{S} sweeps (the oracle's own "
+                      f"count for this update) = {est:.0f} s per update",
+            "measured_s": t[0] + t[1],
+            "config1": {"updates": len(gates), "seconds": t_c1, "updates_per_s": len(gates) / t_c1,
+                        "workload": "10 qubits, brickwork depth 10, chi_max=32, eps=0, all 45 gates"}}
 
 
 def main():
@@ -245,10 +318,12 @@ def main():
     results = {}
     if want in ("fp64", "both"):
         results["fp64"] = run_variant(B, W, B.MPS_PREC_FP64, args.steps, args.warmup)
+        results["fp64"]["error"] = golden_error(B, W, B.MPS_PREC_FP64)
         print(f"# fp64: {results['fp64']['rate']:.1f} updates/s, mean sweeps {results['fp64']['mean_sweeps']:.1f}",
               file=sys.stderr, flush=True)
     if want in ("dd", "both"):
         results["dd"] = run_variant(B, W, B.MPS_PREC_DD, args.steps, args.warmup)
+        results["dd"]["error"] = golden_error(B, W, B.MPS_PREC_DD)
         print(f"# dd: {results['dd']['rate']:.1f} updates/s, mean sweeps {results['dd']['mean_sweeps']:.1f} "
               f"+ dd {results['dd']['mean_dd_sweeps']:.1f}",
               file=sys.stderr, flush=True)
@@ -272,13 +347,25 @@ def main():
                    "updates_per_step": r["gates"] / args.steps, "variant": head,
                    "schedule": "all timed layers submitted in one call; updates overlap across layers"},
         "variants": {k: {"value": v["rate"], "ms_per_step": v["ms_per_step"],
+                         "error_vs_oracle": v["error"], "noconv_updates": v["noconv"],
                          "mean_sweeps": v["mean_sweeps"], "mean_dd_sweeps": v["mean_dd_sweeps"],
                          "kernel_ms": {n: t[0] for n, t in v["ktimes"].items()},
                          "schmidt_normalised": v["lam_ok"],
-                         "roofline": roofline(v, 1 if k == "dd" else 0),
+                         "roofline": roofline(v, 1 if k == "dd" else 0, k == "dd"),
                          "work_at_s_ref": work_at_s_ref(v["rate"])} for k, v in results.items()},
-        "roofline": roofline(r, 1 if head == "dd" else 0),
+        "error_vs_oracle": r["error"],
+        "noconv_updates": sum(v["noconv"] for v in results.values()),
+        "roofline": roofline(r, 1 if head == "dd" else 0, head == "dd"),
     }
+    bad = [k for k, v in results.items() if v["noconv"] or v["noconv_rc"] or not v["error"]["within_bound"]
+           or not v["lam_ok"]]
+    if bad:
+        # an update that stopped at its sweep limit, or a result outside its error
+        # bound, makes the measurement invalid: no line is reported
+        print("bench.py: invalid run (" + ", ".join(
+            f"{k}: noconv {results[k]['noconv']}, error {results[k]['error']}" for k in bad) + ")",
+            file=sys.stderr, flush=True)
+        sys.exit(3)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

@@ -271,7 +271,8 @@ int mps_sync(mps_handle h);
  * counters after reading.
  * cls 8 / 9 are counters (always on): *launches receives the number of
  * update-sweeps executed by the FP64 Jacobi / the dd polish (one update taking
- * one sweep counts 1), *ms receives 0. */
+ * one sweep counts 1), *ms receives 0.  cls 10 counts the SVD splits finalised
+ * at a sweep limit (each one also made its call return MPS_ENOCONV). */
 int mps_kernel_time(mps_handle h, int cls, double* ms, long* launches, int reset);
 
 /* Message for the last error on h (h may be NULL: the last error of mps_create*). */

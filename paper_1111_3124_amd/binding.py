@@ -28,7 +28,7 @@ MPS_OPT_BLOCK_WIDTH, MPS_OPT_MAX_INNER, MPS_OPT_MAX_SLOTS, MPS_OPT_WORKSPACE_MB 
 MPS_OPT_DD_REFINE, MPS_OPT_JACOBI_STREAMS, MPS_OPT_FUSE, MPS_OPT_QR, MPS_OPT_STEP_SPLIT = 9, 10, 11, 12, 13
 MPS_OPT_DD_STREAM, MPS_OPT_MAX_INNER_FEW = 14, 15
 KERNEL_CLASSES = ["theta", "jacobi", "truncate", "split", "gate1", "amplitude", "dd_refine", "rdo"]
-COUNTER_SWEEPS, COUNTER_SWEEPS_DD = 8, 9
+COUNTER_SWEEPS, COUNTER_SWEEPS_DD, COUNTER_NOCONV = 8, 9, 10
 
 _STATUS = {0: "MPS_OK", -1: "MPS_EINVAL", -2: "MPS_ERANGE", -3: "MPS_ENOMEM", -4: "MPS_EDEVICE",
            -5: "MPS_ENOCONV", -6: "MPS_ENONFINITE", -7: "MPS_ESTATE"}

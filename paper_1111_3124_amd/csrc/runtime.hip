@@ -139,6 +139,7 @@ struct Engine {
   double tms[8] = {0};
   long tcount[8] = {0};
   long slot_sweeps = 0, slot_sweeps_dd = 0;  // update-sweeps executed (FP64, dd polish)
+  long noconv_updates = 0;                    // splits finalised at a sweep limit
   long long* d_phase = nullptr;               // MPS_DEBUG_PHASES=1: step phase stamps
 };
 
@@ -1286,7 +1287,10 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
         sbl.JM = tb.JM;
         gsweeps[sa.gate] = sa.fp64_sweeps;
         gdd[sa.gate] = sa.dd_sweeps;
-        if (!sa.conv) status = MPS_ENOCONV;
+        if (!sa.conv) {
+          status = MPS_ENOCONV;
+          ++E->noconv_updates;
+        }
         mids.push_back(mpsk::Ent{si, sb});
         newB.push_back(sb);
         mN1 = std::max(mN1, sa.Nt);
@@ -1315,7 +1319,10 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
         std::memcpy(&gstats[8 * sl.gate], hstats + 8 * si, sizeof(double) * 8);
         gsweeps[sl.gate] = std::max(gsweeps[sl.gate], sl.fp64_sweeps);
         gdd[sl.gate] = std::max(gdd[sl.gate], sl.dd_sweeps);
-        if (!sl.conv) status = MPS_ENOCONV;
+        if (!sl.conv) {
+          status = MPS_ENOCONV;
+          ++E->noconv_updates;
+        }
         if (E->debug_sweeps)
           std::fprintf(stderr, "[mps] update at state %d site %d (M %d, N %d, kind %d): %d FP64 sweeps, %d dd sweeps\n",
                        g.unit, g.first, sl.M, sl.N, sl.kind, sl.fp64_sweeps, sl.dd_sweeps);
@@ -2210,12 +2217,13 @@ int mps_sync(mps_handle h) {
 }
 
 int mps_kernel_time(mps_handle h, int cls, double* ms, long* launches, int reset) {
-  if (!h || cls < 0 || cls >= 10) return MPS_EINVAL;
+  if (!h || cls < 0 || cls >= 11) return MPS_EINVAL;
   Engine* E = h->E;
   HIPCHK(h, hipStreamSynchronize(E->stream));
   harvest_timing(E);
-  if (cls >= 8) {  // counters: update-sweeps of the FP64 Jacobi (8) and of the dd polish (9)
-    long& c = cls == 8 ? E->slot_sweeps : E->slot_sweeps_dd;
+  if (cls >= 8) {  // counters: update-sweeps of the FP64 Jacobi (8) and of the dd polish (9),
+                   // splits finalised at a sweep limit (10)
+    long& c = cls == 8 ? E->slot_sweeps : cls == 9 ? E->slot_sweeps_dd : E->noconv_updates;
     if (ms) *ms = 0.0;
     if (launches) *launches = c;
     if (reset) c = 0;

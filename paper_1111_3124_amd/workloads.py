@@ -309,3 +309,34 @@ def batch_gates(specs: list[CircuitSpec]) -> tuple[list[int], list[Gate]]:
                 circ += [i] * len(ls[t])
                 gates += ls[t]
     return circ, gates
+
+
+def _saturated_dims(n: int, chi: int) -> list[int]:
+    return [min(chi, 2 ** (b + 1), 2 ** (n - 1 - b)) for b in range(n - 1)]
+
+
+def update_chi256_inputs() -> dict:
+    """One two-site update at a = b = c = 256: a 20-qubit random (B, V) state whose
+    bonds 7..11 hold 256 values, a Haar U(4) on sites 9, 10 (theta 512 x 512),
+    chi_max = 256 (binding), eps = 1e-12, 24 random bitstrings (seed 256)."""
+    n, chi, eps, seed = 20, 256, 1e-12, 256
+    dims = _saturated_dims(n, chi)
+    rng = rng_for(seed)
+    Bt, lam = random_mps_B(dims, rng, spread=4.0)
+    U = haar_unitary(4, rng)
+    bits = bitstrings(n, 24, seed + 1)
+    return dict(n=n, chi=chi, eps=eps, seed=seed, dims=dims, B=Bt, lam=lam, U=U, first=9, bits=bits)
+
+
+def update3_chi512_inputs() -> dict:
+    """One three-site update at a = b = c = d = 512: a 22-qubit random (B, V) state
+    whose bonds 8..12 hold 512 values, a Haar U(8) on sites 9, 10, 11 (first split
+    theta 1024 x 2048, second 1024 x 1024), chi_max = 512 (binding), eps = 1e-14, 24
+    random bitstrings (seed 512)."""
+    n, chi, eps, seed = 22, 512, 1e-14, 512
+    dims = _saturated_dims(n, chi)
+    rng = rng_for(seed)
+    Bt, lam = random_mps_B(dims, rng, spread=4.0)
+    U = haar_unitary(8, rng)
+    bits = bitstrings(n, 24, seed + 1)
+    return dict(n=n, chi=chi, eps=eps, seed=seed, dims=dims, B=Bt, lam=lam, U=U, first=9, bits=bits)

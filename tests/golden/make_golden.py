@@ -10,6 +10,20 @@ chi_max = 256 (bonds 7..11 hold 256), one Haar U(4) on sites 9, 10 (theta 512 x 
 truncation by chi_max binding), eps = 1e-12.  Stores the new bond dims, the 256
 Schmidt values of bond 9 and 24 amplitudes as double-double pairs, plus the
 oracle's diagnostics of the split (gap at the cut, discarded weight).
+
+update3_chi512: a 22-qubit random (B, V) state with bond dims at capacity for
+chi_max = 512 (bonds 8..12 hold 512), one Haar U(8) on sites 9, 10, 11: the first
+split is theta 1024 x 2048 (rows (alpha, i), columns (j, k, delta)), truncated to
+512 by chi_max, the second 1024 x 1024, truncated to 512; eps = 1e-14.  Stores the
+new bond dims, the Schmidt values of bonds 9 and 10, 24 amplitudes and both splits'
+diagnostics.  Several hours of 256-bit arithmetic on 8 cores.
+
+qft60_eps: configuration 5 with its own truncation: 60 qubits, the random product
+state of seed 5 (dd preparation gates), then the nearest-neighbour QFT network (60
+Hadamards, 1770 SWAP-phase U(4) gates, dd), chi_max = 1024, eps = 1e-24, applied
+gate by gate.  Stores the final bond dims, the 64 sampled amplitudes (bitstrings of
+numpy seed 55) and, over all splits, the smallest relative gap at a cut and the
+smallest relative distance of an eps decision from its boundary.
 """
 import json
 import os
@@ -25,14 +39,7 @@ from paper_1111_3124_amd import workloads as W  # noqa: E402
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def update_chi256_inputs():
-    n, chi, eps, seed = 20, 256, 1e-12, 256
-    dims = [min(chi, 2 ** (b + 1), 2 ** (n - 1 - b)) for b in range(n - 1)]
-    rng = W.rng_for(seed)
-    Bt, lam = W.random_mps_B(dims, rng, spread=4.0)
-    U = W.haar_unitary(4, rng)
-    bits = W.bitstrings(n, 24, seed + 1)
-    return dict(n=n, chi=chi, eps=eps, seed=seed, dims=dims, B=Bt, lam=lam, U=U, first=9, bits=bits)
+update_chi256_inputs = W.update_chi256_inputs
 
 
 def make_update_chi256():
@@ -59,6 +66,69 @@ def make_update_chi256():
     print("wrote update_chi256.json", out["split"], f"{out['oracle_seconds']:.0f} s")
 
 
+update3_chi512_inputs = W.update3_chi512_inputs
+
+
+def make_update3_chi512():
+    inp = update3_chi512_inputs()
+    t0 = time.time()
+    om = oracle.OracleMPS(inp["n"], inp["chi"], inp["eps"])
+    om.load(inp["B"], inp["lam"])
+    om.apply(inp["first"], 3, inp["U"])
+    stats = om.last_stats()
+    out = dict(
+        recipe="tests/golden/make_golden.py update3_chi512 (oracle at 256 bits)",
+        n=inp["n"], chi=inp["chi"], eps=inp["eps"], seed=inp["seed"], first=inp["first"],
+        dims_after=om.bond_dims(),
+        splits=[dict(gap=st["gap"], w=st["w"], k=st["k"], rank=st["rank"], sweeps=st["sweeps"])
+                for st in stats],
+    )
+    for j, bond in enumerate((inp["first"], inp["first"] + 1)):
+        sh, sl = om.schmidt(bond)
+        out[f"schmidt{j}_hi"], out[f"schmidt{j}_lo"] = sh.tolist(), sl.tolist()
+    ah, al = om.amplitudes(inp["bits"])
+    out.update(amp_re_hi=ah.real.tolist(), amp_re_lo=al.real.tolist(),
+               amp_im_hi=ah.imag.tolist(), amp_im_lo=al.imag.tolist(),
+               oracle_seconds=time.time() - t0, oracle_threads=oracle.oracle_threads())
+    with open(os.path.join(HERE, "update3_chi512.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print("wrote update3_chi512.json", out["splits"], f"{out['oracle_seconds']:.0f} s")
+
+
+def qft60_inputs():
+    import numpy as np
+    n, chi, eps, seed = 60, 1024, 1e-24, 5
+    circ = W.product_state_prep(n, seed) + W.qft_lnn_circuit(n)
+    bits = np.random.default_rng(55).integers(0, 2, (64, n)).astype(np.uint8)
+    return dict(n=n, chi=chi, eps=eps, seed=seed, circ=circ, bits=bits)
+
+
+def make_qft60_eps():
+    inp = qft60_inputs()
+    t0 = time.time()
+    om = oracle.OracleMPS(inp["n"], inp["chi"], inp["eps"])
+    min_gap, min_epsdist, w_sum = float("inf"), float("inf"), 0.0
+    for g in inp["circ"]:
+        om.apply_gate(g)
+        for st in om.last_stats():
+            min_gap = min(min_gap, st["gap"])
+            min_epsdist = min(min_epsdist, st["epsdist"])
+            w_sum += st["w"]
+    ah, al = om.amplitudes(inp["bits"])
+    out = dict(
+        recipe="tests/golden/make_golden.py qft60_eps (oracle at 256 bits)",
+        n=inp["n"], chi=inp["chi"], eps=inp["eps"], seed=inp["seed"], gates=len(inp["circ"]),
+        dims_after=om.bond_dims(), min_gap=min_gap, min_epsdist=min_epsdist, discarded_weight_sum=w_sum,
+        amp_re_hi=ah.real.tolist(), amp_re_lo=al.real.tolist(),
+        amp_im_hi=ah.imag.tolist(), amp_im_lo=al.imag.tolist(),
+        oracle_seconds=time.time() - t0, oracle_threads=oracle.oracle_threads(),
+    )
+    with open(os.path.join(HERE, "qft60_eps.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print("wrote qft60_eps.json", max(out["dims_after"]), min_gap, min_epsdist, f"{out['oracle_seconds']:.0f} s")
+
+
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "update_chi256"
-    {"update_chi256": make_update_chi256}[what]()
+    {"update_chi256": make_update_chi256, "update3_chi512": make_update3_chi512,
+     "qft60_eps": make_qft60_eps}[what]()

@@ -46,19 +46,37 @@ def test_counter_summary_hash_rule(tmp_path, monkeypatch):
 
 
 def test_committed_summaries_name_their_figures():
-    for name, key in (("jacobi_step_chi256_traffic.md", "bytes_per_update_step"),
-                      ("jacobi_step_chi256_fp64_ops.md", "fp64_flops_per_update_step")):
+    for name, key in (("jacobi_step_chi256_dd_traffic.md", "bytes_per_update_step"),
+                      ("jacobi_step_chi256_dd_fp64_ops.md", "fp64_flops_per_update_step")):
         text = open(os.path.join(bench.ROOT, "profiles", name)).read()
         assert f"{key}:" in text and "kernels_hip_sha256:" in text and "rocprofv3 --pmc" in text
 
 
-def test_roofline_totals():
-    # 46 updates x 11 sweeps of 63 steps in 145 ms over 3276 step launches
-    res = {"ktimes": {"jacobi": (145.0, 3276)}, "slot_sweeps": 46 * 11}
-    r = bench.roofline(res, 1)
+def test_update_bytes():
+    # 16 (2ab + 2bc + 2ak + 2kc) + 8a + 256 at a = b = c = k = 256: about 8.4 MB, x2 dd
+    a = 256
+    assert bench.update_bytes(a, False) == 16 * 8 * a * a + 8 * a + 256
+    assert bench.update_bytes(a, True) == 2 * bench.update_bytes(a, False)
+    assert 8.3e6 < bench.update_bytes(a, False) < 8.5e6
+
+
+def test_roofline_totals(monkeypatch):
+    # 46 updates x 11 sweeps of 63 steps in 145 ms over 3276 step launches, 20 updates/s
+    monkeypatch.setattr(bench, "measured", lambda path, key: None)
+    res = {"ktimes": {"jacobi": (145.0, 3276)}, "slot_sweeps": 46 * 11, "mean_sweeps": 11.0, "rate": 20.0}
+    r = bench.roofline(res, 1, True)
     usteps = 46 * 11 * 63
-    assert r["bytes_per_launch"] == pytest.approx(usteps * bench.step_bytes(512, 512) / 3276, rel=1e-15)
-    assert r["achieved"] == pytest.approx(usteps * bench.step_bytes(512, 512) / 0.145 / 1e9, rel=1e-12)
-    assert r["frac"] == pytest.approx(r["achieved"] * 1e9 / bench.PEAK_HBM, rel=1e-12)
+    assert r["bound"] == "mfma" and r["unit"] == "TFLOP/s" and r["peak"] == 78.6
+    assert r["flops_per_launch"] == pytest.approx(usteps * bench.step_flops(512, 512) / 3276, rel=1e-15)
+    assert r["achieved"] == pytest.approx(usteps * bench.step_flops(512, 512) / 0.145 / 1e12, rel=1e-12)
+    assert r["frac"] == pytest.approx(r["achieved"] * 1e12 / bench.PEAK_FP64, rel=1e-12)
     assert r["avg_launch_us"] == pytest.approx(145e3 / 3276, rel=1e-12)
-    assert bench.roofline({"ktimes": {"jacobi": (0.0, 0)}, "slot_sweeps": 0}, 1) is None
+    assert r["traffic"] is None and r["executed"] is None
+    assert r["hbm_algorithmic"]["achieved_GBps"] == pytest.approx(20.0 * bench.update_bytes(256, True) / 1e9)
+    # counter figures per update-step scale to launches and to whole updates
+    monkeypatch.setattr(bench, "measured", lambda path, key: 1e6 if "traffic" in path else 7e7)
+    r = bench.roofline(res, 1, True)
+    assert r["traffic"] == pytest.approx(1e6 * usteps / 3276, rel=1e-12)
+    assert r["traffic_per_update"]["bytes"] == pytest.approx(1e6 * 11 * 63, rel=1e-12)
+    assert r["executed"]["achieved"] == pytest.approx(7e7 * usteps / 0.145 / 1e12, rel=1e-12)
+    assert bench.roofline({"ktimes": {"jacobi": (0.0, 0)}, "slot_sweeps": 0}, 1, True) is None

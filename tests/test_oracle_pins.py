@@ -238,6 +238,43 @@ def test_truncation_eckart_young(oracle_mod):
     assert abs(1 - sum(x ** 2 for x in full[:3]) - w) < 1e-29
 
 
+def test_truncation_eckart_young_three_site(oracle_mod):
+    """A U(8) update truncated in both of its splits, from a canonical state.  Split 1
+    keeps the k1 largest Schmidt components of the exact state psi across cut s
+    (discarded weight w1); split 2 then keeps the k2 largest of that state across cut
+    s+1 (w2), leaving the left Schmidt vectors of split 1 untouched, so the final
+    state psi_k lies in the range of the first projector.  Hence
+    <psi|psi_k> = sqrt((1 - w1)(1 - w2)) and ||psi - <psi|psi_k> psi_k||^2 =
+    1 - (1 - w1)(1 - w2) (the Eckart-Young identity applied at each cut in turn)."""
+    n = 8
+    rng = W.rng_for(33)
+    pre = [g for layer in W.brickwork_dd(n, 6, 32) for g in layer]
+    hi, lo = W.haar_unitary_dd(8, rng)
+    last = W.Gate(2, 3, hi, lo)
+    m = oracle_mod.OracleMPS(n, 256, 0.0)
+    sv = oracle_mod.OracleSV(n)
+    for g in pre:
+        m.apply_gate(g)
+        sv.apply_gate(g)
+    assert m.bond_dims()[1] == 4 and m.bond_dims()[4] == 8
+    m.set_trunc(5, 0.0)
+    m.apply_gate(last)
+    sv.apply_gate(last)
+    st = m.last_stats()
+    assert len(st) == 2 and st[0]["k"] == 5 and st[1]["k"] == 5
+    w1, w2 = mpr(st[0]["w"], st[0]["w_lo"]), mpr(st[1]["w"], st[1]["w_lo"])
+    assert w1 > 1e-6 and w2 > 1e-6
+    ex_hi, ex_lo = sv.amplitudes()
+    exact = [mpc(h, l) for h, l in zip(ex_hi, ex_lo)]
+    kept = all_amps(m, n)
+    assert abs(sum(abs(x) ** 2 for x in kept) - 1) < 1e-28
+    ov = sum(mpmath.conj(e) * x for e, x in zip(exact, kept))
+    c = mpmath.sqrt((1 - w1) * (1 - w2))
+    assert abs(ov - c) < 1e-28
+    resid = sum(abs(e - c * x) ** 2 for e, x in zip(exact, kept))
+    assert abs(resid - (1 - c ** 2)) < 1e-28
+
+
 def test_eps_rule(oracle_mod):
     """Truncation by discarded weight: k is the smallest count whose dropped weight
     is <= eps * W (Section 3.1: small coefficients are cut; the threshold is the
