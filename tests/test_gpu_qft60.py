@@ -12,8 +12,16 @@ evaluated here at 256 bits for 64 sampled bitstrings:
 * eps = 1e-24, the configuration's own truncation, gates applied one at a time: a
   renormalised truncation moves the state by at most sqrt(2 w) in norm (w its relative
   discarded weight, reported per split), the gates preserve distances, so every
-  amplitude lies within the sum of sqrt(2 w_i) of the closed form."""
+  amplitude lies within the sum of sqrt(2 w_i) of the closed form; and, against the
+  256-bit oracle run of the same gates with the same truncation rule
+  (tests/golden/qft60_eps.json, written by tests/golden/make_golden.py qft60_eps), the
+  same bond dims everywhere and the 64 amplitudes within 1e-26.  The oracle run's
+  smallest relative gap at a cut (2.4e-13) and smallest relative distance of an eps
+  decision from its boundary (0.23) keep every cut far from the ambiguous cases, so
+  both sides keep the same subspaces."""
+import json
 import math
+import os
 
 import mpmath
 import numpy as np
@@ -25,6 +33,7 @@ pytestmark = pytest.mark.gpu
 
 N, CHI, SEED = 60, 1024, 5
 TOL = 1e-26
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "qft60_eps.json")
 
 
 @pytest.fixture(scope="module")
@@ -77,7 +86,7 @@ def test_qft60_exact(B, case):
     d.close()
 
 
-def test_qft60_truncated_within_discarded_weight(B, case):
+def test_qft60_truncated_vs_oracle_and_bound(B, case):
     circ, bits, want = case
     print(f"config 5: n={N} chi={CHI} eps=1e-24 seed={SEED}, gate by gate", flush=True)
     d = B.MPS(N, CHI, 1e-24, B.MPS_PREC_DD)
@@ -91,4 +100,14 @@ def test_qft60_truncated_within_discarded_weight(B, case):
     worst = worst_error(d, bits, want)
     print(f"  max bond dim {max(d.bond_dims())}, worst {worst:.3e}, bound {bound:.3e}", flush=True)
     assert worst <= bound + TOL
+    # the oracle's run of the same gates with the same truncation
+    g = json.load(open(GOLDEN))
+    assert g["n"] == N and g["chi"] == CHI and g["eps"] == 1e-24 and g["gates"] == len(circ)
+    assert d.bond_dims() == g["dims_after"]
+    gh, gl = d.amplitudes(bits, dd=True)
+    oh = np.array(g["amp_re_hi"]) + 1j * np.array(g["amp_im_hi"])
+    ol = np.array(g["amp_re_lo"]) + 1j * np.array(g["amp_im_lo"])
+    err = float(np.max(np.abs((gh - oh) + (gl - ol))))
+    print(f"  vs the 256-bit oracle (same truncation): worst |amplitude error| {err:.3e}", flush=True)
+    assert err <= TOL
     d.close()
