@@ -204,6 +204,23 @@ int mps_amplitude_dd(mps_handle h, const unsigned char* bits, double out[4]);
  * 2 doubles per amplitude (FP64 handle) or 4 (dd handle: re_hi, re_lo, im_hi, im_lo). */
 int mps_amplitudes(mps_handle h, int count, const unsigned char* bits, double* out);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): mps_amplitudes with the same arguments,
+ * layout and results, bit for bit, but no device, pinned or host allocation.  Its
+ * scratch (bitstrings, the site-pointer and row-length tables, the results) is a
+ * fixed 4 MiB device array held by each GPU the library runs on until the process
+ * ends; the bitstrings are copied straight from `bits` and the results straight
+ * into `out` (pageable copies on the handle's stream, which is synchronised before
+ * return).  Limit: align256(count * n) + align256(16 n) + align256(4 n) +
+ * align256(count * 16) (x2 for the results of a dd handle) <= 4 MiB, else
+ * MPS_ERANGE; e.g. n = 60 allows count <= 55000 on an FP64 handle.  Nothing in the
+ * scratch needs to start at zero (every result is written); the array keeps the
+ * last call's contents.  Calls that overlap on one GPU (handles on different
+ * streams, or different threads) share the array and race: serialise them.
+ * Errors as mps_amplitudes, plus MPS_EDEVICE if the array's address cannot be
+ * looked up. */
+int mps_amplitudes_noalloc(mps_handle h, int count, const unsigned char* bits, double* out);
+
 /* Reduced density operator (paper, Section 3.2: RDO(list)) of `count` distinct
  * qubits q[0..count-1], 1 <= count <= 7: rho = Tr over every other qubit of
  * |Psi><Psi|, contracted exactly from the site tensors (no canonical form assumed;

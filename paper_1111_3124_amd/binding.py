@@ -67,6 +67,7 @@ _lib.mps_schmidt_dd.argtypes = [_h, C.c_int, _dp, _dp, C.c_int, C.POINTER(C.c_in
 _lib.mps_amplitude.argtypes = [_h, C.POINTER(C.c_ubyte), _dp]
 _lib.mps_amplitude_dd.argtypes = [_h, C.POINTER(C.c_ubyte), _dp]
 _lib.mps_amplitudes.argtypes = [_h, C.c_int, C.POINTER(C.c_ubyte), _dp]
+_lib.mps_amplitudes_noalloc.argtypes = [_h, C.c_int, C.POINTER(C.c_ubyte), _dp]
 _lib.mps_stats.argtypes = [_h, C.POINTER(mps_update_stats)]
 _lib.mps_load.argtypes = [_h, C.POINTER(C.c_int), C.POINTER(_dp), C.POINTER(_dp), C.POINTER(_dp), C.POINTER(_dp)]
 _lib.mps_get_site.argtypes = [_h, C.c_int, _dp, _dp, C.c_long]
@@ -93,7 +94,7 @@ _lib.mps_batch_destroy.argtypes = [_b]
 
 EXPORTED = ["mps_create", "mps_create_ex", "mps_destroy", "mps_apply_gate", "mps_apply_gate_dd",
             "mps_apply_gates", "mps_apply_gate2", "mps_apply_gate2_dd", "mps_bond_dim", "mps_schmidt", "mps_schmidt_dd", "mps_amplitude",
-            "mps_amplitude_dd", "mps_amplitudes", "mps_stats", "mps_load", "mps_get_site",
+            "mps_amplitude_dd", "mps_amplitudes", "mps_amplitudes_noalloc", "mps_stats", "mps_load", "mps_get_site",
             "mps_export", "mps_import",
             "mps_set_option", "mps_sync", "mps_kernel_time", "mps_last_error", "mps_version",
             "mps_rdo", "mps_rdo_dd", "mps_rdo_block", "mps_batch_create", "mps_batch_run", "mps_batch_get", "mps_batch_set_option",
@@ -246,16 +247,22 @@ def mps_amplitude_dd(h, bits):
     return complex(out[0], out[2]), complex(out[1], out[3])
 
 
-def mps_amplitudes(h, bits_2d, dd: bool = False):
+def mps_amplitudes(h, bits_2d, dd: bool = False, noalloc: bool = False):
     a, p = _bits(bits_2d)
     count = a.shape[0]
     out = np.zeros(count * (4 if dd else 2))
-    _check(h, _lib.mps_amplitudes(h, count, p, _ptr(out)))
+    fn = _lib.mps_amplitudes_noalloc if noalloc else _lib.mps_amplitudes
+    _check(h, fn(h, count, p, _ptr(out)))
     if dd:
         o = out.reshape(count, 4)
         return o[:, 0] + 1j * o[:, 2], o[:, 1] + 1j * o[:, 3]
     o = out.reshape(count, 2)
     return o[:, 0] + 1j * o[:, 1]
+
+
+def mps_amplitudes_noalloc(h, bits_2d, dd: bool = False):
+    """mps_amplitudes through the entry point that allocates nothing."""
+    return mps_amplitudes(h, bits_2d, dd, noalloc=True)
 
 
 def mps_rdo(h, qubits):
@@ -459,8 +466,8 @@ class MPS:
     def amplitude(self, bits):
         return mps_amplitude(self.h, bits)
 
-    def amplitudes(self, bits_2d, dd=False):
-        return mps_amplitudes(self.h, bits_2d, dd)
+    def amplitudes(self, bits_2d, dd=False, noalloc=False):
+        return mps_amplitudes(self.h, bits_2d, dd, noalloc)
 
     def stats(self):
         return mps_stats(self.h)

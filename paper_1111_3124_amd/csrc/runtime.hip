@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -158,6 +159,9 @@ struct mps_state {
   double* d_lam_lo = nullptr;
   mps_update_stats last{};
   std::string err;
+  // room for any message this library writes, so that an error on a path that must
+  // not allocate (mps_amplitudes_noalloc) does not grow the string
+  mps_state() { err.reserve(256); }
 };
 
 struct mps_batch {
@@ -1620,6 +1624,79 @@ void outer_gate8(const double* u, int p0, int p1, double* out) {
 
 }  // namespace
 
+// ---------------------------------------------------------------- no-allocation amplitudes
+// The amplitude kernels' scratch (bitstrings, site-pointer and row-length tables,
+// results) in a fixed device array instead of the engine's staging areas, which
+// grow by hipMalloc / hipHostMalloc.  Each device holds its own copy at its own
+// address, looked up once per device with that device current.
+constexpr size_t kNoAllocScratch = size_t(4) << 20;
+constexpr int kNoAllocMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+// the address of `scratch` on device `dev` (looked up on first use); nullptr on error
+void* scratch_on(int dev, hipError_t* e) {
+  *e = hipSuccess;
+  if (dev < 0 || dev >= kNoAllocMaxDevices) {
+    *e = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = 0;
+    if ((*e = hipGetDevice(&cur)) != hipSuccess) return nullptr;
+    if (cur != dev && (*e = hipSetDevice(dev)) != hipSuccess) return nullptr;
+    void* p = nullptr;
+    *e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) {
+      const hipError_t r = hipSetDevice(cur);
+      if (*e == hipSuccess) *e = r;
+    }
+    if (*e != hipSuccess) return nullptr;
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+// scratch layout of one call: bits | site pointers (hi, then lo) | row lengths | results
+struct NoAllocLayout {
+  size_t ptr, ld, out, end;
+};
+NoAllocLayout noalloc_layout(long count, int n, bool dd) {
+  NoAllocLayout L;
+  L.ptr = align_up((size_t)count * n);
+  L.ld = L.ptr + align_up(sizeof(void*) * 2 * n);
+  L.out = L.ld + align_up(sizeof(int) * n);
+  L.end = L.out + align_up((size_t)count * sizeof(double2) * (dd ? 2 : 1));
+  return L;
+}
+
+// an error of the no-allocation path: the message is written into the handle's
+// reserved string (no temporary strings), cut to its capacity
+int fail_na(mps_state* h, int code, const char* what, const char* detail = nullptr) {
+  std::string& m = h->err;
+  m.clear();
+  const size_t cap = m.capacity();
+  m.append(what, std::min(std::strlen(what), cap));
+  if (detail && m.size() + 2 < cap) {
+    m.append(": ");
+    m.append(detail, std::min(std::strlen(detail), cap - m.size()));
+  }
+  return code;
+}
+
+#define NACHK(h, call)                                                                              \
+  do {                                                                                              \
+    hipError_t e_ = (call);                                                                         \
+    if (e_ != hipSuccess) return fail_na(h, MPS_EDEVICE, #call, hipGetErrorString(e_));             \
+  } while (0)
+
+}  // namespace
+
 extern "C" {
 
 const char* mps_version(void) { return "mps-mi355x 0.2 (gfx950)"; }
@@ -1977,6 +2054,46 @@ int mps_rdo_dd(mps_handle h, int count, const int* qubits, double* rho_hi, doubl
         rho_lo[2 * dst + 1] = dd ? rl[src].y : 0.0;
       }
     }
+  return MPS_OK;
+}
+
+int mps_amplitudes_noalloc(mps_handle h, int count, const unsigned char* bits, double* out) {
+  if (!h || count < 0 || (count > 0 && (!bits || !out))) return MPS_EINVAL;
+  if (count == 0) return MPS_OK;
+  for (long i = 0; i < (long)count * h->n; ++i)
+    if (bits[i] > 1) return fail_na(h, MPS_EINVAL, "bits must be 0 or 1");
+  for (int s = 0; s <= h->n; ++s)
+    if (h->dimx[s] > 1024) return fail_na(h, MPS_ERANGE, "amplitude kernel supports bond dims up to 1024");
+  Engine* E = h->E;
+  const bool dd = h->prec == MPS_PREC_DD;
+  const NoAllocLayout L = noalloc_layout(count, h->n, dd);
+  if (L.end > kNoAllocScratch)
+    return fail_na(h, MPS_ERANGE, "mps_amplitudes_noalloc: bits, tables and results exceed its 4 MiB scratch");
+  hipError_t e = hipSuccess;
+  char* base = (char*)scratch_on(E->device, &e);
+  if (!base) return fail_na(h, MPS_EDEVICE, "scratch lookup", hipGetErrorString(e));
+  // every table comes straight from the caller's or the handle's host memory (the
+  // handle's vectors exist already); nothing is staged in pinned memory
+  const size_t nb = (size_t)count * h->n;
+  NACHK(h, hipMemcpyAsync(base, bits, nb, hipMemcpyHostToDevice, E->stream));
+  NACHK(h, hipMemcpyAsync(base + L.ptr, h->B.data(), sizeof(void*) * h->n, hipMemcpyHostToDevice, E->stream));
+  if (dd)
+    NACHK(h, hipMemcpyAsync(base + L.ptr + sizeof(void*) * h->n, h->Blo.data(), sizeof(void*) * h->n,
+                            hipMemcpyHostToDevice, E->stream));
+  NACHK(h, hipMemcpyAsync(base + L.ld, h->capx.data() + 1, sizeof(int) * h->n, hipMemcpyHostToDevice, E->stream));
+  mpsk::AmpArgs a{};
+  a.B = (const double2* const*)(base + L.ptr);
+  a.ld = (const int*)(base + L.ld);
+  a.dimx = h->d_dimx;
+  a.n = h->n;
+  a.bits = (const unsigned char*)base;
+  a.out = (double2*)(base + L.out);
+  e = dd ? mpsk::launch_amplitude_dd(a, (const double2* const*)(base + L.ptr) + h->n, count, E->stream)
+         : mpsk::launch_amplitude(a, count, E->stream);
+  if (e != hipSuccess) return fail_na(h, MPS_EDEVICE, "amplitude", hipGetErrorString(e));
+  NACHK(h, hipMemcpyAsync(out, base + L.out, (size_t)count * sizeof(double2) * (dd ? 2 : 1), hipMemcpyDeviceToHost,
+                          E->stream));
+  NACHK(h, hipStreamSynchronize(E->stream));
   return MPS_OK;
 }
 
