@@ -65,9 +65,11 @@ def step_gates(W, rng, t):
     return [g for g in layer if 8 <= g.first <= 30]
 
 
-def run_variant(B, W, prec: int, steps: int, warmup: int):
+def run_variant(B, W, prec: int, steps: int, warmup: int, launch=None):
     rng = W.rng_for(SEED)
     m = B.MPS(N_QUBITS, CHI, EPS, prec)
+    for key, value in (launch or {}).items():
+        m.set_option(key, value)
     t = saturate(m, B, W, rng)
     dims = m.bond_dims()
     # the layers of the timed region (and the warmup) are drawn up front; each call
@@ -82,7 +84,8 @@ def run_variant(B, W, prec: int, steps: int, warmup: int):
     for g in timed:
         assert dims[g.first - 1] == dims[g.first] == dims[g.first + 1] == CHI
     m.set_option(B.MPS_OPT_KERNEL_TIMING, 1)
-    for c in list(range(len(B.KERNEL_CLASSES))) + [B.COUNTER_SWEEPS, B.COUNTER_SWEEPS_DD, B.COUNTER_NOCONV]:
+    for c in list(range(len(B.KERNEL_CLASSES))) + [B.COUNTER_SWEEPS, B.COUNTER_SWEEPS_DD, B.COUNTER_NOCONV,
+                                                   B.COUNTER_GRAPHS]:
         m.kernel_time(c, reset=True)
     m.sync()
     t0 = time.perf_counter()
@@ -93,6 +96,7 @@ def run_variant(B, W, prec: int, steps: int, warmup: int):
     slot_sweeps = m.kernel_time(B.COUNTER_SWEEPS)[1]
     slot_sweeps_dd = m.kernel_time(B.COUNTER_SWEEPS_DD)[1]
     noconv = m.kernel_time(B.COUNTER_NOCONV)[1]
+    graphs = m.kernel_time(B.COUNTER_GRAPHS)
     dims = m.bond_dims()
     assert all(dims[g.first] == CHI for g in timed)
     lam_ok = all(abs(float((m.schmidt(b) ** 2).sum()) - 1.0) < 1e-12 for b in range(N_QUBITS - 1))
@@ -100,7 +104,7 @@ def run_variant(B, W, prec: int, steps: int, warmup: int):
     return dict(rate=len(timed) / dt, ms_per_step=1e3 * dt / steps, gates=len(timed), seconds=dt,
                 mean_sweeps=slot_sweeps / len(timed), mean_dd_sweeps=slot_sweeps_dd / len(timed),
                 slot_sweeps=slot_sweeps, ktimes=ktimes, lam_ok=lam_ok, noconv=noconv, noconv_rc=rc != 0,
-                steps=steps)
+                steps=steps, graphs_built=int(graphs[0]), graph_replays=graphs[1])
 
 
 def step_bytes(M: int, N: int, jvec: int = 1) -> float:
@@ -288,13 +292,88 @@ def cpu_baseline():
                         "workload": "10 qubits, brickwork depth 10, chi_max=32, eps=0, all 45 gates"}}
 
 
+def batch_workload(B, W, prec: int, launch=None) -> dict:
+    """Configuration 4: 256 independent brickwork circuits of Haar U(4) gates (seed 4:
+    n ~ U{16..48}, chi_max ~ U{32, 64, 128, 256}, depth ~ U{8..24}, eps = 1e-12), all
+    gates handed to one batch in a single call (layer-interleaved across circuits).
+    Timed from the call to its return; states created and zeroed beforehand."""
+    specs = W.batch_spec(256, 4)
+    circ, gates = W.batch_gates(specs)
+    bt = B.Batch([s.n for s in specs], [s.chi_max for s in specs], [1e-12] * len(specs), prec)
+    for key, value in (launch or {}).items():
+        bt.set_option(key, value)
+    bt[0].set_option(B.MPS_OPT_KERNEL_TIMING, 1)
+    bt[0].sync()
+    t0 = time.perf_counter()
+    rc = bt.run(circ, gates, allow_noconv=True)
+    bt[0].sync()
+    dt = time.perf_counter() - t0
+    noconv = bt[0].kernel_time(B.COUNTER_NOCONV)[1]
+    sweeps = bt[0].kernel_time(B.COUNTER_SWEEPS)[1]
+    ktimes = {name: bt[0].kernel_time(c)[0] for c, name in enumerate(B.KERNEL_CLASSES)}
+    multi = sum(1 for g in gates if g.k > 1)
+    bt.close()
+    return {"updates": multi, "seconds": dt, "rate": multi / dt, "noconv": noconv, "noconv_rc": rc != 0,
+            "update_sweeps": sweeps, "kernel_ms": ktimes}
+
+
+def triples_workload(B, W, prec: int, launch=None) -> dict:
+    """Configuration 3: 30 qubits, 200 Haar U(8) gates on random contiguous triples
+    (seed 3), chi_max = 512, eps = 1e-14, from |0...0>, all gates in one call."""
+    gates = W.random_triples(30, 200, 3)
+    m = B.MPS(30, 512, 1e-14, prec)
+    for key, value in (launch or {}).items():
+        m.set_option(key, value)
+    m.set_option(B.MPS_OPT_KERNEL_TIMING, 1)
+    m.sync()
+    t0 = time.perf_counter()
+    rc = m.apply_gates(gates, allow_noconv=True)
+    m.sync()
+    dt = time.perf_counter() - t0
+    noconv = m.kernel_time(B.COUNTER_NOCONV)[1]
+    ktimes = {name: m.kernel_time(c)[0] for c, name in enumerate(B.KERNEL_CLASSES)}
+    dims = m.bond_dims()
+    lam_ok = all(abs(float((m.schmidt(b) ** 2).sum()) - 1.0) < 1e-12 for b in range(29))
+    m.close()
+    return {"gates": len(gates), "seconds": dt, "rate": len(gates) / dt, "noconv": noconv, "noconv_rc": rc != 0,
+            "max_bond_dim": max(dims), "saturated_bonds": sum(d == 512 for d in dims), "schmidt_normalised": lam_ok,
+            "kernel_ms": ktimes}
+
+
+def other_workload(B, W, name: str, want: str, launch) -> None:
+    """One JSON line for configuration 4 (batch256) or 3 (triples), FP64 and dd."""
+    fn, metric, unit = {
+        "batch256": (batch_workload, "batched MPS gate updates/s (256 independent circuits)", "gate updates/s"),
+        "triples": (triples_workload, "U(8) gate updates/s at chi_max=512", "U(8) gates/s")}[name]
+    res = {}
+    for k in (("fp64", "dd") if want in ("both", "auto") else (want,)):
+        res[k] = fn(B, W, B.MPS_PREC_DD if k == "dd" else B.MPS_PREC_FP64, launch)
+        print(f"# {name} {k}: {res[k]['rate']:.1f} {unit}", file=sys.stderr, flush=True)
+    head = "dd" if "dd" in res else "fp64"
+    line = {"metric": metric, "value": res[head]["rate"], "unit": unit, "n_gpus": 1, "higher_is_better": True,
+            "dtype": "dd" if head == "dd" else "f64", "data": "synthetic",
+            "config": {"workload": name}, "variants": res}
+    print(json.dumps(line), flush=True)
+    if any(v["noconv"] or v["noconv_rc"] for v in res.values()):
+        print(f"bench.py: {name}: unconverged updates", file=sys.stderr, flush=True)
+        sys.exit(3)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--variants", default="auto", help="fp64, dd, both or auto")
+    ap.add_argument("--workload", default="chi256", choices=["chi256", "batch256", "triples"],
+                    help="chi256: the headline line (chi = 256 updates); batch256: configuration 4 "
+                         "(256 independent circuits); triples: configuration 3 (U(8) gates, chi_max 512)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tick-sweeps", type=int, default=None,
+                    help="Jacobi sweeps per scheduler tick (1 or 2; default: the library's)")
+    ap.add_argument("--graph", type=int, default=None,
+                    help="1: replay the Jacobi sweeps from captured HIP graphs, 0: stream launches "
+                         "(default: the library's)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -308,6 +387,11 @@ def main():
     from paper_1111_3124_amd import workloads as W
 
     want = args.variants
+    launch = {}
+    if args.tick_sweeps is not None:
+        launch[B.MPS_OPT_TICK_SWEEPS] = args.tick_sweeps
+    if args.graph is not None:
+        launch[B.MPS_OPT_GRAPH] = args.graph
     dd_ok = True
     try:
         B.MPS(2, 2, 0.0, B.MPS_PREC_DD).close()
@@ -315,14 +399,17 @@ def main():
         dd_ok = False
     if want == "auto":
         want = "both" if dd_ok else "fp64"
+    if args.workload != "chi256":
+        other_workload(B, W, args.workload, want, launch)
+        return
     results = {}
     if want in ("fp64", "both"):
-        results["fp64"] = run_variant(B, W, B.MPS_PREC_FP64, args.steps, args.warmup)
+        results["fp64"] = run_variant(B, W, B.MPS_PREC_FP64, args.steps, args.warmup, launch)
         results["fp64"]["error"] = golden_error(B, W, B.MPS_PREC_FP64)
         print(f"# fp64: {results['fp64']['rate']:.1f} updates/s, mean sweeps {results['fp64']['mean_sweeps']:.1f}",
               file=sys.stderr, flush=True)
     if want in ("dd", "both"):
-        results["dd"] = run_variant(B, W, B.MPS_PREC_DD, args.steps, args.warmup)
+        results["dd"] = run_variant(B, W, B.MPS_PREC_DD, args.steps, args.warmup, launch)
         results["dd"]["error"] = golden_error(B, W, B.MPS_PREC_DD)
         print(f"# dd: {results['dd']['rate']:.1f} updates/s, mean sweeps {results['dd']['mean_sweeps']:.1f} "
               f"+ dd {results['dd']['mean_dd_sweeps']:.1f}",
@@ -349,6 +436,7 @@ def main():
         "variants": {k: {"value": v["rate"], "ms_per_step": v["ms_per_step"],
                          "error_vs_oracle": v["error"], "noconv_updates": v["noconv"],
                          "mean_sweeps": v["mean_sweeps"], "mean_dd_sweeps": v["mean_dd_sweeps"],
+                         "graphs": {"built": v["graphs_built"], "replays": v["graph_replays"]},
                          "kernel_ms": {n: t[0] for n, t in v["ktimes"].items()},
                          "schmidt_normalised": v["lam_ok"],
                          "roofline": roofline(v, 1 if k == "dd" else 0, k == "dd"),

@@ -102,7 +102,16 @@ enum mps_option {
   MPS_OPT_MAX_INNER_FEW = 15  /* inner sweeps per block pair for tasks with fewer than 16
                                  column blocks (default 1 FP64, 12 dd; up to that many
                                  sweeps over all the pair's column pairs, ending early
-                                 once one rotates nothing)                              */
+                                 once one rotates nothing)                              */,
+  MPS_OPT_TICK_SWEEPS = 16    /* FP64 Jacobi sweeps launched per scheduler tick, 1 or 2
+                                 (default 2).  Convergence is tested on the device: an
+                                 update whose last sweep rotated nothing skips every
+                                 later one, so results do not depend on this value; the
+                                 host reads the rotation flags once per tick           */,
+  MPS_OPT_GRAPH = 17          /* 1: each tick's Jacobi sweeps (order kernels, step
+                                 launches on both streams) are replayed from a HIP graph
+                                 captured once per launch shape and kept by the engine;
+                                 0 (default): launched one by one.  Same results      */
 };
 
 /* Diagnostics of the most recent split (the last one of a three-qubit gate). */
@@ -289,7 +298,9 @@ int mps_sync(mps_handle h);
  * cls 8 / 9 are counters (always on): *launches receives the number of
  * update-sweeps executed by the FP64 Jacobi / the dd polish (one update taking
  * one sweep counts 1), *ms receives 0.  cls 10 counts the SVD splits finalised
- * at a sweep limit (each one also made its call return MPS_ENOCONV). */
+ * at a sweep limit (each one also made its call return MPS_ENOCONV).  cls 11
+ * counts the graph replays of Jacobi sweeps (MPS_OPT_GRAPH), *ms receiving the
+ * number of graphs captured. */
 int mps_kernel_time(mps_handle h, int cls, double* ms, long* launches, int reset);
 
 /* Message for the last error on h (h may be NULL: the last error of mps_create*). */
@@ -297,6 +308,16 @@ const char* mps_last_error(mps_handle h);
 
 /* Library version string. */
 const char* mps_version(void);
+
+/* The key under which the tuning table (the per-size Jacobi step configurations
+ * chosen by the package's autotuner) is looked up for the current device: its
+ * architecture and the HIP runtime version, e.g. "gfx950 70226015"; "" if the
+ * device cannot be queried.  The table is read from $MPS_TUNING_FILE, else from
+ * tuning.txt beside the library; a handle created on a device with no matching
+ * section uses the defaults of MPS_OPT_BLOCK_WIDTH, MPS_OPT_MAX_INNER_FEW and
+ * MPS_OPT_QR, and setting any of those three options on a handle replaces the
+ * table's choices for it. */
+const char* mps_tuning_key(void);
 
 /* --- batches of independent circuits ----------------------------------------------
  * Many states evolved by independent circuits, updated together: the library's

@@ -26,9 +26,9 @@ MPS_PREC_FP64, MPS_PREC_DD = 0, 1
 MPS_OPT_MAX_SWEEPS, MPS_OPT_JACOBI_TOL, MPS_OPT_KERNEL_TIMING, MPS_OPT_RANK_FLOOR = 1, 2, 3, 4
 MPS_OPT_BLOCK_WIDTH, MPS_OPT_MAX_INNER, MPS_OPT_MAX_SLOTS, MPS_OPT_WORKSPACE_MB = 5, 6, 7, 8
 MPS_OPT_DD_REFINE, MPS_OPT_JACOBI_STREAMS, MPS_OPT_FUSE, MPS_OPT_QR, MPS_OPT_STEP_SPLIT = 9, 10, 11, 12, 13
-MPS_OPT_DD_STREAM, MPS_OPT_MAX_INNER_FEW = 14, 15
+MPS_OPT_DD_STREAM, MPS_OPT_MAX_INNER_FEW, MPS_OPT_TICK_SWEEPS, MPS_OPT_GRAPH = 14, 15, 16, 17
 KERNEL_CLASSES = ["theta", "jacobi", "truncate", "split", "gate1", "amplitude", "dd_refine", "rdo"]
-COUNTER_SWEEPS, COUNTER_SWEEPS_DD, COUNTER_NOCONV = 8, 9, 10
+COUNTER_SWEEPS, COUNTER_SWEEPS_DD, COUNTER_NOCONV, COUNTER_GRAPHS = 8, 9, 10, 11
 
 _STATUS = {0: "MPS_OK", -1: "MPS_EINVAL", -2: "MPS_ERANGE", -3: "MPS_ENOMEM", -4: "MPS_EDEVICE",
            -5: "MPS_ENOCONV", -6: "MPS_ENONFINITE", -7: "MPS_ESTATE"}
@@ -77,6 +77,8 @@ _lib.mps_kernel_time.argtypes = [_h, C.c_int, _dp, C.POINTER(C.c_long), C.c_int]
 _lib.mps_last_error.restype = C.c_char_p
 _lib.mps_last_error.argtypes = [_h]
 _lib.mps_version.restype = C.c_char_p
+_lib.mps_tuning_key.restype = C.c_char_p
+_lib.mps_tuning_key.argtypes = []
 _lib.mps_rdo.argtypes = [_h, C.c_int, C.POINTER(C.c_int), _dp]
 _lib.mps_rdo_dd.argtypes = [_h, C.c_int, C.POINTER(C.c_int), _dp, _dp]
 _lib.mps_rdo_block.argtypes = [_h, C.c_int, C.c_int, _dp]
@@ -96,7 +98,7 @@ EXPORTED = ["mps_create", "mps_create_ex", "mps_destroy", "mps_apply_gate", "mps
             "mps_apply_gates", "mps_apply_gate2", "mps_apply_gate2_dd", "mps_bond_dim", "mps_schmidt", "mps_schmidt_dd", "mps_amplitude",
             "mps_amplitude_dd", "mps_amplitudes", "mps_amplitudes_noalloc", "mps_stats", "mps_load", "mps_get_site",
             "mps_export", "mps_import",
-            "mps_set_option", "mps_sync", "mps_kernel_time", "mps_last_error", "mps_version",
+            "mps_set_option", "mps_sync", "mps_kernel_time", "mps_last_error", "mps_version", "mps_tuning_key",
             "mps_rdo", "mps_rdo_dd", "mps_rdo_block", "mps_batch_create", "mps_batch_run", "mps_batch_get", "mps_batch_set_option",
             "mps_batch_last_error", "mps_batch_destroy"]
 
@@ -121,6 +123,10 @@ def _gate_doubles(u, k):
 # ---------------------------------------------------------------- C-ABI mirrors
 def mps_version() -> str:
     return _lib.mps_version().decode()
+
+
+def mps_tuning_key() -> str:
+    return (_lib.mps_tuning_key() or b"").decode()
 
 
 def mps_last_error(h=None) -> str:

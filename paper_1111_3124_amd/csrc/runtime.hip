@@ -9,8 +9,12 @@
 // that every launch is sized to the live shapes.
 #include <hip/hip_runtime.h>
 
+#include <dlfcn.h>
+
 #include <algorithm>
 #include <deque>
+#include <fstream>
+#include <sstream>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -81,6 +85,14 @@ struct Arena {
 
 }  // namespace
 
+// One row of a tuning table: the step kernel configuration of Jacobi problems with
+// at most nmax columns at one precision, measured fastest on this device (written by
+// the package's autotuner).
+struct TuneEntry {
+  int prec = 0, nmax = 0;
+  int bw = 8, inner_few = 1, qr = 1;
+};
+
 struct Engine {
   int prec = MPS_PREC_FP64;
   hipStream_t stream = nullptr;
@@ -117,6 +129,10 @@ struct Engine {
   // starting point their refinement and polish expect on rank-deficient thetas
   int max_inner_few = 1;
   int block_width = 8;
+  // per-size step configurations from the tuning table of this device (see
+  // TuneEntry); off once block width, inner-sweep limit or QR is set explicitly
+  bool tuned = true;
+  std::vector<struct TuneEntry> tune;
   int max_slots = 32;
   double ws_limit = 16.0 * (1ull << 30);  // batch engines: workspace arena cap, bytes
   double tol_mult = 1.0;
@@ -142,6 +158,11 @@ struct Engine {
   long slot_sweeps = 0, slot_sweeps_dd = 0;  // update-sweeps executed (FP64, dd polish)
   long noconv_updates = 0;                    // splits finalised at a sweep limit
   long long* d_phase = nullptr;               // MPS_DEBUG_PHASES=1: step phase stamps
+  // Jacobi sweeps per tick (1 or 2) and whether they are replayed from captured graphs
+  int tick_sweeps = 2;
+  bool graphs_on = false;
+  std::map<std::vector<long long>, hipGraphExec_t> graphs;
+  long graphs_built = 0, graph_launches = 0;
 };
 
 struct mps_state {
@@ -202,6 +223,87 @@ int bond_capacity(int n, int chi, int b) {
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 constexpr int kQrMaxN = 1024;
 
+// ------------------------------------------------------------------ tuning table
+// A text file of sections
+//     key <arch> <hip runtime version>
+//     <fp64|dd> <nmax> <block width> <inner sweeps, few blocks> <qr 0|1>
+// (lines starting with # are comments).  The section whose key matches the device
+// and the runtime is used; without one the built-in defaults apply.  The file is
+// $MPS_TUNING_FILE, else tuning.txt beside this library.
+std::string tuning_key(int device) {
+  hipDeviceProp_t prop;
+  int ver = 0;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess || hipRuntimeGetVersion(&ver) != hipSuccess) return "";
+  std::string arch = prop.gcnArchName;
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch = arch.substr(0, colon);
+  return arch + " " + std::to_string(ver);
+}
+
+std::string tuning_path() {
+  if (const char* p = std::getenv("MPS_TUNING_FILE")) return p;
+  Dl_info info;
+  if (dladdr((void*)&tuning_path, &info) && info.dli_fname) {
+    std::string lib = info.dli_fname;
+    const size_t slash = lib.rfind('/');
+    return (slash == std::string::npos ? std::string(".") : lib.substr(0, slash)) + "/tuning.txt";
+  }
+  return "tuning.txt";
+}
+
+std::vector<TuneEntry> load_tuning(const std::string& key) {
+  std::vector<TuneEntry> out;
+  std::ifstream f(tuning_path());
+  if (!f || key.empty()) return out;
+  std::string line;
+  bool in = false;
+  while (std::getline(f, line)) {
+    std::istringstream ls(line);
+    std::string w;
+    if (!(ls >> w) || w[0] == '#') continue;
+    if (w == "key") {
+      std::string arch, ver;
+      ls >> arch >> ver;
+      in = (arch + " " + ver) == key;
+      continue;
+    }
+    if (!in || (w != "fp64" && w != "dd")) continue;
+    TuneEntry t;
+    t.prec = w == "dd" ? MPS_PREC_DD : MPS_PREC_FP64;
+    if (!(ls >> t.nmax >> t.bw >> t.inner_few >> t.qr)) continue;
+    if ((t.bw != 4 && t.bw != 8 && t.bw != 16) || t.inner_few < 1 || t.inner_few > 64 || t.nmax < 1) continue;
+    out.push_back(t);
+  }
+  std::sort(out.begin(), out.end(), [](const TuneEntry& a, const TuneEntry& b) {
+    return a.prec != b.prec ? a.prec < b.prec : a.nmax < b.nmax;
+  });
+  return out;
+}
+
+// the tables read so far, by key (each file is read once per key and process)
+std::mutex g_tune_mu;
+std::map<std::string, std::vector<TuneEntry>> g_tune;
+
+std::vector<TuneEntry> tuning_for(int device) {
+  const std::string key = tuning_key(device);
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = g_tune.find(key);
+  if (it == g_tune.end()) it = g_tune.emplace(key, load_tuning(key)).first;
+  return it->second;
+}
+
+// step configuration of a Jacobi problem with N columns: the first table row of the
+// engine's precision with N <= nmax, else the engine's options
+struct StepCfg {
+  int bw, inner_few, qr;
+};
+StepCfg step_cfg(const Engine* E, int N) {
+  if (E->tuned)
+    for (const TuneEntry& t : E->tune)
+      if (t.prec == E->prec && N <= t.nmax) return StepCfg{t.bw, t.inner_few, t.qr};
+  return StepCfg{E->block_width, E->max_inner_few, E->qr ? 1 : 0};
+}
+
 // ------------------------------------------------------------------ engines
 void engine_free(Engine* E);
 
@@ -232,6 +334,7 @@ Engine* engine_new(int prec, void* hip_stream, std::string* err) {
     engine_free(E);
     return nullptr;
   }
+  if (e == hipSuccess) E->tune = tuning_for(E->device);
   if (const char* dbg = std::getenv("MPS_DEBUG_PHASES"))
     if (dbg[0] == '1' && hipMalloc((void**)&E->d_phase, 8 * sizeof(long long)) != hipSuccess) E->d_phase = nullptr;
   return E;
@@ -264,6 +367,8 @@ void engine_free(Engine* E) {
   if (E->ev_qr) (void)hipEventDestroy(E->ev_qr);
   if (E->ev_fork) (void)hipEventDestroy(E->ev_fork);
   if (E->ev_join) (void)hipEventDestroy(E->ev_join);
+  for (auto& kv : E->graphs) (void)hipGraphExecDestroy(kv.second);
+  E->graphs.clear();
   if (E->d_phase) (void)hipFree(E->d_phase);
   if (E->ws) (void)hipFree(E->ws);
   if (E->d_small) (void)hipFree(E->d_small);
@@ -473,6 +578,7 @@ struct Slot {
   int fp64_sweeps = 0, dd_sweeps = 0;
   bool fp64_conv = false, conv = false;
   int M = 0, Nt = 0, JM = 0, N = 0;  // theta rows and columns, Jacobi rows and columns
+  int bw = 8, inner_few = 1;          // step kernel configuration (step_cfg)
   size_t ws_off = 0, ws_len = 0;  // workspace held in the arena
 };
 
@@ -638,6 +744,129 @@ size_t gate_need_cap(bool dd, const mps_state* h, int first, int k) {
   return 0;
 }
 
+// ------------------------------------------------------------------ Jacobi sweeps
+// The FP64 Jacobi sweeps of one tick.  The iterating updates form groups that share
+// a step kernel configuration (block width, inner-sweep limit); each group's updates
+// are split into two halves, whose step launches run on the engine's stream and on
+// stream2.  One sweep = the column-order kernel for every update, then the steps of
+// the round-robin schedule.  An update whose previous sweep rotated nothing leaves
+// each of its blocks at once (the kernels read its rotation flags), so sweeps past
+// its convergence change nothing: a tick may run K sweeps and read the flags once.
+struct SweepGroup {
+  int bw = 8, inner_few = 1;
+  int na = 0, nb = 0;  // updates of the two halves
+  int oa = 0, ob = 0;  // their offsets in the sweep's half lists
+  int mNa = 0, mNb = 0;
+  bool split_a = false, split_b = false;
+};
+
+struct SweepPlan {
+  std::vector<SweepGroup> groups;
+  int n_order = 0;  // updates in the order list
+  bool two = false;
+  int K = 1;        // sweeps
+  mpsk::Ent* la[2] = {nullptr, nullptr};  // per sweep: half-a list, half-b list, order list
+  mpsk::Ent* lb[2] = {nullptr, nullptr};
+  mpsk::Ent* lo[2] = {nullptr, nullptr};
+  long long* phase = nullptr;  // debug stamps of one step (direct launches only)
+};
+
+int steps_of(int N, int bw) {
+  const int nb = (N + bw - 1) / bw;
+  return nb + (nb & 1) - 1;
+}
+
+int plan_steps(const SweepPlan& P) {
+  int m = 0;
+  for (const SweepGroup& g : P.groups) m = std::max(m, std::max(steps_of(g.mNa, g.bw), g.nb ? steps_of(g.mNb, g.bw) : 0));
+  return m;
+}
+
+// enqueue the plan's K sweeps on st (and stream2): also the body of a captured graph
+hipError_t enqueue_sweeps(Engine* E, Task2* dt, const SweepPlan& P, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  const int nsteps = plan_steps(P);
+  for (int k = 0; k < P.K; ++k) {
+    e = mpsk::launch_jacobi_order(dt, P.lo[k], P.n_order, st);
+    if (e != hipSuccess) return e;
+    if (P.two) {
+      if ((e = hipEventRecord(E->ev_fork, st)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(E->stream2, E->ev_fork, 0)) != hipSuccess) return e;
+    }
+    for (int stp = 0; stp < nsteps; ++stp) {
+      for (const SweepGroup& g : P.groups) {
+        long long* pc = (P.phase && k == 0 && stp == nsteps / 2 && &g == &P.groups[0]) ? P.phase : nullptr;
+        if (g.na && stp < steps_of(g.mNa, g.bw)) {
+          e = (g.split_a && !pc)
+                  ? mpsk::launch_jacobi_split(dt, P.la[k] + g.oa, g.na, g.mNa, stp, E->tol_mult, E->max_inner,
+                                              g.inner_few, st)
+                  : mpsk::launch_jacobi_step(dt, P.la[k] + g.oa, g.na, g.mNa, g.bw, stp, E->tol_mult, E->max_inner,
+                                             g.inner_few, st, pc);
+          if (e != hipSuccess) return e;
+        }
+        if (g.nb && stp < steps_of(g.mNb, g.bw)) {
+          hipStream_t s2 = P.two ? E->stream2 : st;
+          e = g.split_b ? mpsk::launch_jacobi_split(dt, P.lb[k] + g.ob, g.nb, g.mNb, stp, E->tol_mult, E->max_inner,
+                                                    g.inner_few, s2)
+                        : mpsk::launch_jacobi_step(dt, P.lb[k] + g.ob, g.nb, g.mNb, g.bw, stp, E->tol_mult,
+                                                   E->max_inner, g.inner_few, s2, nullptr);
+          if (e != hipSuccess) return e;
+        }
+      }
+    }
+    if (P.two) {
+      if ((e = hipEventRecord(E->ev_join, E->stream2)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(st, E->ev_join, 0)) != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+// the plan's launch sequence as an instantiated graph (captured on first use and
+// kept while the engine lives); its shape and every device address it reads are
+// the key, the lists' contents are uploaded before each launch
+std::vector<long long> graph_key(const Engine* E, const Task2* dt, const SweepPlan& P) {
+  std::vector<long long> k = {P.K, P.two, P.n_order, (long long)(uintptr_t)dt, E->max_inner};
+  long long tol;
+  std::memcpy(&tol, &E->tol_mult, sizeof tol);
+  k.push_back(tol);
+  for (int i = 0; i < P.K; ++i)
+    for (const mpsk::Ent* l : {P.la[i], P.lb[i], P.lo[i]}) k.push_back((long long)(uintptr_t)l);
+  for (const SweepGroup& g : P.groups)
+    for (long long v : {g.bw, g.inner_few, g.na, g.nb, g.oa, g.ob, g.mNa, g.mNb, (int)g.split_a, (int)g.split_b})
+      k.push_back(v);
+  return k;
+}
+
+hipError_t launch_sweep_graph(Engine* E, Task2* dt, const SweepPlan& P, hipStream_t st) {
+  const std::vector<long long> key = graph_key(E, dt, P);
+  auto it = E->graphs.find(key);
+  if (it == E->graphs.end()) {
+    if (E->graphs.size() >= 256) {  // shapes come and go with the workload: start over
+      for (auto& kv : E->graphs) (void)hipGraphExecDestroy(kv.second);
+      E->graphs.clear();
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return e;
+    const hipError_t ec = enqueue_sweeps(E, dt, P, st);
+    e = hipStreamEndCapture(st, &g);
+    if (ec != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return ec;
+    }
+    if (e != hipSuccess) return e;
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return e;
+    it = E->graphs.emplace(key, x).first;
+    ++E->graphs_built;
+  }
+  ++E->graph_launches;
+  return hipGraphLaunch(it->second, st);
+}
+
 // Runs `gates` on the states `U` of engine E.  d_dims / dims_total: one device range
 // covering every state's bond-dimension table; dims_off[u] = offset of state u's.
 int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, int dims_total,
@@ -689,11 +918,11 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
   const size_t o_u8 = o_dims + align_up(sizeof(int) * dims_total);
   const size_t o_g1 = o_u8 + align_up(sizeof(double2) * 128 * S);
   const size_t o_ents = o_g1 + align_up(sizeof(Task1) * nsites);
-  // new2, new3, jacobi (two + order), dd, dd-enter, final, final3, mid, znorm, ref,
-  // polish, qr z, dd-enter QR tasks, and a ring of kQrRing lists of QR factorisations
-  // in flight
+  // new2, new3, jacobi (two halves + order, for each of two sweeps), dd, dd-enter,
+  // final, final3, mid, znorm, ref, polish, qr z, dd-enter QR tasks, and a ring of
+  // kQrRing lists of QR factorisations in flight
   constexpr int kQrRing = 4;
-  constexpr int kLists = 15 + kQrRing;
+  constexpr int kLists = 18 + kQrRing;
   const size_t list_bytes = align_up(sizeof(mpsk::Ent) * S);
   rc = ensure_small(E, o_ents + kLists * list_bytes, err);
   if (rc) return rc;
@@ -707,7 +936,7 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
   int* hdims = (int*)(E->h_stage + o_dims);
   double2* hu8 = (double2*)(E->h_stage + o_u8);
   double2* du8 = (double2*)(E->d_small + o_u8);
-  enum { LN2 = 0, LN3, LJ, LD, LENTER, LFIN, LFIN3, LMID, LZN, LR, LPOL, LJ2, LJO, LQZ, LQL, LQR0 };
+  enum { LN2 = 0, LN3, LJ, LD, LENTER, LFIN, LFIN3, LMID, LZN, LR, LPOL, LJ2, LJO, LQZ, LQL, LJ_1, LJ2_1, LJO_1, LQR0 };
   auto hlist = [&](int i) { return E->h_stage + o_ents + i * list_bytes; };
   auto dlist = [&](int i) { return E->d_small + o_ents + i * list_bytes; };
 
@@ -718,7 +947,6 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
   std::vector<size_t> head(nu, 0);  // per state: first queue entry not yet admitted
   size_t remaining = gates.size();
   int status = MPS_OK;
-  const int bw = E->block_width;
   int rot0 = 0;  // first state scanned at admission (rotates for fairness)
   hipError_t e;
   hipStream_t st = E->stream;
@@ -762,6 +990,62 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
     v.reserve(sl.size());
     for (int si : sl) v.push_back(mpsk::Ent{si, slot[si].sweep});
     return v;
+  };
+  // the FP64 sweeps of the iterating slots `jl` (K of them), as stream launches or
+  // as a replayed graph
+  auto launch_jacobi = [&](const std::vector<int>& jl, int K) -> hipError_t {
+    SweepPlan P;
+    P.K = K;
+    P.two = E->jacobi_streams == 2 && jl.size() >= 2;
+    P.n_order = (int)jl.size();
+    // groups by step kernel configuration, in order of first appearance
+    std::vector<std::vector<int>> ga, gb;
+    std::vector<std::pair<int, int>> cfgs;
+    for (int si : jl) {
+      const std::pair<int, int> c{slot[si].bw, slot[si].inner_few};
+      size_t gi = 0;
+      while (gi < cfgs.size() && cfgs[gi] != c) ++gi;
+      if (gi == cfgs.size()) {
+        cfgs.push_back(c);
+        ga.emplace_back();
+        gb.emplace_back();
+      }
+      // alternate updates of a group go to the two halves
+      ((P.two && ((ga[gi].size() + gb[gi].size()) & 1)) ? gb[gi] : ga[gi]).push_back(si);
+    }
+    std::vector<int> all_a, all_b;
+    for (size_t gi = 0; gi < cfgs.size(); ++gi) {
+      SweepGroup g;
+      g.bw = cfgs[gi].first;
+      g.inner_few = cfgs[gi].second;
+      g.na = (int)ga[gi].size();
+      g.nb = (int)gb[gi].size();
+      g.oa = (int)all_a.size();
+      g.ob = (int)all_b.size();
+      for (int si : ga[gi]) g.mNa = std::max(g.mNa, slot[si].N);
+      for (int si : gb[gi]) g.mNb = std::max(g.mNb, slot[si].N);
+      g.split_a = g.bw == 8 && g.na <= E->split_max;
+      g.split_b = g.bw == 8 && g.nb <= E->split_max;
+      all_a.insert(all_a.end(), ga[gi].begin(), ga[gi].end());
+      all_b.insert(all_b.end(), gb[gi].begin(), gb[gi].end());
+      P.groups.push_back(g);
+    }
+    const int lists[2][3] = {{LJ, LJ2, LJO}, {LJ_1, LJ2_1, LJO_1}};
+    for (int k = 0; k < K; ++k) {
+      auto with_sweep = [&](const std::vector<int>& v) {
+        std::vector<mpsk::Ent> out = ents_of(v);
+        for (mpsk::Ent& x : out) x.sweep += k;
+        return out;
+      };
+      P.la[k] = upload_list(lists[k][0], with_sweep(all_a));
+      P.lb[k] = all_b.empty() ? P.la[k] : upload_list(lists[k][1], with_sweep(all_b));
+      P.lo[k] = upload_list(lists[k][2], with_sweep(jl));
+      if (!P.la[k] || !P.lb[k] || !P.lo[k]) return hipErrorInvalidValue;
+    }
+    P.phase = E->d_phase;
+    Timed tm(E, 1, K * plan_steps(P));
+    if (E->graphs_on && !E->d_phase) return launch_sweep_graph(E, dt, P, st);
+    return enqueue_sweeps(E, dt, P, st);
   };
   std::vector<int> free_list;  // free slot indices, lowest last
   for (int si = S - 1; si >= 0; --si) free_list.push_back(si);
@@ -911,7 +1195,10 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
               new3.push_back(si);
             }
             carve(dd, t, E->ws + off1, d_flags, d_stats, d_fro, si);
-            if (g.k == 2 && E->qr) qr_select(dd, t);
+            const StepCfg cfg = step_cfg(E, t.N);
+            sl.bw = cfg.bw;
+            sl.inner_few = cfg.inner_few;
+            if (g.k == 2 && cfg.qr) qr_select(dd, t);
             if (t.qr) sl.state = 6;  // waits one tick for its QR factorisation
             mark(si);
             sl.M = t.M;
@@ -1034,59 +1321,12 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
         }
       }
     }
+    int K = 1;  // sweeps this tick
     if (!jl.empty()) {
-      // two halves (alternate updates) on two streams when there are at least two
-      const bool two = E->jacobi_streams == 2 && jl.size() >= 2;
-      std::vector<int> ja, jb;
-      for (size_t i = 0; i < jl.size(); ++i) ((two && (i & 1)) ? jb : ja).push_back(jl[i]);
-      mpsk::Ent* ea = upload_list(LJ, ents_of(ja));
-      mpsk::Ent* eb = two ? upload_list(LJ2, ents_of(jb)) : nullptr;
-      if (!ea || (two && !eb)) return fail(err, MPS_EDEVICE, "list upload failed");
-      int mNa = 0, mNb = 0;
-      for (int si : ja) mNa = std::max(mNa, slot[si].N);
-      for (int si : jb) mNb = std::max(mNb, slot[si].N);
-      const int mN = std::max(mNa, mNb);
-      const int nb = (mN + bw - 1) / bw;
-      const int nsteps = nb + (nb & 1) - 1;
-      const int nba = (mNa + bw - 1) / bw, nbb = (mNb + bw - 1) / bw;
-      const int nsa = nba + (nba & 1) - 1, nsb = two ? nbb + (nbb & 1) - 1 : 0;
-      Timed tm(E, 1, nsteps);
-      E->slot_sweeps += (long)jl.size();
-      {
-        mpsk::Ent* eo = upload_list(LJO, ents_of(jl));
-        if (!eo) return fail(err, MPS_EDEVICE, "list upload failed");
-        e = mpsk::launch_jacobi_order(dt, eo, (int)jl.size(), st);
-        if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("jacobi order: ") + hipGetErrorString(e));
-      }
-      if (two) {
-        HIPCHK(err, hipEventRecord(E->ev_fork, st));
-        HIPCHK(err, hipStreamWaitEvent(E->stream2, E->ev_fork, 0));
-      }
-      for (int stp = 0; stp < nsteps; ++stp) {
-        long long* pc = (E->d_phase && stp == nsteps / 2) ? E->d_phase : nullptr;
-        const bool split_a = bw == 8 && !pc && (int)ja.size() <= E->split_max;
-        const bool split_b = bw == 8 && (int)jb.size() <= E->split_max;
-        if (stp < nsa) {
-          e = split_a ? mpsk::launch_jacobi_split(dt, ea, (int)ja.size(), mNa, stp, E->tol_mult, E->max_inner,
-                                                  E->max_inner_few, st)
-                      : mpsk::launch_jacobi_step(dt, ea, (int)ja.size(), mNa, bw, stp, E->tol_mult, E->max_inner,
-                                                 E->max_inner_few, st,
-                                                 pc);
-          if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("jacobi: ") + hipGetErrorString(e));
-        }
-        if (stp < nsb) {
-          e = split_b ? mpsk::launch_jacobi_split(dt, eb, (int)jb.size(), mNb, stp, E->tol_mult, E->max_inner,
-                                                  E->max_inner_few, E->stream2)
-                      : mpsk::launch_jacobi_step(dt, eb, (int)jb.size(), mNb, bw, stp, E->tol_mult, E->max_inner,
-                                                 E->max_inner_few,
-                                                 E->stream2, nullptr);
-          if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("jacobi: ") + hipGetErrorString(e));
-        }
-      }
-      if (two) {
-        HIPCHK(err, hipEventRecord(E->ev_join, E->stream2));
-        HIPCHK(err, hipStreamWaitEvent(st, E->ev_join, 0));
-      }
+      K = std::max(1, std::min(2, E->tick_sweeps));
+      for (int si : jl) K = std::min(K, E->max_sweeps - slot[si].sweep);
+      K = std::max(K, 1);
+      HIPCHK(err, launch_jacobi(jl, K));
     }
     // finished QR factorisations: their slots start iterating at the next tick; when
     // this tick has no sweep work at all, wait for the oldest
@@ -1109,8 +1349,14 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
     std::vector<int> enter;
     for (int si : jl) {
       Slot& sl = slot[si];
-      const bool rot = hflags[3 * si + sl.sweep % 3] != 0;
-      ++sl.sweep;
+      // the tick's K sweeps: the first without a rotation ends the iteration (the
+      // sweeps after it left the update untouched)
+      bool rot = true;
+      for (int k = 0; k < K && rot; ++k) {
+        rot = hflags[3 * si + sl.sweep % 3] != 0;
+        ++sl.sweep;
+        ++E->slot_sweeps;
+      }
       if (!rot || sl.sweep >= E->max_sweeps) {
         sl.fp64_sweeps = sl.sweep;
         sl.fp64_conv = !rot;
@@ -1287,6 +1533,9 @@ int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, in
         sbl.sweep = 0;
         sbl.M = tb.M;
         sbl.N = tb.N;
+        const StepCfg cfg = step_cfg(E, tb.N);
+        sbl.bw = cfg.bw;
+        sbl.inner_few = cfg.inner_few;
         sbl.Nt = tb.Nt;
         sbl.JM = tb.JM;
         gsweeps[sa.gate] = sa.fp64_sweeps;
@@ -1392,6 +1641,7 @@ int set_option(Engine* E, int prec, int key, double value, std::string* err) {
     case MPS_OPT_BLOCK_WIDTH:
       if (!(value == 4 || value == 8 || value == 16)) return fail(err, MPS_EINVAL, "block width must be 4, 8 or 16");
       E->block_width = (int)value;
+      E->tuned = false;
       return MPS_OK;
     case MPS_OPT_MAX_INNER:
       if (!(value >= 1 && value <= 64)) return fail(err, MPS_EINVAL, "inner sweep limit out of range");
@@ -1400,6 +1650,7 @@ int set_option(Engine* E, int prec, int key, double value, std::string* err) {
     case MPS_OPT_MAX_INNER_FEW:
       if (!(value >= 1 && value <= 64)) return fail(err, MPS_EINVAL, "inner sweep limit out of range");
       E->max_inner_few = (int)value;
+      E->tuned = false;
       return MPS_OK;
     case MPS_OPT_RANK_FLOOR:
       if (!(value >= 0 && value < 1)) return fail(err, MPS_EINVAL, "rank floor out of range");
@@ -1421,6 +1672,7 @@ int set_option(Engine* E, int prec, int key, double value, std::string* err) {
     case MPS_OPT_QR:
       if (!(value == 0 || value == 1)) return fail(err, MPS_EINVAL, "QR switch must be 0 or 1");
       E->qr = value != 0;
+      E->tuned = false;
       return MPS_OK;
     case MPS_OPT_FUSE:
       if (!(value == 0 || value == 1)) return fail(err, MPS_EINVAL, "fusion switch must be 0 or 1");
@@ -1433,6 +1685,14 @@ int set_option(Engine* E, int prec, int key, double value, std::string* err) {
     case MPS_OPT_DD_REFINE:
       if (!(value == 0 || value == 1)) return fail(err, MPS_EINVAL, "dd refinement switch must be 0 or 1");
       E->dd_refine = value != 0;
+      return MPS_OK;
+    case MPS_OPT_TICK_SWEEPS:
+      if (!(value == 1 || value == 2)) return fail(err, MPS_EINVAL, "sweeps per tick must be 1 or 2");
+      E->tick_sweeps = (int)value;
+      return MPS_OK;
+    case MPS_OPT_GRAPH:
+      if (!(value == 0 || value == 1)) return fail(err, MPS_EINVAL, "graph switch must be 0 or 1");
+      E->graphs_on = value != 0;
       return MPS_OK;
     case MPS_OPT_WORKSPACE_MB:
       if (!(value >= 1 && value <= 1 << 22)) return fail(err, MPS_EINVAL, "workspace limit out of range");
@@ -1700,6 +1960,13 @@ int fail_na(mps_state* h, int code, const char* what, const char* detail = nullp
 extern "C" {
 
 const char* mps_version(void) { return "mps-mi355x 0.2 (gfx950)"; }
+
+const char* mps_tuning_key(void) {
+  static thread_local std::string key;
+  int dev = 0;
+  key = hipGetDevice(&dev) == hipSuccess ? tuning_key(dev) : std::string();
+  return key.c_str();
+}
 
 const char* mps_last_error(mps_handle h) { return h ? h->err.c_str() : g_create_error.c_str(); }
 
@@ -2334,10 +2601,16 @@ int mps_sync(mps_handle h) {
 }
 
 int mps_kernel_time(mps_handle h, int cls, double* ms, long* launches, int reset) {
-  if (!h || cls < 0 || cls >= 11) return MPS_EINVAL;
+  if (!h || cls < 0 || cls >= 12) return MPS_EINVAL;
   Engine* E = h->E;
   HIPCHK(h, hipStreamSynchronize(E->stream));
   harvest_timing(E);
+  if (cls == 11) {  // graph replays of Jacobi sweeps; *ms: graphs captured
+    if (ms) *ms = (double)E->graphs_built;
+    if (launches) *launches = E->graph_launches;
+    if (reset) E->graph_launches = E->graphs_built = 0;
+    return MPS_OK;
+  }
   if (cls >= 8) {  // counters: update-sweeps of the FP64 Jacobi (8) and of the dd polish (9),
                    // splits finalised at a sweep limit (10)
     long& c = cls == 8 ? E->slot_sweeps : cls == 9 ? E->slot_sweeps_dd : E->noconv_updates;
