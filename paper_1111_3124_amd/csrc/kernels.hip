@@ -691,13 +691,12 @@ __global__ __launch_bounds__(1024) void k_truncate(Task2* tasks, const Ent* ents
   __shared__ int idx[kMaxSort];
   __shared__ double sc[kMaxSort];
   __shared__ int s_rank, s_keps;
-  __shared__ double s_kept;
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int j = tid; j < P; j += nt) {
     key[j] = j < N ? fmax(T.sig2[j], 0.0) : -1.0;
     idx[j] = j;
   }
-  if (tid == 0) { s_rank = 0; s_keps = N; s_kept = 0.0; }
+  if (tid == 0) { s_rank = 0; s_keps = N; }
   __syncthreads();
   bitonic_desc(key, idx, P);
   // suffix sums: sc[j] = sum_{i >= j} sigma_i^2
@@ -734,11 +733,9 @@ __global__ __launch_bounds__(1024) void k_truncate(Task2* tasks, const Ent* ents
   const int mn = M < N ? M : N;
   if (mn < k) k = mn;
   if (k < 1) k = 1;
-  double part = 0.0;
-  for (int j = tid; j < k; j += nt) part += key[j];
-  atomicAdd(&s_kept, part);
-  __syncthreads();
-  const double nu = sqrt(s_kept);
+  // kept weight from the suffix sums (a fixed order of additions, so the result does
+  // not depend on how the block's waves are scheduled), as the dd truncation does
+  const double nu = sqrt(W - (k < N ? sc[k] : 0.0));
   for (int j = tid; j < N; j += nt) {
     T.perm[j] = idx[j];
     if (j < k) T.lamS[j] = sqrt(key[j]) / nu;

@@ -18,6 +18,12 @@ split is theta 1024 x 2048 (rows (alpha, i), columns (j, k, delta)), truncated t
 new bond dims, the Schmidt values of bonds 9 and 10, 24 amplitudes and both splits'
 diagnostics.  Several hours of 256-bit arithmetic on 8 cores.
 
+batch256_subset: configuration 4 (256 independent brickwork circuits of seed 4, n ~
+U{16..48}, chi_max ~ U{32, 64, 128, 256}, depth ~ U{8..24}, eps = 1e-12): the oracle
+runs of three of its circuits (indices 125, 222, 199: the smallest ones with chi_max
+= 32), each with its final bond dims and 32 amplitudes (bitstrings of seed 4000 +
+index).
+
 qft60_eps: configuration 5 with its own truncation: 60 qubits, the random product
 state of seed 5 (dd preparation gates), then the nearest-neighbour QFT network (60
 Hadamards, 1770 SWAP-phase U(4) gates, dd), chi_max = 1024, eps = 1e-24, applied
@@ -128,7 +134,40 @@ def make_qft60_eps():
     print("wrote qft60_eps.json", max(out["dims_after"]), min_gap, min_epsdist, f"{out['oracle_seconds']:.0f} s")
 
 
+BATCH_SUBSET = (125, 222, 199)
+
+
+def make_batch256_subset():
+    specs = W.batch_spec(256, 4)
+    out = dict(recipe="tests/golden/make_golden.py batch256_subset (oracle at 256 bits)", count=256, seed=4,
+               eps=1e-12, circuits=[])
+    t0 = time.time()
+    for i in BATCH_SUBSET:
+        sp = specs[i]
+        gates = [g for layer in W.brickwork(sp.n, sp.depth, sp.seed) for g in layer]
+        om = oracle.OracleMPS(sp.n, sp.chi_max, 1e-12)
+        min_gap, min_epsdist = float("inf"), float("inf")
+        for g in gates:
+            om.apply_gate(g)
+            for st in om.last_stats():
+                min_gap = min(min_gap, st["gap"])
+                min_epsdist = min(min_epsdist, st["epsdist"])
+        bits = W.bitstrings(sp.n, 32, 4000 + i)
+        ah, al = om.amplitudes(bits)
+        out["circuits"].append(dict(index=i, n=sp.n, chi_max=sp.chi_max, depth=sp.depth, gates=len(gates),
+                                    dims_after=om.bond_dims(), min_gap=min_gap, min_epsdist=min_epsdist,
+                                    amp_re_hi=ah.real.tolist(), amp_re_lo=al.real.tolist(),
+                                    amp_im_hi=ah.imag.tolist(), amp_im_lo=al.imag.tolist()))
+        om.close()
+        print(f"circuit {i}: n={sp.n} chi_max={sp.chi_max} depth={sp.depth} gates={len(gates)} "
+              f"gap {min_gap:.2e} epsdist {min_epsdist:.2e}", flush=True)
+    out.update(oracle_seconds=time.time() - t0, oracle_threads=oracle.oracle_threads())
+    with open(os.path.join(HERE, "batch256_subset.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print("wrote batch256_subset.json", f"{out['oracle_seconds']:.0f} s")
+
+
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "update_chi256"
     {"update_chi256": make_update_chi256, "update3_chi512": make_update3_chi512,
-     "qft60_eps": make_qft60_eps}[what]()
+     "qft60_eps": make_qft60_eps, "batch256_subset": make_batch256_subset}[what]()
