@@ -340,6 +340,70 @@ __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* en
       }
       Gb[0][i][j] = cmk(sr[0] + sr[1], (pij[0] + pij[1]) - (pji[0] + pji[1]));
     }
+  } else if constexpr (W2 == 32) {
+    // by MFMA, the pair's 32 columns as two halves of 16: per k-step of 4 rows lane l
+    // holds X[4 ks + l / 16][l % 16] of each half (x0, x1).  Re G = Xr^T Xr + Xi^T Xi
+    // from the tiles 00, 01 and 11 (10 = 01^T), P = Xr^T Xi from all four tiles, then
+    // Im G = P - P^T; wave w takes the k-steps w, w + 8, ...; the waves' tiles are added
+    // in wave order.
+    __shared__ double Gs[2][W2][W2 + 1];
+    constexpr int KB = 8;  // k-steps of loads in flight per wave
+    mfma_d4 r00 = {0.0, 0.0, 0.0, 0.0}, r01 = r00, r11 = r00, p00 = r00, p01 = r00, p10 = r00, p11 = r00;
+    const int c0 = cols[lane & 15], c1 = cols[16 + (lane & 15)];
+    const int roff = lane >> 4;
+    const int nks = (M + 3) / 4;
+    for (int ks0 = wave; ks0 < nks; ks0 += NW * KB) {
+      double2 x0[KB], x1[KB];
+#pragma unroll
+      for (int t = 0; t < KB; ++t) {
+        const int r = (ks0 + NW * t) * 4 + roff;
+        x0[t] = (c0 >= 0 && r < M) ? A[(long)c0 * M + r] : cmk(0.0, 0.0);
+        x1[t] = (c1 >= 0 && r < M) ? A[(long)c1 * M + r] : cmk(0.0, 0.0);
+      }
+#pragma unroll
+      for (int t = 0; t < KB; ++t) {
+        r00 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[t].x, x0[t].x, r00, 0, 0, 0);
+        r00 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[t].y, x0[t].y, r00, 0, 0, 0);
+        r01 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[t].x, x1[t].x, r01, 0, 0, 0);
+        r01 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[t].y, x1[t].y, r01, 0, 0, 0);
+        r11 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[t].x, x1[t].x, r11, 0, 0, 0);
+        r11 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[t].y, x1[t].y, r11, 0, 0, 0);
+        p00 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[t].x, x0[t].y, p00, 0, 0, 0);
+        p01 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[t].x, x1[t].y, p01, 0, 0, 0);
+        p10 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[t].x, x0[t].y, p10, 0, 0, 0);
+        p11 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[t].x, x1[t].y, p11, 0, 0, 0);
+      }
+    }
+    for (int w = 0; w < NW; ++w) {
+      if (wave == w) {
+        const int j = lane & 15;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = roff + 4 * r;
+          const bool first = w == 0;
+          double* re = &Gs[0][0][0];
+          double* pp = &Gs[1][0][0];
+          auto acc = [&](double* base, int ii, int jj, double v) {
+            double& d = base[ii * (W2 + 1) + jj];
+            d = first ? v : d + v;
+          };
+          acc(re, i, j, r00[r]);
+          acc(re, i, 16 + j, r01[r]);
+          acc(re, 16 + i, 16 + j, r11[r]);
+          acc(pp, i, j, p00[r]);
+          acc(pp, i, 16 + j, p01[r]);
+          acc(pp, 16 + i, j, p10[r]);
+          acc(pp, 16 + i, 16 + j, p11[r]);
+        }
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < W2 * W2; e += NT) {
+      const int i = e / W2, j = e % W2;
+      // Re G's lower-left tile is the transpose of its upper-right one
+      const double re = (i >= 16 && j < 16) ? Gs[0][j][i] : Gs[0][i][j];
+      Gb[0][i][j] = cmk(re, Gs[1][i][j] - Gs[1][j][i]);
+    }
   } else {
     // row chunks staged in LDS, D chunks of loads in flight; each wave an eighth of
     // a chunk's rows, each lane a TB x TB register block of G

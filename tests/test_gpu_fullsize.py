@@ -29,12 +29,17 @@ def fixture():
     return json.load(open(GOLD)), make_golden.update_chi256_inputs()
 
 
+@pytest.mark.parametrize("bw", [None, 16, 4])
 @pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-26)])
-def test_update_chi256(B, fixture, prec, tol):
+def test_update_chi256(B, fixture, prec, tol, bw):
+    """bw None: the tuned step configuration; 16 and 4: that block width forced (32-
+    and 8-column pairs: 31 or 127 steps a sweep instead of 63)."""
     g, inp = fixture
-    print(f"full-size update: prec={prec} n={inp['n']} site={inp['first']}", flush=True)
+    print(f"full-size update: prec={prec} bw={bw} n={inp['n']} site={inp['first']}", flush=True)
     assert g["split"]["gap"] > (1e-10 if prec == 0 else 1e-20)
     d = B.MPS(inp["n"], inp["chi"], inp["eps"], prec)
+    if bw is not None:
+        d.set_option(B.MPS_OPT_BLOCK_WIDTH, bw)
     d.load(inp["B"], inp["lam"])
     d.apply(inp["first"], 2, inp["U"])
     assert d.bond_dims() == g["dims_after"]
