@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libmps_hip.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["kernels.hip", "kernels_qr.hip", "dd_kernels.hip", "kernels3.hip", "ddref.hip", "rdo.hip", "runtime.hip"]
+SOURCES = ["kernels.hip", "kernels_qr.hip", "dd_kernels.hip", "kernels3.hip", "ddref.hip", "rdo.hip", "engine.hip", "sched.hip",
+           "runtime.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-mcode-object-version=5",

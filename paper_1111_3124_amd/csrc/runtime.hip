@@ -1,215 +1,13 @@
-// Host runtime of the MPS gate-update library: engines (stream, workspace arena,
-// staging, timing), states, the update scheduler and the C ABI of include/mps.h.
-//
-// An engine owns everything a run of the scheduler needs besides the states: one
-// standalone handle owns one engine; a batch owns one engine shared by all its
-// states, so the updates of every circuit of the batch run in the same launches.
-// Bond dimensions live in device tables written by the truncation kernel; the
-// host mirrors them after each finalisation (one small device-to-host copy), so
-// that every launch is sized to the live shapes.
-#include <hip/hip_runtime.h>
+// The C ABI of include/mps.h: states and batches (device memory, product states,
+// loading, checkpoints), gate validation and fusion, readout (Schmidt values,
+// amplitudes, reduced density operators) and options; updates go to the scheduler.
+#include "runtime.h"
 
-#include <dlfcn.h>
-
-#include <algorithm>
-#include <deque>
-#include <fstream>
-#include <sstream>
-#include <cmath>
-#include <cstdint>
-#include <cstdio>
-#include <cstdlib>
-#include <cstring>
-#include <map>
-#include <mutex>
-#include <string>
-#include <vector>
-
-#include "../../include/mps.h"
-#include "common.h"
-#include "dd.h"
-#include "dd_kernels.h"
-#include "ddref.h"
-#include "kernels3.h"
-#include "launch.h"
-#include "rdo.h"
-
-using mpsk::Task1;
-using mpsk::Task2;
+using namespace mpsrt;
 
 namespace {
 
 thread_local std::string g_create_error;
-
-struct EvPair {
-  hipEvent_t a, b;
-  int cls;
-  int n;
-};
-
-// First-fit allocator of offsets in the workspace arena, with coalescing.
-struct Arena {
-  size_t size = 0;
-  std::map<size_t, size_t> fr;  // offset -> length of each free block
-  void reset(size_t s) {
-    size = s;
-    fr.clear();
-    if (s) fr[0] = s;
-  }
-  size_t alloc(size_t len) {
-    for (auto it = fr.begin(); it != fr.end(); ++it)
-      if (it->second >= len) {
-        const size_t off = it->first, rem = it->second - len;
-        fr.erase(it);
-        if (rem) fr[off + len] = rem;
-        return off;
-      }
-    return SIZE_MAX;
-  }
-  void release(size_t off, size_t len) {
-    auto it = fr.emplace(off, len).first;
-    auto nx = std::next(it);
-    if (nx != fr.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      fr.erase(nx);
-    }
-    if (it != fr.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        fr.erase(it);
-      }
-    }
-  }
-};
-
-}  // namespace
-
-// One row of a tuning table: the step kernel configuration of Jacobi problems with
-// at most nmax columns at one precision, measured fastest on this device (written by
-// the package's autotuner).
-struct TuneEntry {
-  int prec = 0, nmax = 0;
-  int bw = 8, inner_few = 1, qr = 1;
-};
-
-struct Engine {
-  int prec = MPS_PREC_FP64;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  // the Jacobi steps of a tick run as two interleaved launch sequences (half the
-  // iterating updates each) on stream and stream2, so that one half's memory phases
-  // overlap the other half's inner Jacobi
-  hipStream_t stream2 = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  // QR factorisations of newly admitted updates run on stream3, overlapping the
-  // tick's Jacobi sweep of the updates already iterating
-  hipStream_t stream3 = nullptr;
-  hipEvent_t ev_qr = nullptr;
-  // dd refinement passes, dd polish sweeps and the dd promotion of converged updates
-  // run on stream4, overlapping the FP64 sweeps of the others; joined before every
-  // readback of the rotation flags
-  hipStream_t stream4 = nullptr;
-  hipEvent_t ev_dd_fork = nullptr, ev_dd_join = nullptr;
-  bool dd_stream = true;
-  int jacobi_streams = 2;
-  bool fuse = true;  // mps_apply_gates multiplies single-site gates into neighbours
-  bool qr = true;   // QR preconditioning of two-site Jacobi problems
-  // block width 8: a step launch serving at most this many updates runs as two launches
-  // of half-sized blocks (more blocks for few updates); 0: never
-  int split_max = 4;
-  int device = 0;
-  bool batch = false;  // a batch engine sizes workspace per update, not per slot
-  // options (shared by every state of the engine)
-  int max_sweeps = 40;
-  int max_sweeps_dd = 16;
-  int max_inner = 1;
-  // inner sweeps per block pair, tasks with fewer than 16 blocks: one for FP64 (the
-  // cheapest overall); dd engines keep every pair diagonalised per step (12), the
-  // starting point their refinement and polish expect on rank-deficient thetas
-  int max_inner_few = 1;
-  int block_width = 8;
-  // per-size step configurations from the tuning table of this device (see
-  // TuneEntry); off once block width, inner-sweep limit or QR is set explicitly
-  bool tuned = true;
-  std::vector<struct TuneEntry> tune;
-  int max_slots = 32;
-  double ws_limit = 16.0 * (1ull << 30);  // batch engines: workspace arena cap, bytes
-  double tol_mult = 1.0;
-  bool dd_refine = true;  // dd: simultaneous first-order corrections before any pairwise polish
-  int max_ref_passes = 4;
-  double rank_floor = 0x1p-44;
-  double rank_floor_dd = 0x1p-96;
-  bool timing = false;
-  bool debug_sweeps = false;  // MPS_DEBUG_SWEEPS=1: print per-update sweep counts
-  // workspace
-  char* ws = nullptr;
-  size_t ws_size = 0;
-  Arena arena;
-  char* h_stage = nullptr;  // pinned host staging (task arrays, readbacks)
-  size_t h_stage_size = 0;
-  char* d_small = nullptr;  // device task arrays + flags + stats
-  size_t d_small_size = 0;
-  // timing
-  std::vector<EvPair> pending;
-  std::vector<hipEvent_t> evpool;
-  double tms[8] = {0};
-  long tcount[8] = {0};
-  long slot_sweeps = 0, slot_sweeps_dd = 0;  // update-sweeps executed (FP64, dd polish)
-  long noconv_updates = 0;                    // splits finalised at a sweep limit
-  long long* d_phase = nullptr;               // MPS_DEBUG_PHASES=1: step phase stamps
-  // Jacobi sweeps per tick (1 or 2) and whether they are replayed from captured graphs
-  int tick_sweeps = 2;
-  bool graphs_on = false;
-  std::map<std::vector<long long>, hipGraphExec_t> graphs;
-  long graphs_built = 0, graph_launches = 0;
-};
-
-struct mps_state {
-  int n = 0, chi = 0, prec = MPS_PREC_FP64;
-  double eps = 0.0;
-  Engine* E = nullptr;
-  bool own_engine = false;
-  mps_batch* batch = nullptr;  // non-null: a member of a batch (which owns its memory)
-  char* mem = nullptr;         // device block holding B, B_lo, V, V_lo, dims (standalone)
-  std::vector<int> capx;  // capx[b+1] = capacity of bond b; capx[0] = capx[n] = 1
-  std::vector<int> dimx;  // host mirror of the bond dims, same indexing
-  int* d_dimx = nullptr;
-  std::vector<double2*> B, Blo;  // per site, capx[s] * 2 * capx[s+1]
-  double* d_lam = nullptr;       // (n+1) slots x chi; slot b+1 = bond b; slots 0, n = [1]
-  double* d_lam_lo = nullptr;
-  mps_update_stats last{};
-  std::string err;
-  // room for any message this library writes, so that an error on a path that must
-  // not allocate (mps_amplitudes_noalloc) does not grow the string
-  mps_state() { err.reserve(256); }
-};
-
-struct mps_batch {
-  Engine* E = nullptr;
-  std::vector<mps_state*> units;
-  char* mem = nullptr;  // one device block for every state
-  int* d_dims = nullptr;  // all bond-dimension tables, back to back
-  int dims_total = 0;
-  std::string err;
-};
-
-namespace {
-
-int fail(std::string* err, int code, const std::string& msg) {
-  if (err) *err = msg;
-  return code;
-}
-int fail(mps_state* h, int code, const std::string& msg) { return fail(h ? &h->err : nullptr, code, msg); }
-int fail(mps_batch* b, int code, const std::string& msg) { return fail(b ? &b->err : nullptr, code, msg); }
-
-#define HIPCHK(h, call)                                                                        \
-  do {                                                                                         \
-    hipError_t e_ = (call);                                                                    \
-    if (e_ != hipSuccess)                                                                      \
-      return fail(h, e_ == hipErrorOutOfMemory ? MPS_ENOMEM : MPS_EDEVICE,                     \
-                  std::string(#call) + ": " + hipGetErrorString(e_));                          \
-  } while (0)
 
 int bond_capacity(int n, int chi, int b) {
   // min(chi, 2^{b+1}, 2^{n-1-b})
@@ -218,249 +16,6 @@ int bond_capacity(int n, int chi, int b) {
   if (l < 31) c = std::min(c, 1L << l);
   if (r < 31) c = std::min(c, 1L << r);
   return (int)c;
-}
-
-size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
-constexpr int kQrMaxN = 1024;
-
-// ------------------------------------------------------------------ tuning table
-// A text file of sections
-//     key <arch> <hip runtime version>
-//     <fp64|dd> <nmax> <block width> <inner sweeps, few blocks> <qr 0|1>
-// (lines starting with # are comments).  The section whose key matches the device
-// and the runtime is used; without one the built-in defaults apply.  The file is
-// $MPS_TUNING_FILE, else tuning.txt beside this library.
-std::string tuning_key(int device) {
-  hipDeviceProp_t prop;
-  int ver = 0;
-  if (hipGetDeviceProperties(&prop, device) != hipSuccess || hipRuntimeGetVersion(&ver) != hipSuccess) return "";
-  std::string arch = prop.gcnArchName;
-  const size_t colon = arch.find(':');
-  if (colon != std::string::npos) arch = arch.substr(0, colon);
-  return arch + " " + std::to_string(ver);
-}
-
-std::string tuning_path() {
-  if (const char* p = std::getenv("MPS_TUNING_FILE")) return p;
-  Dl_info info;
-  if (dladdr((void*)&tuning_path, &info) && info.dli_fname) {
-    std::string lib = info.dli_fname;
-    const size_t slash = lib.rfind('/');
-    return (slash == std::string::npos ? std::string(".") : lib.substr(0, slash)) + "/tuning.txt";
-  }
-  return "tuning.txt";
-}
-
-std::vector<TuneEntry> load_tuning(const std::string& key) {
-  std::vector<TuneEntry> out;
-  std::ifstream f(tuning_path());
-  if (!f || key.empty()) return out;
-  std::string line;
-  bool in = false;
-  while (std::getline(f, line)) {
-    std::istringstream ls(line);
-    std::string w;
-    if (!(ls >> w) || w[0] == '#') continue;
-    if (w == "key") {
-      std::string arch, ver;
-      ls >> arch >> ver;
-      in = (arch + " " + ver) == key;
-      continue;
-    }
-    if (!in || (w != "fp64" && w != "dd")) continue;
-    TuneEntry t;
-    t.prec = w == "dd" ? MPS_PREC_DD : MPS_PREC_FP64;
-    if (!(ls >> t.nmax >> t.bw >> t.inner_few >> t.qr)) continue;
-    if ((t.bw != 4 && t.bw != 8 && t.bw != 16) || t.inner_few < 1 || t.inner_few > 64 || t.nmax < 1) continue;
-    out.push_back(t);
-  }
-  std::sort(out.begin(), out.end(), [](const TuneEntry& a, const TuneEntry& b) {
-    return a.prec != b.prec ? a.prec < b.prec : a.nmax < b.nmax;
-  });
-  return out;
-}
-
-// the tables read so far, by key (each file is read once per key and process)
-std::mutex g_tune_mu;
-std::map<std::string, std::vector<TuneEntry>> g_tune;
-
-std::vector<TuneEntry> tuning_for(int device) {
-  const std::string key = tuning_key(device);
-  std::lock_guard<std::mutex> lock(g_tune_mu);
-  auto it = g_tune.find(key);
-  if (it == g_tune.end()) it = g_tune.emplace(key, load_tuning(key)).first;
-  return it->second;
-}
-
-// step configuration of a Jacobi problem with N columns: the first table row of the
-// engine's precision with N <= nmax, else the engine's options
-struct StepCfg {
-  int bw, inner_few, qr;
-};
-StepCfg step_cfg(const Engine* E, int N) {
-  if (E->tuned)
-    for (const TuneEntry& t : E->tune)
-      if (t.prec == E->prec && N <= t.nmax) return StepCfg{t.bw, t.inner_few, t.qr};
-  return StepCfg{E->block_width, E->max_inner_few, E->qr ? 1 : 0};
-}
-
-// ------------------------------------------------------------------ engines
-void engine_free(Engine* E);
-
-Engine* engine_new(int prec, void* hip_stream, std::string* err) {
-  Engine* E = new Engine();
-  E->prec = prec;
-  if (prec == MPS_PREC_DD) E->max_inner_few = 12;
-  if (const char* dbg = std::getenv("MPS_DEBUG_SWEEPS")) E->debug_sweeps = dbg[0] == '1';
-  hipError_t e = hipGetDevice(&E->device);
-  if (e == hipSuccess) {
-    if (hip_stream) {
-      E->stream = (hipStream_t)hip_stream;
-    } else {
-      e = hipStreamCreateWithFlags(&E->stream, hipStreamNonBlocking);
-      E->own_stream = e == hipSuccess;
-    }
-  }
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&E->stream2, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&E->ev_fork, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&E->ev_join, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&E->stream3, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&E->ev_qr, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&E->stream4, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&E->ev_dd_fork, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&E->ev_dd_join, hipEventDisableTiming);
-  if (e != hipSuccess) {
-    *err = std::string("engine: ") + hipGetErrorString(e);
-    engine_free(E);
-    return nullptr;
-  }
-  if (e == hipSuccess) E->tune = tuning_for(E->device);
-  if (const char* dbg = std::getenv("MPS_DEBUG_PHASES"))
-    if (dbg[0] == '1' && hipMalloc((void**)&E->d_phase, 8 * sizeof(long long)) != hipSuccess) E->d_phase = nullptr;
-  return E;
-}
-
-// wait for every stream of the engine (before memory that kernels may touch is freed)
-void engine_sync(Engine* E) {
-  if (!E) return;
-  for (hipStream_t q : {E->stream, E->stream2, E->stream3, E->stream4})
-    if (q) (void)hipStreamSynchronize(q);
-}
-
-void engine_free(Engine* E) {
-  if (!E) return;
-  if (E->stream) (void)hipStreamSynchronize(E->stream);
-  if (E->stream2) {
-    (void)hipStreamSynchronize(E->stream2);
-    (void)hipStreamDestroy(E->stream2);
-  }
-  if (E->stream3) {
-    (void)hipStreamSynchronize(E->stream3);
-    (void)hipStreamDestroy(E->stream3);
-  }
-  if (E->stream4) {
-    (void)hipStreamSynchronize(E->stream4);
-    (void)hipStreamDestroy(E->stream4);
-  }
-  if (E->ev_dd_fork) (void)hipEventDestroy(E->ev_dd_fork);
-  if (E->ev_dd_join) (void)hipEventDestroy(E->ev_dd_join);
-  if (E->ev_qr) (void)hipEventDestroy(E->ev_qr);
-  if (E->ev_fork) (void)hipEventDestroy(E->ev_fork);
-  if (E->ev_join) (void)hipEventDestroy(E->ev_join);
-  for (auto& kv : E->graphs) (void)hipGraphExecDestroy(kv.second);
-  E->graphs.clear();
-  if (E->d_phase) (void)hipFree(E->d_phase);
-  if (E->ws) (void)hipFree(E->ws);
-  if (E->d_small) (void)hipFree(E->d_small);
-  if (E->h_stage) (void)hipHostFree(E->h_stage);
-  for (auto& p : E->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
-  for (auto e : E->evpool) (void)hipEventDestroy(e);
-  if (E->own_stream && E->stream) (void)hipStreamDestroy(E->stream);
-  delete E;
-}
-
-hipEvent_t ev_get(Engine* E) {
-  if (!E->evpool.empty()) {
-    hipEvent_t e = E->evpool.back();
-    E->evpool.pop_back();
-    return e;
-  }
-  hipEvent_t e;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
-  return e;
-}
-
-struct Timed {
-  Engine* E;
-  EvPair p{};
-  bool on;
-  hipStream_t s;
-  // `launches` kernels are enqueued on stream `ss` (default: the engine's) between
-  // the two events
-  Timed(Engine* EE, int cls, int launches = 1, hipStream_t ss = nullptr)
-      : E(EE), on(EE->timing), s(ss ? ss : EE->stream) {
-    if (on) {
-      p.a = ev_get(E);
-      p.b = ev_get(E);
-      p.cls = cls;
-      p.n = launches;
-      (void)hipEventRecord(p.a, s);
-    }
-  }
-  ~Timed() {
-    if (on) {
-      (void)hipEventRecord(p.b, s);
-      E->pending.push_back(p);
-    }
-  }
-};
-
-// after a synchronisation: fold finished event pairs into the per-class totals
-void harvest_timing(Engine* E) {
-  for (auto& p : E->pending) {
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
-      E->tms[p.cls] += ms;
-      E->tcount[p.cls] += p.n;
-    }
-    E->evpool.push_back(p.a);
-    E->evpool.push_back(p.b);
-  }
-  E->pending.clear();
-}
-
-// the arena must hold `bytes`; only called while no update holds workspace
-int ensure_ws(Engine* E, size_t bytes, std::string* err) {
-  if (bytes > E->ws_size) {
-    HIPCHK(err, hipStreamSynchronize(E->stream));
-    HIPCHK(err, hipStreamSynchronize(E->stream4));
-    if (E->ws) HIPCHK(err, hipFree(E->ws));
-    E->ws = nullptr;
-    E->ws_size = 0;
-    HIPCHK(err, hipMalloc((void**)&E->ws, bytes));
-    E->ws_size = bytes;
-  }
-  E->arena.reset(E->ws_size);
-  return MPS_OK;
-}
-
-int ensure_small(Engine* E, size_t bytes, std::string* err) {
-  if (bytes <= E->d_small_size && bytes <= E->h_stage_size) return MPS_OK;
-  HIPCHK(err, hipStreamSynchronize(E->stream));
-  size_t want = std::max<size_t>(bytes, 1 << 16);
-  if (bytes > E->d_small_size) {
-    if (E->d_small) HIPCHK(err, hipFree(E->d_small));
-    E->d_small = nullptr;
-    HIPCHK(err, hipMalloc((void**)&E->d_small, want));
-    E->d_small_size = want;
-  }
-  if (bytes > E->h_stage_size) {
-    if (E->h_stage) HIPCHK(err, hipHostFree(E->h_stage));
-    E->h_stage = nullptr;
-    HIPCHK(err, hipHostMalloc((void**)&E->h_stage, want, hipHostMallocDefault));
-    E->h_stage_size = want;
-  }
-  return MPS_OK;
 }
 
 // ------------------------------------------------------------------ state memory
@@ -544,1166 +99,8 @@ int validate_gate(const mps_state* h, int first, int k, const double* U, const d
   return MPS_OK;
 }
 
-struct GateRef {
-  int unit;  // index of the state in the run's state list
-  int first, k;
-  const double* U;
-  const double* Ulo;
-};
-
-// ------------------------------------------------------------------ update scheduler
-// Continuous batching of gate updates over one or more states.  Each two-site
-// split occupies a slot (task descriptor + workspace from the engine's arena).
-// One scheduler tick:
-//   1. admit queued gates whose sites are free and not claimed by an earlier queued
-//      gate of the same state (gates on disjoint sites commute, so queue order is
-//      kept where it matters; states are independent): a single-site gate runs at
-//      once; a two-site gate takes a slot and gets its prep + theta launch; a
-//      three-site gate takes a slot for its first split (s | s+1 s+2) and reserves
-//      a second one for its second split;
-//   2. one Jacobi sweep for every slot still iterating (FP64 sweeps, or dd polish
-//      sweeps after the FP64 iteration of a dd state has converged);
-//   3. read the rotation flags; converged slots are truncated and split at once and
-//      their new bond dimensions read back.  A finished first split of a three-site
-//      gate hands Z1_k^H, weighted by its new Schmidt values, to the reserved slot as
-//      the theta of the second split; any other finished slot frees its sites.
-// A slow update never holds back updates that do not depend on it.
-struct Slot {
-  int state = 0;  // 0 free, 1 FP64 Jacobi, 2 dd refinement passes, 4 dd pairwise polish,
-                  // 3 ready to finalise, 5 reserved
-  int kind = 0;   // 0 two-site, 1 three-site first split, 2 three-site second split
-  int gate = -1;
-  int partner = -1;  // kind 1: the reserved slot of the second split
-  int sweep = 0;
-  int fp64_sweeps = 0, dd_sweeps = 0;
-  bool fp64_conv = false, conv = false;
-  int M = 0, Nt = 0, JM = 0, N = 0;  // theta rows and columns, Jacobi rows and columns
-  int bw = 8, inner_few = 1;          // step kernel configuration (step_cfg)
-  size_t ws_off = 0, ws_len = 0;  // workspace held in the arena
-};
-
-// Workspace of a task with an M x Nt theta: theta and theta_w (later W; for a wide
-// theta theta_w^H, then Z), V (N x N, N = min(M, Nt)), the dd scratch (two N x N, one
-// M x N), sigma^2, the order and T1 (three-site first split).
-// partial Grams of the split Jacobi step (block width 8): the pairs of the padded
-// block count, two row halves, two 16 x 16 parts
-size_t jg_doubles(int N) { return (size_t)((N + 7) / 8 + 2) / 2 * 2 * 2 * 256; }
-
-size_t task_ws_bytes(bool dd, int M, int Nt, int t1) {
-  const int N = std::min(M, Nt), P = dd ? 2 : 1;
-  const size_t MN = (size_t)M * Nt, NN = (size_t)N * N;
-  size_t b = align_up((2 * MN + NN) * sizeof(double2)) * P;
-  if (dd) b += 2 * align_up(NN * sizeof(double2)) + align_up(MN * sizeof(double2));
-  b += align_up(N * sizeof(double)) * P + align_up(N * sizeof(int));
-  b += align_up((size_t)t1 * sizeof(double2)) * P;
-  // QR preconditioning: order, reflector heads, scales, panel factors (16 x 16 each)
-  b += align_up(N * sizeof(int)) + align_up(N * sizeof(double2)) + align_up(N * sizeof(double)) +
-       align_up((size_t)((N + 15) / 16) * 256 * sizeof(double2));
-  b += align_up(jg_doubles(N) * sizeof(double));  // split Jacobi step: partial Grams
-  return b;
-}
-
-// a bound over every task with M <= Mcap and Nt <= Ncap (task_ws_bytes is monotone)
-size_t task_ws_bound(bool dd, int Mcap, int Ncap, int t1) { return task_ws_bytes(dd, Mcap, Ncap, t1); }
-
-// theta columns; a wide theta (Nt > M) runs its one-sided Jacobi on theta_w^H, whose
-// M columns are independent (theta_w's Nt columns would have to be driven to rank M)
-void set_cols(Task2& t, int Nt) {
-  t.Nt = Nt;
-  t.tr = Nt > t.M ? 1 : 0;
-  t.JM = t.tr ? Nt : t.M;
-  t.N = t.tr ? t.M : Nt;
-}
-
-// workspace pointers of a task (shape already set), carved from the region w
-void carve(bool dd, Task2& t, char* w, int* d_flags, double* d_stats, double* d_fro, int slot) {
-  const size_t MN = (size_t)t.M * t.Nt, NN = (size_t)t.N * t.N;
-  t.thu = (double2*)w;
-  t.thw = t.thu + MN;
-  t.V = t.thw + MN;
-  w += align_up((2 * MN + NN) * sizeof(double2));
-  if (dd) {
-    t.thu_lo = (double2*)w;
-    t.thw_lo = t.thu_lo + MN;
-    t.V_lo = t.thw_lo + MN;
-    w += align_up((2 * MN + NN) * sizeof(double2));
-    t.aux1 = (double2*)w;
-    w += align_up(NN * sizeof(double2));
-    t.aux2 = (double2*)w;
-    w += align_up(NN * sizeof(double2));
-    t.aux3 = (double2*)w;
-    w += align_up(MN * sizeof(double2));
-  }
-  t.sig2 = (double*)w;
-  w += align_up(t.N * sizeof(double));
-  if (dd) {
-    t.sig2_lo = (double*)w;
-    w += align_up(t.N * sizeof(double));
-  }
-  t.perm = (int*)w;
-  w += align_up(t.N * sizeof(int));
-  if (t.B3) {
-    const size_t t1 = (size_t)4 * t.a * t.c;
-    t.T1 = (double2*)w;
-    w += align_up(t1 * sizeof(double2));
-    if (dd) {
-      t.T1_lo = (double2*)w;
-      w += align_up(t1 * sizeof(double2));
-    }
-  }
-  t.qperm = (int*)w;
-  w += align_up(t.N * sizeof(int));
-  t.qvd = (double2*)w;
-  w += align_up(t.N * sizeof(double2));
-  t.qt = (double*)w;
-  w += align_up(t.N * sizeof(double));
-  t.qT = (double2*)w;
-  w += align_up((size_t)((t.N + 15) / 16) * 256 * sizeof(double2));
-  t.JG = (double*)w;
-  w += align_up(jg_doubles(t.N) * sizeof(double));
-  t.qr = 0;
-  t.JW = t.thw;
-  t.JV = t.V;
-  t.JR = t.JM;
-  t.jvec = 1;
-  // the split's right factor: V, or for a wide theta W itself (its kept columns are
-  // scaled to unit norm after the truncation)
-  t.Z = t.tr ? t.thw : t.V;
-  t.Z_lo = t.tr ? t.thw_lo : t.V_lo;
-  t.flags = d_flags + 3 * slot;
-  t.stats = d_stats + 8 * slot;
-  t.fro2 = d_fro + slot;
-}
-
-// QR preconditioning of a two-site task (theta_w P = Q R, Jacobi on R^H): tall or
-// square thetas with 64 <= N and M <= 1024 (the panel kernel keeps at most two rows
-// a thread), and for double-double only square ones (their refinement then runs on
-// the transposed problem from the left singular vectors Q V).  FP64: the Jacobi's W
-// is R^H in V's storage, V is not accumulated, Z is formed in theta_w's storage.
-void qr_select(bool dd, Task2& t) {
-  if (t.tr || t.N < 64 || t.M > 1024 || t.N > kQrMaxN || (dd && t.M != t.N)) return;
-  t.qr = 1;
-  t.JR = t.N;
-  if (dd) {
-    t.JW = t.aux1;
-    t.JV = t.V;
-    t.jvec = 1;
-  } else {
-    t.JW = t.V;
-    t.JV = nullptr;
-    t.jvec = 0;
-    t.Z = t.thw;
-  }
-}
-
-// a QR-preconditioned dd task after its FP64 Jacobi (V = Q V_x, the left singular
-// vectors): from here on it is refined as the transposed problem theta_w^H V = W
-void qr_to_transposed(Task2& t) {
-  t.qr = 0;
-  t.tr = 1;
-  t.JM = t.Nt;
-  t.N = t.M;
-  t.Z = t.thw;
-  t.Z_lo = t.thw_lo;
-  t.JW = t.thw;
-  t.JV = t.V;
-  t.JR = t.JM;
-  t.jvec = 1;
-}
-
-// the two-site split of state h between sites s and s+1 with bond dims a | (b) | c
-void setup_split(const mps_state* h, Task2& t, int s, int a, int b, int c) {
-  const bool dd = h->prec == MPS_PREC_DD;
-  t = Task2{};
-  t.Bl = h->B[s];
-  t.Br = h->B[s + 1];
-  t.Bl_lo = dd ? h->Blo[s] : nullptr;
-  t.Br_lo = dd ? h->Blo[s + 1] : nullptr;
-  t.ldl = h->capx[s + 1];
-  t.ldr = h->capx[s + 2];
-  t.a = a;
-  t.b = b;
-  t.c = c;
-  t.M = 2 * a;
-  set_cols(t, 2 * c);
-  t.lamL = h->d_lam + (size_t)s * h->chi;
-  t.lamL_lo = dd ? h->d_lam_lo + (size_t)s * h->chi : nullptr;
-  t.lamS = h->d_lam + (size_t)(s + 1) * h->chi;
-  t.lamS_lo = dd ? h->d_lam_lo + (size_t)(s + 1) * h->chi : nullptr;
-  t.dim_out = h->d_dimx + s + 1;
-  t.chi = h->chi;
-  t.eps = h->eps;
-}
-
-// workspace of a gate's tasks (upper bound over the live dims: capacities)
-size_t gate_need_cap(bool dd, const mps_state* h, int first, int k) {
-  if (k == 2) return task_ws_bound(dd, 2 * h->capx[first], 2 * h->capx[first + 2], 0);
-  if (k == 3)
-    return task_ws_bound(dd, 2 * h->capx[first], 4 * h->capx[first + 3], 4 * h->capx[first] * h->capx[first + 2]) +
-           task_ws_bound(dd, 2 * h->capx[first + 1], 2 * h->capx[first + 3], 0);
-  return 0;
-}
-
-// ------------------------------------------------------------------ Jacobi sweeps
-// The FP64 Jacobi sweeps of one tick.  The iterating updates form groups that share
-// a step kernel configuration (block width, inner-sweep limit); each group's updates
-// are split into two halves, whose step launches run on the engine's stream and on
-// stream2.  One sweep = the column-order kernel for every update, then the steps of
-// the round-robin schedule.  An update whose previous sweep rotated nothing leaves
-// each of its blocks at once (the kernels read its rotation flags), so sweeps past
-// its convergence change nothing: a tick may run K sweeps and read the flags once.
-struct SweepGroup {
-  int bw = 8, inner_few = 1;
-  int na = 0, nb = 0;  // updates of the two halves
-  int oa = 0, ob = 0;  // their offsets in the sweep's half lists
-  int mNa = 0, mNb = 0;
-  bool split_a = false, split_b = false;
-};
-
-struct SweepPlan {
-  std::vector<SweepGroup> groups;
-  int n_order = 0;  // updates in the order list
-  bool two = false;
-  int K = 1;        // sweeps
-  mpsk::Ent* la[2] = {nullptr, nullptr};  // per sweep: half-a list, half-b list, order list
-  mpsk::Ent* lb[2] = {nullptr, nullptr};
-  mpsk::Ent* lo[2] = {nullptr, nullptr};
-  long long* phase = nullptr;  // debug stamps of one step (direct launches only)
-};
-
-int steps_of(int N, int bw) {
-  const int nb = (N + bw - 1) / bw;
-  return nb + (nb & 1) - 1;
-}
-
-int plan_steps(const SweepPlan& P) {
-  int m = 0;
-  for (const SweepGroup& g : P.groups) m = std::max(m, std::max(steps_of(g.mNa, g.bw), g.nb ? steps_of(g.mNb, g.bw) : 0));
-  return m;
-}
-
-// enqueue the plan's K sweeps on st (and stream2): also the body of a captured graph
-hipError_t enqueue_sweeps(Engine* E, Task2* dt, const SweepPlan& P, hipStream_t st) {
-  hipError_t e = hipSuccess;
-  const int nsteps = plan_steps(P);
-  for (int k = 0; k < P.K; ++k) {
-    e = mpsk::launch_jacobi_order(dt, P.lo[k], P.n_order, st);
-    if (e != hipSuccess) return e;
-    if (P.two) {
-      if ((e = hipEventRecord(E->ev_fork, st)) != hipSuccess) return e;
-      if ((e = hipStreamWaitEvent(E->stream2, E->ev_fork, 0)) != hipSuccess) return e;
-    }
-    for (int stp = 0; stp < nsteps; ++stp) {
-      for (const SweepGroup& g : P.groups) {
-        long long* pc = (P.phase && k == 0 && stp == nsteps / 2 && &g == &P.groups[0]) ? P.phase : nullptr;
-        if (g.na && stp < steps_of(g.mNa, g.bw)) {
-          e = (g.split_a && !pc)
-                  ? mpsk::launch_jacobi_split(dt, P.la[k] + g.oa, g.na, g.mNa, stp, E->tol_mult, E->max_inner,
-                                              g.inner_few, st)
-                  : mpsk::launch_jacobi_step(dt, P.la[k] + g.oa, g.na, g.mNa, g.bw, stp, E->tol_mult, E->max_inner,
-                                             g.inner_few, st, pc);
-          if (e != hipSuccess) return e;
-        }
-        if (g.nb && stp < steps_of(g.mNb, g.bw)) {
-          hipStream_t s2 = P.two ? E->stream2 : st;
-          e = g.split_b ? mpsk::launch_jacobi_split(dt, P.lb[k] + g.ob, g.nb, g.mNb, stp, E->tol_mult, E->max_inner,
-                                                    g.inner_few, s2)
-                        : mpsk::launch_jacobi_step(dt, P.lb[k] + g.ob, g.nb, g.mNb, g.bw, stp, E->tol_mult,
-                                                   E->max_inner, g.inner_few, s2, nullptr);
-          if (e != hipSuccess) return e;
-        }
-      }
-    }
-    if (P.two) {
-      if ((e = hipEventRecord(E->ev_join, E->stream2)) != hipSuccess) return e;
-      if ((e = hipStreamWaitEvent(st, E->ev_join, 0)) != hipSuccess) return e;
-    }
-  }
-  return hipSuccess;
-}
-
-// the plan's launch sequence as an instantiated graph (captured on first use and
-// kept while the engine lives); its shape and every device address it reads are
-// the key, the lists' contents are uploaded before each launch
-std::vector<long long> graph_key(const Engine* E, const Task2* dt, const SweepPlan& P) {
-  std::vector<long long> k = {P.K, P.two, P.n_order, (long long)(uintptr_t)dt, E->max_inner};
-  long long tol;
-  std::memcpy(&tol, &E->tol_mult, sizeof tol);
-  k.push_back(tol);
-  for (int i = 0; i < P.K; ++i)
-    for (const mpsk::Ent* l : {P.la[i], P.lb[i], P.lo[i]}) k.push_back((long long)(uintptr_t)l);
-  for (const SweepGroup& g : P.groups)
-    for (long long v : {g.bw, g.inner_few, g.na, g.nb, g.oa, g.ob, g.mNa, g.mNb, (int)g.split_a, (int)g.split_b})
-      k.push_back(v);
-  return k;
-}
-
-hipError_t launch_sweep_graph(Engine* E, Task2* dt, const SweepPlan& P, hipStream_t st) {
-  const std::vector<long long> key = graph_key(E, dt, P);
-  auto it = E->graphs.find(key);
-  if (it == E->graphs.end()) {
-    if (E->graphs.size() >= 256) {  // shapes come and go with the workload: start over
-      for (auto& kv : E->graphs) (void)hipGraphExecDestroy(kv.second);
-      E->graphs.clear();
-    }
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
-    if (e != hipSuccess) return e;
-    const hipError_t ec = enqueue_sweeps(E, dt, P, st);
-    e = hipStreamEndCapture(st, &g);
-    if (ec != hipSuccess) {
-      if (g) (void)hipGraphDestroy(g);
-      return ec;
-    }
-    if (e != hipSuccess) return e;
-    hipGraphExec_t x = nullptr;
-    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return e;
-    it = E->graphs.emplace(key, x).first;
-    ++E->graphs_built;
-  }
-  ++E->graph_launches;
-  return hipGraphLaunch(it->second, st);
-}
-
-// Runs `gates` on the states `U` of engine E.  d_dims / dims_total: one device range
-// covering every state's bond-dimension table; dims_off[u] = offset of state u's.
-int run_sched(Engine* E, const std::vector<mps_state*>& U, const int* d_dims, int dims_total,
-              const std::vector<int>& dims_off, const std::vector<GateRef>& gates, std::string* err) {
-  if (gates.empty()) return MPS_OK;
-  // a previous run that ended in an error may have left QR factorisations or dd work
-  // queued: let them drain before any slot, list or workspace is reused
-  HIPCHK(err, hipStreamSynchronize(E->stream3));
-  HIPCHK(err, hipStreamSynchronize(E->stream4));
-  const bool dd = E->prec == MPS_PREC_DD;
-  const int nu = (int)U.size();
-  std::vector<int> site_base(nu + 1, 0);
-  for (int u = 0; u < nu; ++u) site_base[u + 1] = site_base[u] + U[u]->n;
-  const int nsites = site_base[nu];
-  std::vector<std::vector<int>> queue(nu);
-  int n2 = 0, n3 = 0, par = 0;
-  size_t max_need = 0;
-  int capmax = 1;
-  for (int u = 0; u < nu; ++u) {
-    par += std::max(2, U[u]->n / 2 + 1);
-    for (int b = 0; b <= U[u]->n; ++b) capmax = std::max(capmax, U[u]->capx[b]);
-  }
-  for (size_t gi = 0; gi < gates.size(); ++gi) {
-    const GateRef& g = gates[gi];
-    queue[g.unit].push_back((int)gi);
-    n2 += g.k == 2;
-    n3 += g.k == 3;
-    max_need = std::max(max_need, gate_need_cap(dd, U[g.unit], g.first, g.k));
-  }
-  const int S = std::max(n3 ? 2 : 1, std::min(std::min(E->max_slots, par), std::max(1, n2 + 2 * n3)));
-  // standalone engines: every slot takes the same, largest workspace (no
-  // fragmentation); batch engines: each update takes what its shape needs
-  size_t uniform = 0, arena_bytes;
-  if (!E->batch) {
-    const int Mcap = 2 * capmax, Ncap = (n3 ? 4 : 2) * capmax;
-    uniform = task_ws_bound(dd, Mcap, Ncap, n3 ? 4 * capmax * capmax : 0);
-    arena_bytes = uniform * S;
-  } else {
-    arena_bytes = std::max(max_need, (size_t)std::min(E->ws_limit, (double)max_need * S));
-  }
-  int rc = ensure_ws(E, align_up(arena_bytes), err);
-  if (rc) return rc;
-  // small device / pinned areas
-  const size_t o_tasks = 0;
-  const size_t o_flags = align_up(sizeof(Task2) * S);
-  const size_t o_stats = o_flags + align_up(sizeof(int) * 3 * S);
-  const size_t o_fro = o_stats + align_up(sizeof(double) * 8 * S);
-  const size_t o_dims = o_fro + align_up(sizeof(double) * S);
-  const size_t o_u8 = o_dims + align_up(sizeof(int) * dims_total);
-  const size_t o_g1 = o_u8 + align_up(sizeof(double2) * 128 * S);
-  const size_t o_ents = o_g1 + align_up(sizeof(Task1) * nsites);
-  // new2, new3, jacobi (two halves + order, for each of two sweeps), dd, dd-enter,
-  // final, final3, mid, znorm, ref, polish, qr z, dd-enter QR tasks, and a ring of
-  // kQrRing lists of QR factorisations in flight
-  constexpr int kQrRing = 4;
-  constexpr int kLists = 18 + kQrRing;
-  const size_t list_bytes = align_up(sizeof(mpsk::Ent) * S);
-  rc = ensure_small(E, o_ents + kLists * list_bytes, err);
-  if (rc) return rc;
-  Task2* ht = (Task2*)(E->h_stage + o_tasks);
-  Task2* dt = (Task2*)(E->d_small + o_tasks);
-  int* d_flags = (int*)(E->d_small + o_flags);
-  int* hflags = (int*)(E->h_stage + o_flags);
-  double* d_stats = (double*)(E->d_small + o_stats);
-  double* hstats = (double*)(E->h_stage + o_stats);
-  double* d_fro = (double*)(E->d_small + o_fro);
-  int* hdims = (int*)(E->h_stage + o_dims);
-  double2* hu8 = (double2*)(E->h_stage + o_u8);
-  double2* du8 = (double2*)(E->d_small + o_u8);
-  enum { LN2 = 0, LN3, LJ, LD, LENTER, LFIN, LFIN3, LMID, LZN, LR, LPOL, LJ2, LJO, LQZ, LQL, LJ_1, LJ2_1, LJO_1, LQR0 };
-  auto hlist = [&](int i) { return E->h_stage + o_ents + i * list_bytes; };
-  auto dlist = [&](int i) { return E->d_small + o_ents + i * list_bytes; };
-
-  std::vector<Slot> slot(S);
-  std::vector<char> done(gates.size(), 0), busy(nsites, 0), claimed(nsites, 0);
-  std::vector<double> gstats(8 * gates.size(), 0.0);
-  std::vector<int> gsweeps(gates.size(), 0), gdd(gates.size(), 0);
-  std::vector<size_t> head(nu, 0);  // per state: first queue entry not yet admitted
-  size_t remaining = gates.size();
-  int status = MPS_OK;
-  int rot0 = 0;  // first state scanned at admission (rotates for fairness)
-  hipError_t e;
-  hipStream_t st = E->stream;
-  // the dd work's stream; its launches follow everything queued on st so far (fork)
-  // and st waits for them before reading flags back (join)
-  hipStream_t sd = (dd && E->dd_stream) ? E->stream4 : st;
-  bool sd_pending = false;
-  auto fork_dd = [&]() -> hipError_t {
-    if (sd == st) return hipSuccess;
-    hipError_t ee = hipEventRecord(E->ev_dd_fork, st);
-    if (ee == hipSuccess) ee = hipStreamWaitEvent(sd, E->ev_dd_fork, 0);
-    sd_pending = true;
-    return ee;
-  };
-  auto join_dd = [&]() -> hipError_t {
-    if (!sd_pending) return hipSuccess;
-    sd_pending = false;
-    hipError_t ee = hipEventRecord(E->ev_dd_join, sd);
-    if (ee == hipSuccess) ee = hipStreamWaitEvent(st, E->ev_dd_join, 0);
-    return ee;
-  };
-  int dirty_lo = S, dirty_hi = -1;  // task descriptors changed since the last upload
-  auto mark = [&](int si) { dirty_lo = std::min(dirty_lo, si); dirty_hi = std::max(dirty_hi, si); };
-  auto upload_tasks = [&]() -> hipError_t {
-    if (dirty_hi < dirty_lo) return hipSuccess;
-    hipError_t ee = hipMemcpyAsync(dt + dirty_lo, ht + dirty_lo, sizeof(Task2) * (dirty_hi - dirty_lo + 1),
-                                   hipMemcpyHostToDevice, st);
-    dirty_lo = S;
-    dirty_hi = -1;
-    return ee;
-  };
-
-  auto upload_list = [&](int li, const std::vector<mpsk::Ent>& ents) -> mpsk::Ent* {
-    mpsk::Ent* hl = (mpsk::Ent*)hlist(li);
-    for (size_t i = 0; i < ents.size(); ++i) hl[i] = ents[i];
-    hipError_t ee = hipMemcpyAsync(dlist(li), hl, sizeof(mpsk::Ent) * ents.size(), hipMemcpyHostToDevice, st);
-    return ee == hipSuccess ? (mpsk::Ent*)dlist(li) : nullptr;
-  };
-  auto ents_of = [&](const std::vector<int>& sl) {
-    std::vector<mpsk::Ent> v;
-    v.reserve(sl.size());
-    for (int si : sl) v.push_back(mpsk::Ent{si, slot[si].sweep});
-    return v;
-  };
-  // the FP64 sweeps of the iterating slots `jl` (K of them), as stream launches or
-  // as a replayed graph
-  auto launch_jacobi = [&](const std::vector<int>& jl, int K) -> hipError_t {
-    SweepPlan P;
-    P.K = K;
-    P.two = E->jacobi_streams == 2 && jl.size() >= 2;
-    P.n_order = (int)jl.size();
-    // groups by step kernel configuration, in order of first appearance
-    std::vector<std::vector<int>> ga, gb;
-    std::vector<std::pair<int, int>> cfgs;
-    for (int si : jl) {
-      const std::pair<int, int> c{slot[si].bw, slot[si].inner_few};
-      size_t gi = 0;
-      while (gi < cfgs.size() && cfgs[gi] != c) ++gi;
-      if (gi == cfgs.size()) {
-        cfgs.push_back(c);
-        ga.emplace_back();
-        gb.emplace_back();
-      }
-      // alternate updates of a group go to the two halves
-      ((P.two && ((ga[gi].size() + gb[gi].size()) & 1)) ? gb[gi] : ga[gi]).push_back(si);
-    }
-    std::vector<int> all_a, all_b;
-    for (size_t gi = 0; gi < cfgs.size(); ++gi) {
-      SweepGroup g;
-      g.bw = cfgs[gi].first;
-      g.inner_few = cfgs[gi].second;
-      g.na = (int)ga[gi].size();
-      g.nb = (int)gb[gi].size();
-      g.oa = (int)all_a.size();
-      g.ob = (int)all_b.size();
-      for (int si : ga[gi]) g.mNa = std::max(g.mNa, slot[si].N);
-      for (int si : gb[gi]) g.mNb = std::max(g.mNb, slot[si].N);
-      g.split_a = g.bw == 8 && g.na <= E->split_max;
-      g.split_b = g.bw == 8 && g.nb <= E->split_max;
-      all_a.insert(all_a.end(), ga[gi].begin(), ga[gi].end());
-      all_b.insert(all_b.end(), gb[gi].begin(), gb[gi].end());
-      P.groups.push_back(g);
-    }
-    const int lists[2][3] = {{LJ, LJ2, LJO}, {LJ_1, LJ2_1, LJO_1}};
-    for (int k = 0; k < K; ++k) {
-      auto with_sweep = [&](const std::vector<int>& v) {
-        std::vector<mpsk::Ent> out = ents_of(v);
-        for (mpsk::Ent& x : out) x.sweep += k;
-        return out;
-      };
-      P.la[k] = upload_list(lists[k][0], with_sweep(all_a));
-      P.lb[k] = all_b.empty() ? P.la[k] : upload_list(lists[k][1], with_sweep(all_b));
-      P.lo[k] = upload_list(lists[k][2], with_sweep(jl));
-      if (!P.la[k] || !P.lb[k] || !P.lo[k]) return hipErrorInvalidValue;
-    }
-    P.phase = E->d_phase;
-    Timed tm(E, 1, K * plan_steps(P));
-    if (E->graphs_on && !E->d_phase) return launch_sweep_graph(E, dt, P, st);
-    return enqueue_sweeps(E, dt, P, st);
-  };
-  std::vector<int> free_list;  // free slot indices, lowest last
-  for (int si = S - 1; si >= 0; --si) free_list.push_back(si);
-  auto take_slot = [&]() {
-    const int si = free_list.back();
-    free_list.pop_back();
-    return si;
-  };
-  auto release_slot = [&](int si) {
-    if (slot[si].ws_len) E->arena.release(slot[si].ws_off, slot[si].ws_len);
-    slot[si] = Slot{};
-    free_list.push_back(si);
-  };
-  auto ws_alloc = [&](size_t need, size_t& off) {
-    const size_t len = align_up(uniform ? uniform : need);
-    off = E->arena.alloc(len);
-    return off == SIZE_MAX ? (size_t)0 : len;
-  };
-  std::vector<int> active;  // slots not free
-
-  bool unsynced = false;  // async copies from the pinned staging may still be pending
-  // QR factorisations in flight on stream3, oldest first: completion event, list ring
-  // slot, the slots waiting (state 6); polled at the end of each tick, so that a
-  // factorisation longer than a sweep does not hold up the other updates' sweeps
-  struct QrBatch {
-    hipEvent_t ev;
-    std::vector<int> slots;
-  };
-  std::deque<QrBatch> qr_inflight;
-  int qr_ring = 0;
-  auto qr_poll = [&](bool block) -> hipError_t {
-    while (!qr_inflight.empty()) {
-      QrBatch& b = qr_inflight.front();
-      const hipError_t q = block ? hipEventSynchronize(b.ev) : hipEventQuery(b.ev);
-      if (q == hipErrorNotReady) break;
-      if (q != hipSuccess) return q;
-      for (int si : b.slots)
-        if (slot[si].state == 6) slot[si].state = 1;
-      E->evpool.push_back(b.ev);
-      qr_inflight.pop_front();
-      if (block) block = false;  // one finished batch is progress enough
-    }
-    return hipSuccess;
-  };
-  while (true) {
-    // the staging buffers are rewritten below: wait for copies a previous tick left
-    if (unsynced) {
-      HIPCHK(err, hipStreamSynchronize(st));
-      unsynced = false;
-    }
-    // ---- 1. admission
-    std::vector<int> new2, new3;
-    std::vector<Task1> g1;
-    long g1_maxel = 0;
-    std::fill(claimed.begin(), claimed.end(), 0);
-    for (int uu = 0; uu < nu && remaining; ++uu) {
-      const int u = (rot0 + uu) % nu;
-      const mps_state* h = U[u];
-      const int sb0 = site_base[u];
-      std::vector<int>& qu = queue[u];
-      while (head[u] < qu.size() && done[qu[head[u]]]) ++head[u];
-      int blocked = 0;  // sites of this state that no later gate may use this tick
-      for (int q = 0; q < h->n; ++q) blocked += busy[sb0 + q];
-      const size_t window = (size_t)4 * h->n + 16;
-      for (size_t qi = head[u]; qi < qu.size() && qi < head[u] + window && blocked < h->n; ++qi) {
-        const int gi = qu[qi];
-        if (done[gi]) continue;
-        const GateRef& g = gates[gi];
-        bool free_ = true;
-        for (int q = g.first; q < g.first + g.k; ++q) free_ &= !busy[sb0 + q] && !claimed[sb0 + q];
-        if (free_ && g.k == 1) {
-          Task1 t{};
-          t.B = h->B[g.first];
-          t.B_lo = dd ? h->Blo[g.first] : nullptr;
-          t.ld = h->capx[g.first + 1];
-          t.a = h->dimx[g.first];
-          t.b = h->dimx[g.first + 1];
-          for (int q = 0; q < 4; ++q) {
-            t.U[q] = make_double2(g.U[2 * q], g.U[2 * q + 1]);
-            t.U_lo[q] = (dd && g.Ulo) ? make_double2(g.Ulo[2 * q], g.Ulo[2 * q + 1]) : make_double2(0, 0);
-          }
-          g1.push_back(t);
-          g1_maxel = std::max(g1_maxel, (long)t.a * t.b);
-          done[gi] = 1;
-          --remaining;
-          claimed[sb0 + g.first] = 1;  // later gates on this site wait for the next tick
-          ++blocked;
-          continue;
-        }
-        const int s0 = g.first;
-        bool admitted = false;
-        if (free_ && (int)free_list.size() >= (g.k == 3 ? 2 : 1)) {
-          size_t off1 = 0, off2 = 0, len1 = 0, len2 = 0;
-          if (g.k == 2) {
-            len1 = ws_alloc(task_ws_bytes(dd, 2 * h->dimx[s0], 2 * h->dimx[s0 + 2], 0), off1);
-          } else {
-            const int a = h->dimx[s0], c = h->dimx[s0 + 2], d = h->dimx[s0 + 3];
-            len1 = ws_alloc(task_ws_bytes(dd, 2 * a, 4 * d, 4 * a * c), off1);
-            if (len1) {
-              len2 = ws_alloc(task_ws_bound(dd, 2 * h->capx[s0 + 1], 2 * d, 0), off2);
-              if (!len2) {
-                E->arena.release(off1, len1);
-                len1 = 0;
-              }
-            }
-          }
-          if (len1) {
-            admitted = true;
-            const int si = take_slot();
-            Slot& sl = slot[si];
-            sl = Slot{};
-            sl.state = 1;
-            sl.gate = gi;
-            sl.ws_off = off1;
-            sl.ws_len = len1;
-            Task2& t = ht[si];
-            setup_split(h, t, s0, h->dimx[s0], h->dimx[s0 + 1], h->dimx[s0 + 2]);
-            if (g.k == 2) {
-              for (int q = 0; q < 16; ++q) {
-                t.U[q] = make_double2(g.U[2 * q], g.U[2 * q + 1]);
-                t.U_lo[q] = (dd && g.Ulo) ? make_double2(g.Ulo[2 * q], g.Ulo[2 * q + 1]) : make_double2(0, 0);
-              }
-              new2.push_back(si);
-            } else {
-              t.B3 = h->B[s0 + 2];
-              t.B3_lo = dd ? h->Blo[s0 + 2] : nullptr;
-              t.ld3 = h->capx[s0 + 3];
-              t.d = h->dimx[s0 + 3];
-              set_cols(t, 4 * t.d);
-              double2* u8h = hu8 + 128 * si;
-              for (int q = 0; q < 64; ++q) {
-                u8h[q] = make_double2(g.U[2 * q], g.U[2 * q + 1]);
-                u8h[64 + q] = (dd && g.Ulo) ? make_double2(g.Ulo[2 * q], g.Ulo[2 * q + 1]) : make_double2(0, 0);
-              }
-              t.U8 = du8 + 128 * si;
-              t.U8_lo = du8 + 128 * si + 64;
-              sl.kind = 1;
-              const int sb = take_slot();
-              slot[sb] = Slot{};
-              slot[sb].state = 5;
-              slot[sb].kind = 2;
-              slot[sb].gate = gi;
-              slot[sb].ws_off = off2;
-              slot[sb].ws_len = len2;
-              sl.partner = sb;
-              active.push_back(sb);
-              new3.push_back(si);
-            }
-            carve(dd, t, E->ws + off1, d_flags, d_stats, d_fro, si);
-            const StepCfg cfg = step_cfg(E, t.N);
-            sl.bw = cfg.bw;
-            sl.inner_few = cfg.inner_few;
-            if (g.k == 2 && cfg.qr) qr_select(dd, t);
-            if (t.qr) sl.state = 6;  // waits one tick for its QR factorisation
-            mark(si);
-            sl.M = t.M;
-            sl.N = t.N;
-            sl.Nt = t.Nt;
-            sl.JM = t.JM;
-            active.push_back(si);
-            for (int q = g.first; q < g.first + g.k; ++q) busy[sb0 + q] = 1;
-            done[gi] = 1;
-            --remaining;
-          }
-        }
-        if (!admitted)
-          for (int q = g.first; q < g.first + g.k; ++q) {
-            blocked += !claimed[sb0 + q] && !busy[sb0 + q];
-            claimed[sb0 + q] = 1;
-          }
-        else
-          blocked += g.k;
-      }
-    }
-    rot0 = nu ? (rot0 + 1) % nu : 0;
-    if (!g1.empty()) {
-      Task1* h1 = (Task1*)(E->h_stage + o_g1);
-      std::memcpy(h1, g1.data(), sizeof(Task1) * g1.size());
-      HIPCHK(err, hipMemcpyAsync(E->d_small + o_g1, h1, sizeof(Task1) * g1.size(), hipMemcpyHostToDevice, st));
-      unsynced = true;
-      Timed tm(E, 4);
-      e = dd ? mpsk::launch_gate1_dd((Task1*)(E->d_small + o_g1), (int)g1.size(), g1_maxel, st)
-             : mpsk::launch_gate1((Task1*)(E->d_small + o_g1), (int)g1.size(), g1_maxel, st);
-      if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("gate1: ") + hipGetErrorString(e));
-    }
-    if (!new2.empty() || !new3.empty()) {
-      HIPCHK(err, upload_tasks());
-      if (!new3.empty())
-        for (int si : new3)
-          HIPCHK(err, hipMemcpyAsync(du8 + 128 * si, hu8 + 128 * si, sizeof(double2) * 128, hipMemcpyHostToDevice, st));
-      unsynced = true;
-      for (int which = 0; which < 2; ++which) {
-        Timed tm(E, 0);
-        const std::vector<int>& nl = which ? new3 : new2;
-        if (nl.empty()) continue;
-        mpsk::Ent* el = upload_list(which ? LN3 : LN2, ents_of(nl));
-        if (!el) return fail(err, MPS_EDEVICE, "list upload failed");
-        int mM = 0, mN = 0, mNt = 0, mA = 0, mC = 0, mD = 0;
-        for (int si : nl) {
-          mM = std::max(mM, slot[si].M);
-          mN = std::max(mN, slot[si].N);
-          mNt = std::max(mNt, slot[si].Nt);
-          mA = std::max(mA, ht[si].a);
-          mC = std::max(mC, ht[si].c);
-          mD = std::max(mD, ht[si].d);
-        }
-        e = mpsk::launch_prep2(dt, el, (int)nl.size(), mN, st);
-        if (e == hipSuccess) {
-          if (which)
-            e = mpsk::launch_theta3(dt, el, (int)nl.size(), mA, mC, mD, dd, st);
-          else
-            e = dd ? mpsk::launch_theta2_dd(dt, el, (int)nl.size(), mM, mNt, st)
-                   : mpsk::launch_theta2(dt, el, (int)nl.size(), mM, mNt, st);
-        }
-        if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("theta: ") + hipGetErrorString(e));
-        std::vector<int> qrs;
-        for (int si : nl)
-          if (ht[si].qr) qrs.push_back(si);
-        if (!qrs.empty()) {  // on stream3 after the theta kernels, with a list of its own
-          if ((int)qr_inflight.size() >= kQrRing) HIPCHK(err, qr_poll(true));  // frees the oldest ring slot
-          mpsk::Ent* eq = upload_list(LQR0 + qr_ring, ents_of(qrs));
-          if (!eq) return fail(err, MPS_EDEVICE, "list upload failed");
-          qr_ring = (qr_ring + 1) % kQrRing;
-          HIPCHK(err, hipEventRecord(E->ev_qr, st));
-          HIPCHK(err, hipStreamWaitEvent(E->stream3, E->ev_qr, 0));
-          e = mpsk::launch_qr_factor(dt, eq, (int)qrs.size(), mM, mN, E->stream3);
-          if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("qr: ") + hipGetErrorString(e));
-          hipEvent_t done = ev_get(E);
-          if (!done) return fail(err, MPS_EDEVICE, "event creation failed");
-          HIPCHK(err, hipEventRecord(done, E->stream3));
-          qr_inflight.push_back(QrBatch{done, qrs});
-        }
-      }
-    }
-    // ---- 2. one sweep for every iterating slot (QR-pending slots wait)
-    std::vector<int> jl, rl, dl;
-    for (int si : active) {
-      if (slot[si].state == 1) jl.push_back(si);
-      if (slot[si].state == 2) rl.push_back(si);
-      if (slot[si].state == 4) dl.push_back(si);
-    }
-    if (jl.empty() && rl.empty() && dl.empty() && qr_inflight.empty()) {
-      if (active.empty()) {
-        if (!remaining) break;
-        continue;  // only single-site gates were admitted; admit the rest
-      }
-    }
-    // dd refinement passes and polish sweeps first, on the dd stream, so that they
-    // overlap the FP64 sweeps launched below
-    if (!rl.empty() || !dl.empty()) {
-      mpsk::Ent* elr = rl.empty() ? nullptr : upload_list(LR, ents_of(rl));
-      mpsk::Ent* eld = dl.empty() ? nullptr : upload_list(LD, ents_of(dl));
-      if ((!rl.empty() && !elr) || (!dl.empty() && !eld)) return fail(err, MPS_EDEVICE, "list upload failed");
-      HIPCHK(err, fork_dd());
-      if (!rl.empty()) {
-        int mM = 0, mN = 0;
-        for (int si : rl) { mM = std::max(mM, slot[si].JM); mN = std::max(mN, slot[si].N); }
-        Timed tm(E, 6, 1, sd);
-        E->slot_sweeps_dd += (long)rl.size();
-        e = mpsk::launch_ddref_pass(dt, elr, (int)rl.size(), mM, mN, E->tol_mult, sd);
-        if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("dd refinement: ") + hipGetErrorString(e));
-      }
-      if (!dl.empty()) {
-        int mN = 0;
-        for (int si : dl) mN = std::max(mN, slot[si].N);
-        const int nb = (mN + 7) / 8;
-        const int nsteps = nb + (nb & 1) - 1;
-        Timed tm(E, 6, nsteps, sd);
-        E->slot_sweeps_dd += (long)dl.size();
-        for (int stp = 0; stp < nsteps; ++stp) {
-          e = mpsk::launch_jacobi_step_dd(dt, eld, (int)dl.size(), mN, stp, E->tol_mult, E->max_inner, sd);
-          if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("dd jacobi: ") + hipGetErrorString(e));
-        }
-      }
-    }
-    int K = 1;  // sweeps this tick
-    if (!jl.empty()) {
-      K = std::max(1, std::min(2, E->tick_sweeps));
-      for (int si : jl) K = std::min(K, E->max_sweeps - slot[si].sweep);
-      K = std::max(K, 1);
-      HIPCHK(err, launch_jacobi(jl, K));
-    }
-    // finished QR factorisations: their slots start iterating at the next tick; when
-    // this tick has no sweep work at all, wait for the oldest
-    HIPCHK(err, qr_poll(jl.empty() && rl.empty() && dl.empty()));
-    // ---- 3. convergence
-    HIPCHK(err, join_dd());
-    if (!jl.empty() || !rl.empty() || !dl.empty()) {
-      HIPCHK(err, hipMemcpyAsync(hflags, d_flags, sizeof(int) * 3 * S, hipMemcpyDeviceToHost, st));
-      HIPCHK(err, hipStreamSynchronize(st));
-      unsynced = false;
-      if (E->d_phase && !jl.empty()) {
-        long long pc[5];
-        HIPCHK(err, hipMemcpy(pc, E->d_phase, sizeof(pc), hipMemcpyDeviceToHost));
-        // wall_clock64 runs at 100 MHz on gfx950
-        std::fprintf(stderr, "[mps] step phases (us, %zu updates, N %d): gram %.1f inner %.1f update %.1f rot %lld\n",
-                     jl.size(), slot[jl[0]].N, (pc[1] - pc[0]) * 0.01, (pc[2] - pc[1]) * 0.01, (pc[3] - pc[2]) * 0.01,
-                     pc[4]);
-      }
-    }
-    std::vector<int> enter;
-    for (int si : jl) {
-      Slot& sl = slot[si];
-      // the tick's K sweeps: the first without a rotation ends the iteration (the
-      // sweeps after it left the update untouched)
-      bool rot = true;
-      for (int k = 0; k < K && rot; ++k) {
-        rot = hflags[3 * si + sl.sweep % 3] != 0;
-        ++sl.sweep;
-        ++E->slot_sweeps;
-      }
-      if (!rot || sl.sweep >= E->max_sweeps) {
-        sl.fp64_sweeps = sl.sweep;
-        sl.fp64_conv = !rot;
-        if (dd) {
-          enter.push_back(si);
-          sl.state = E->dd_refine ? 2 : 4;
-          sl.sweep = 0;
-        } else {
-          sl.conv = sl.fp64_conv;
-          sl.state = 3;
-        }
-      }
-    }
-    std::vector<int> to_polish;
-    for (int si : rl) {
-      Slot& sl = slot[si];
-      const int code = hflags[3 * si + sl.sweep % 3];
-      ++sl.sweep;
-      if (code == 0) {
-        sl.dd_sweeps = sl.sweep;
-        sl.conv = true;
-        sl.state = 3;
-      } else if ((code & 2) || sl.sweep >= E->max_ref_passes) {
-        sl.dd_sweeps = sl.sweep;
-        sl.state = 4;
-        sl.sweep = 0;
-        to_polish.push_back(si);
-      }
-    }
-    for (int si : dl) {
-      Slot& sl = slot[si];
-      const bool rot = hflags[3 * si + sl.sweep % 3] != 0;
-      ++sl.sweep;
-      if (!rot || sl.sweep >= E->max_sweeps_dd) {
-        sl.dd_sweeps += sl.sweep;
-        sl.conv = !rot;
-        sl.state = 3;
-      }
-    }
-    if (!to_polish.empty()) {
-      unsynced = true;
-      mpsk::Ent* el = upload_list(LPOL, ents_of(to_polish));
-      if (!el) return fail(err, MPS_EDEVICE, "list upload failed");
-      HIPCHK(err, fork_dd());
-      e = mpsk::launch_flags_clear(dt, el, (int)to_polish.size(), sd);
-      if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("flags: ") + hipGetErrorString(e));
-    }
-    if (!enter.empty()) {
-      unsynced = true;
-      mpsk::Ent* el = upload_list(LENTER, ents_of(enter));
-      if (!el) return fail(err, MPS_EDEVICE, "list upload failed");
-      // QR-preconditioned tasks: V <- Q V_x, then the refinement of the transposed
-      // problem (square thetas: the shapes stay the same).  The descriptors are
-      // converted first; the Q application reads none of the converted fields, so it
-      // and the promotion both follow the upload on the dd stream.
-      std::vector<int> qrl;
-      int qN = 0;
-      for (int si : enter)
-        if (ht[si].qr) {
-          qrl.push_back(si);
-          qN = std::max(qN, ht[si].N);
-        }
-      mpsk::Ent* eql = nullptr;
-      if (!qrl.empty()) {
-        eql = upload_list(LQL, ents_of(qrl));
-        if (!eql) return fail(err, MPS_EDEVICE, "list upload failed");
-        for (int si : qrl) {
-          qr_to_transposed(ht[si]);
-          slot[si].JM = ht[si].JM;
-          slot[si].N = ht[si].N;
-          mark(si);
-        }
-        HIPCHK(err, upload_tasks());
-      }
-      int mM = 0, mN = 0;
-      for (int si : enter) { mM = std::max(mM, slot[si].JM); mN = std::max(mN, slot[si].N); }
-      HIPCHK(err, fork_dd());
-      if (eql) {
-        Timed tq(E, 6, 1, sd);
-        e = mpsk::launch_qr_left(dt, eql, (int)qrl.size(), qN, sd);
-        if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("qr left: ") + hipGetErrorString(e));
-      }
-      Timed tm(E, 6, 1, sd);
-      e = mpsk::launch_dd_enter(dt, el, (int)enter.size(), mM, mN, sd);
-      if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("dd enter: ") + hipGetErrorString(e));
-    }
-    // ---- 4. finalise converged slots
-    std::vector<int> fl, fl2, fl3;
-    for (int si : active)
-      if (slot[si].state == 3) {
-        fl.push_back(si);
-        (slot[si].kind == 1 ? fl3 : fl2).push_back(si);
-      }
-    if (!fl.empty()) {
-      mpsk::Ent* el = upload_list(LFIN, ents_of(fl));
-      if (!el) return fail(err, MPS_EDEVICE, "list upload failed");
-      {
-        Timed tm(E, 2);
-        e = dd ? mpsk::launch_truncate_dd(dt, el, (int)fl.size(), E->rank_floor_dd, st)
-               : mpsk::launch_truncate(dt, el, (int)fl.size(), E->rank_floor, st);
-        if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("truncate: ") + hipGetErrorString(e));
-      }
-      {
-        std::vector<int> zl;
-        int zJM = 0, zK = 1;
-        for (int si : fl)
-          if (ht[si].tr) {
-            zl.push_back(si);
-            zJM = std::max(zJM, ht[si].JM);
-            zK = std::max(zK, std::min(ht[si].chi, ht[si].N));
-          }
-        if (!zl.empty()) {
-          mpsk::Ent* ez = upload_list(LZN, ents_of(zl));
-          if (!ez) return fail(err, MPS_EDEVICE, "list upload failed");
-          Timed tz(E, 3);
-          e = dd ? mpsk::launch_znorm_dd(dt, ez, (int)zl.size(), zJM, zK, st)
-                 : mpsk::launch_znorm(dt, ez, (int)zl.size(), zJM, zK, st);
-          if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("znorm: ") + hipGetErrorString(e));
-        }
-        std::vector<int> ql;  // FP64 tasks preconditioned by QR: Z from W's columns
-        int qN = 0, qK = 1;
-        for (int si : fl)
-          if (ht[si].qr) {
-            ql.push_back(si);
-            qN = std::max(qN, ht[si].N);
-            qK = std::max(qK, std::min(ht[si].chi, ht[si].N));
-          }
-        if (!ql.empty()) {
-          mpsk::Ent* eq = upload_list(LQZ, ents_of(ql));
-          if (!eq) return fail(err, MPS_EDEVICE, "list upload failed");
-          Timed tz(E, 3);
-          e = mpsk::launch_qr_z(dt, eq, (int)ql.size(), qN, qK, st);
-          if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("qr z: ") + hipGetErrorString(e));
-        }
-      }
-      {
-        Timed tm(E, 3);
-        for (int which = 0; which < 2; ++which) {
-          const std::vector<int>& ll = which ? fl3 : fl2;
-          if (ll.empty()) continue;
-          mpsk::Ent* e2 = which ? upload_list(LFIN3, ents_of(ll)) : upload_list(LMID, ents_of(ll));
-          if (!e2) return fail(err, MPS_EDEVICE, "list upload failed");
-          int lM = 0, lN = 0, maxK = 1;
-          for (int si : ll) {
-            lM = std::max(lM, slot[si].M);
-            lN = std::max(lN, slot[si].Nt);
-            maxK = std::max(maxK, std::min(ht[si].chi, std::min(slot[si].M, slot[si].N)));
-          }
-          e = dd ? mpsk::launch_split_dd(dt, e2, (int)ll.size(), lM, lN, maxK, st, which == 0)
-                 : mpsk::launch_split(dt, e2, (int)ll.size(), lM, lN, maxK, st, which == 0);
-          if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("split: ") + hipGetErrorString(e));
-        }
-      }
-      HIPCHK(err, hipMemcpyAsync(hstats, d_stats, sizeof(double) * 8 * S, hipMemcpyDeviceToHost, st));
-      HIPCHK(err, hipMemcpyAsync(hdims, d_dims, sizeof(int) * dims_total, hipMemcpyDeviceToHost, st));
-      HIPCHK(err, hipStreamSynchronize(st));
-      unsynced = false;
-      for (int u = 0; u < nu; ++u) std::memcpy(U[u]->dimx.data(), hdims + dims_off[u], sizeof(int) * (U[u]->n + 1));
-      // first splits of three-site gates: the second split takes over in the reserved slot
-      std::vector<mpsk::Ent> mids;
-      std::vector<int> newB;
-      int mN1 = 0, mK1 = 0, mNB = 0;
-      for (int si : fl3) {
-        Slot& sa = slot[si];
-        const GateRef& g = gates[sa.gate];
-        const mps_state* h = U[g.unit];
-        const int s0 = g.first, sb = sa.partner;
-        Task2& tb = ht[sb];
-        setup_split(h, tb, s0 + 1, h->dimx[s0 + 1], 0, h->dimx[s0 + 3]);
-        carve(dd, tb, E->ws + slot[sb].ws_off, d_flags, d_stats, d_fro, sb);
-        mark(sb);
-        Slot& sbl = slot[sb];
-        sbl.state = 1;
-        sbl.sweep = 0;
-        sbl.M = tb.M;
-        sbl.N = tb.N;
-        const StepCfg cfg = step_cfg(E, tb.N);
-        sbl.bw = cfg.bw;
-        sbl.inner_few = cfg.inner_few;
-        sbl.Nt = tb.Nt;
-        sbl.JM = tb.JM;
-        gsweeps[sa.gate] = sa.fp64_sweeps;
-        gdd[sa.gate] = sa.dd_sweeps;
-        if (!sa.conv) {
-          status = MPS_ENOCONV;
-          ++E->noconv_updates;
-        }
-        mids.push_back(mpsk::Ent{si, sb});
-        newB.push_back(sb);
-        mN1 = std::max(mN1, sa.Nt);
-        mK1 = std::max(mK1, std::min(h->chi, sa.M));
-        mNB = std::max(mNB, tb.N);
-      }
-      if (!mids.empty()) {
-        HIPCHK(err, upload_tasks());
-        unsynced = true;
-        mpsk::Ent* eb = upload_list(LN2, ents_of(newB));
-        mpsk::Ent* em = upload_list(LN3, mids);
-        if (!eb || !em) return fail(err, MPS_EDEVICE, "list upload failed");
-        {
-          Timed tm(E, 0);
-          e = mpsk::launch_prep2(dt, eb, (int)newB.size(), mNB, st);
-          if (e == hipSuccess) e = mpsk::launch_mid3(dt, em, (int)mids.size(), mN1, mK1, dd, st);
-          if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("mid: ") + hipGetErrorString(e));
-        }
-      }
-      // a released slot's workspace is reused only by launches queued after the
-      // kernels that still read it (one stream)
-      for (int si : fl3) release_slot(si);
-      for (int si : fl2) {
-        Slot& sl = slot[si];
-        const GateRef& g = gates[sl.gate];
-        std::memcpy(&gstats[8 * sl.gate], hstats + 8 * si, sizeof(double) * 8);
-        gsweeps[sl.gate] = std::max(gsweeps[sl.gate], sl.fp64_sweeps);
-        gdd[sl.gate] = std::max(gdd[sl.gate], sl.dd_sweeps);
-        if (!sl.conv) {
-          status = MPS_ENOCONV;
-          ++E->noconv_updates;
-        }
-        if (E->debug_sweeps)
-          std::fprintf(stderr, "[mps] update at state %d site %d (M %d, N %d, kind %d): %d FP64 sweeps, %d dd sweeps\n",
-                       g.unit, g.first, sl.M, sl.N, sl.kind, sl.fp64_sweeps, sl.dd_sweeps);
-        for (int q = g.first; q < g.first + g.k; ++q) busy[site_base[g.unit] + q] = 0;
-        release_slot(si);
-      }
-      active.erase(std::remove_if(active.begin(), active.end(), [&](int si) { return slot[si].state == 0; }),
-                   active.end());
-    }
-  }
-  HIPCHK(err, join_dd());
-  HIPCHK(err, hipStreamSynchronize(st));
-  for (QrBatch& b : qr_inflight) {  // (none is left once every slot has finished)
-    HIPCHK(err, hipEventSynchronize(b.ev));
-    E->evpool.push_back(b.ev);
-  }
-  qr_inflight.clear();
-  harvest_timing(E);
-  // per state: diagnostics of its last multi-site gate in queue order
-  for (int u = 0; u < nu; ++u) {
-    mps_state* h = U[u];
-    for (size_t qi = queue[u].size(); qi-- > 0;) {
-      const int gi = queue[u][qi];
-      if (gates[gi].k == 1) continue;
-      const double* sv = &gstats[8 * gi];
-      h->last = mps_update_stats{};
-      h->last.W = sv[0];
-      h->last.w = sv[1];
-      h->last.gap = sv[2];
-      h->last.epsdist = sv[3];
-      h->last.k = (int)sv[4];
-      h->last.rank = (int)sv[5];
-      for (int gj : queue[u]) {
-        h->last.sweeps = std::max(h->last.sweeps, gsweeps[gj]);
-        h->last.dd_sweeps = std::max(h->last.dd_sweeps, gdd[gj]);
-      }
-      h->last.splits = gates[gi].k - 1;
-      break;
-    }
-  }
-  if (status) return fail(err, status, "Jacobi sweep limit reached");
-  return MPS_OK;
-}
-
-int run_state(mps_state* h, const std::vector<GateRef>& gates) {
-  return run_sched(h->E, {h}, h->d_dimx, h->n + 1, {0}, gates, &h->err);
-}
-
-int set_option(Engine* E, int prec, int key, double value, std::string* err) {
-  switch (key) {
-    case MPS_OPT_MAX_SWEEPS:
-      if (!(value >= 1 && value <= 1000)) return fail(err, MPS_EINVAL, "max_sweeps out of range");
-      E->max_sweeps = (int)value;
-      E->max_sweeps_dd = (int)value;
-      return MPS_OK;
-    case MPS_OPT_JACOBI_TOL:
-      if (!(value > 0 && value <= 1e6)) return fail(err, MPS_EINVAL, "jacobi tol out of range");
-      E->tol_mult = value;
-      return MPS_OK;
-    case MPS_OPT_KERNEL_TIMING:
-      E->timing = value != 0;
-      return MPS_OK;
-    case MPS_OPT_BLOCK_WIDTH:
-      if (!(value == 4 || value == 8 || value == 16)) return fail(err, MPS_EINVAL, "block width must be 4, 8 or 16");
-      E->block_width = (int)value;
-      E->tuned = false;
-      return MPS_OK;
-    case MPS_OPT_MAX_INNER:
-      if (!(value >= 1 && value <= 64)) return fail(err, MPS_EINVAL, "inner sweep limit out of range");
-      E->max_inner = (int)value;
-      return MPS_OK;
-    case MPS_OPT_MAX_INNER_FEW:
-      if (!(value >= 1 && value <= 64)) return fail(err, MPS_EINVAL, "inner sweep limit out of range");
-      E->max_inner_few = (int)value;
-      E->tuned = false;
-      return MPS_OK;
-    case MPS_OPT_RANK_FLOOR:
-      if (!(value >= 0 && value < 1)) return fail(err, MPS_EINVAL, "rank floor out of range");
-      if (prec == MPS_PREC_DD) E->rank_floor_dd = value; else E->rank_floor = value;
-      return MPS_OK;
-    case MPS_OPT_MAX_SLOTS:
-      if (!(value >= 1 && value <= 65536)) return fail(err, MPS_EINVAL, "slot limit out of range");
-      E->max_slots = (int)value;
-      return MPS_OK;
-    case MPS_OPT_DD_STREAM:
-      if (!(value == 0 || value == 1)) return fail(err, MPS_EINVAL, "dd stream switch must be 0 or 1");
-      E->dd_stream = value != 0;
-      return MPS_OK;
-    case MPS_OPT_STEP_SPLIT:
-      if (!(value >= 0 && value <= 1 << 20 && value == (double)(int)value))
-        return fail(err, MPS_EINVAL, "step split limit must be a non-negative integer");
-      E->split_max = (int)value;
-      return MPS_OK;
-    case MPS_OPT_QR:
-      if (!(value == 0 || value == 1)) return fail(err, MPS_EINVAL, "QR switch must be 0 or 1");
-      E->qr = value != 0;
-      E->tuned = false;
-      return MPS_OK;
-    case MPS_OPT_FUSE:
-      if (!(value == 0 || value == 1)) return fail(err, MPS_EINVAL, "fusion switch must be 0 or 1");
-      E->fuse = value != 0;
-      return MPS_OK;
-    case MPS_OPT_JACOBI_STREAMS:
-      if (!(value == 1 || value == 2)) return fail(err, MPS_EINVAL, "Jacobi stream count must be 1 or 2");
-      E->jacobi_streams = (int)value;
-      return MPS_OK;
-    case MPS_OPT_DD_REFINE:
-      if (!(value == 0 || value == 1)) return fail(err, MPS_EINVAL, "dd refinement switch must be 0 or 1");
-      E->dd_refine = value != 0;
-      return MPS_OK;
-    case MPS_OPT_TICK_SWEEPS:
-      if (!(value == 1 || value == 2)) return fail(err, MPS_EINVAL, "sweeps per tick must be 1 or 2");
-      E->tick_sweeps = (int)value;
-      return MPS_OK;
-    case MPS_OPT_GRAPH:
-      if (!(value == 0 || value == 1)) return fail(err, MPS_EINVAL, "graph switch must be 0 or 1");
-      E->graphs_on = value != 0;
-      return MPS_OK;
-    case MPS_OPT_WORKSPACE_MB:
-      if (!(value >= 1 && value <= 1 << 22)) return fail(err, MPS_EINVAL, "workspace limit out of range");
-      E->ws_limit = value * (1 << 20);
-      return MPS_OK;
-    default:
-      return fail(err, MPS_EINVAL, "unknown option");
-  }
-}
-
 }  // namespace
+
 
 // ====================================================================== C ABI
 // ------------------------------------------------------------------ gate fusion
@@ -2733,3 +1130,4 @@ int mps_batch_set_option(mps_batch_handle b, int key, double value) {
 const char* mps_batch_last_error(mps_batch_handle b) { return b ? b->err.c_str() : g_create_error.c_str(); }
 
 }  // extern "C"
+
