@@ -194,6 +194,109 @@ __device__ __forceinline__ RotCoef inner_coef(double al, double be, double2 g, b
   return k;
 }
 
+// The same inner Jacobi for wide pairs (W2 = 32), organised by pairs: each round,
+// one thread per column pair forms both columns' coefficients (staged in LDS), then
+// one thread per pair of pairs (a, b) forms the 2 x 2 blocks of J^H G J and R J on
+// rows {p_a, q_a} and columns {p_b, q_b}, which need only that block of G and R.
+// Every coefficient comes from the same inputs through the same inner_coef as in
+// inner_jacobi_block and every element from the same expression, so both forms give
+// the same G and R bit for bit; this one reads each G and R element once a round.
+template <int W2>
+struct StagedRot {
+  double2 ra[W2], rb[W2];
+  int rot[W2];
+};
+
+// the columns (p < q) of pair a in round rnd: cross rounds pair a < W2/2 with
+// W2/2 + (a + rnd) mod W2/2; the full round-robin pairs positions a and W2 - 1 - a,
+// position 0 holding column 0 and position m > 0 column 1 + (m - 1 + rnd) mod (W2 - 1)
+template <int W2>
+__device__ __forceinline__ void inner_pair(int a, int rnd, bool cross, int& p, int& q) {
+  constexpr int H = W2 / 2, np1 = W2 - 1;
+  if (cross) {
+    p = a;
+    q = H + (a + rnd) % H;
+    return;
+  }
+  const int m0 = a, m1 = np1 - a;
+  const int c0 = m0 == 0 ? 0 : 1 + (m0 - 1 + rnd) % np1, c1 = 1 + (m1 - 1 + rnd) % np1;
+  p = c0 < c1 ? c0 : c1;
+  q = c0 < c1 ? c1 : c0;
+}
+
+template <int W2, int NT>
+__device__ int inner_jacobi_pairs(double2 (&G)[2][W2][W2 + 1], double2 (&R)[2][W2][W2 + 1], InnerLds<W2>& L,
+                                  StagedRot<W2>& K, const int (&cols)[W2], int inner, double tol, double ztol,
+                                  bool cross) {
+  constexpr int H = W2 / 2;
+  static_assert(NT >= H * H, "one thread per pair of pairs");
+  const int tid = threadIdx.x;
+  for (int e = tid; e < W2 * W2; e += NT) R[0][e / W2][e % W2] = cmk(e / W2 == e % W2 ? 1.0 : 0.0, 0.0);
+  __syncthreads();
+  int cur = 0, any_rot = 0;
+  const int nrnd = cross ? H : W2 - 1;
+  for (int isw = 0; isw < inner; ++isw) {
+    int mine = 0;
+    for (int rnd = 0; rnd < nrnd; ++rnd) {
+      const double2(*Gc)[W2 + 1] = G[cur];
+      if (tid < H) {  // pair tid's rotation: coefficients of both columns
+        int p, q;
+        inner_pair<W2>(tid, rnd, cross, p, q);
+        const bool v = (cols[p] >= 0) & (cols[q] >= 0);
+        const double al = Gc[p][p].x, be = Gc[q][q].x;
+        const double2 g = Gc[p][q];
+        const RotCoef cp = inner_coef(al, be, g, v, true, tol, ztol);
+        const RotCoef cq = inner_coef(al, be, g, v, false, tol, ztol);
+        K.ra[p] = cp.ra;
+        K.rb[p] = cp.rb;
+        K.rot[p] = cp.rot;
+        K.ra[q] = cq.ra;
+        K.rb[q] = cq.rb;
+        K.rot[q] = cq.rot;
+        mine |= cp.rot;
+      }
+      __syncthreads();
+      if (tid < H * H) {
+        int pa, qa, pb, qb;
+        inner_pair<W2>(tid / H, rnd, cross, pa, qa);
+        inner_pair<W2>(tid % H, rnd, cross, pb, qb);
+        const double2 g_pp = Gc[pa][pb], g_pq = Gc[pa][qb], g_qp = Gc[qa][pb], g_qq = Gc[qa][qb];
+        const double2 r_pp = R[cur][pa][pb], r_pq = R[cur][pa][qb], r_qp = R[cur][qa][pb], r_qq = R[cur][qa][qb];
+        const double2 ra_pa = K.ra[pa], rb_pa = K.rb[pa], ra_qa = K.ra[qa], rb_qa = K.rb[qa];
+        const double2 ra_pb = K.ra[pb], rb_pb = K.rb[pb], ra_qb = K.ra[qb], rb_qb = K.rb[qb];
+        const int rot_pa = K.rot[pa], rot_qa = K.rot[qa];
+        // element (i, j) with partners (pi, pj): from G[i][j], G[i][pj], G[pi][j], G[pi][pj]
+        auto elem = [&](int i, int j, int pi_, double2 ra_i, double2 rb_i, int rot_i, double2 ra_j, double2 rb_j,
+                        double2 gij, double2 giq, double2 gpj, double2 gpq) {
+          const double2 colj = cadd(cmul(ra_j, gij), cmul(rb_j, giq));
+          const double2 colpj = cadd(cmul(ra_j, gpj), cmul(rb_j, gpq));
+          double2 v = cadd(cmul(cconj(ra_i), colj), cmul(cconj(rb_i), colpj));
+          if (rot_i && j == pi_) v = cmk(0.0, 0.0);  // the rotated pair's off-diagonal is zero
+          if (i == j) v.y = 0.0;
+          return v;
+        };
+        double2(*Gn)[W2 + 1] = G[cur ^ 1];
+        double2(*Rn)[W2 + 1] = R[cur ^ 1];
+        Gn[pa][pb] = elem(pa, pb, qa, ra_pa, rb_pa, rot_pa, ra_pb, rb_pb, g_pp, g_pq, g_qp, g_qq);
+        Gn[pa][qb] = elem(pa, qb, qa, ra_pa, rb_pa, rot_pa, ra_qb, rb_qb, g_pq, g_pp, g_qq, g_qp);
+        Gn[qa][pb] = elem(qa, pb, pa, ra_qa, rb_qa, rot_qa, ra_pb, rb_pb, g_qp, g_qq, g_pp, g_pq);
+        Gn[qa][qb] = elem(qa, qb, pa, ra_qa, rb_qa, rot_qa, ra_qb, rb_qb, g_qq, g_qp, g_pq, g_pp);
+        Rn[pa][pb] = cadd(cmul(ra_pb, r_pp), cmul(rb_pb, r_pq));
+        Rn[pa][qb] = cadd(cmul(ra_qb, r_pq), cmul(rb_qb, r_pp));
+        Rn[qa][pb] = cadd(cmul(ra_pb, r_qp), cmul(rb_pb, r_qq));
+        Rn[qa][qb] = cadd(cmul(ra_qb, r_qq), cmul(rb_qb, r_qp));
+      }
+      cur ^= 1;
+      __syncthreads();
+    }
+    if (!__syncthreads_or(mine)) break;
+    any_rot = 1;
+  }
+  if (tid == 0) L.any_rot = any_rot;
+  __syncthreads();
+  return cur;
+}
+
 // cross: only the (W2/2)^2 pairs between the two column blocks, in W2/2 rounds
 // (round r pairs p with W2/2 + (p + r) mod W2/2); else all pairs, round-robin.
 template <int W2, int NT>
@@ -344,60 +447,71 @@ __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* en
     // by MFMA, the pair's 32 columns as two halves of 16: per k-step of 4 rows lane l
     // holds X[4 ks + l / 16][l % 16] of each half (x0, x1).  Re G = Xr^T Xr + Xi^T Xi
     // from the tiles 00, 01 and 11 (10 = 01^T), P = Xr^T Xi from all four tiles, then
-    // Im G = P - P^T; wave w takes the k-steps w, w + 8, ...; the waves' tiles are added
-    // in wave order.
+    // Im G = P - P^T; wave w takes the k-steps w, w + 8, ...; the waves' tiles are
+    // summed by a fixed tree ((w0 + w1) + (w2 + w3)) + ((w4 + w5) + (w6 + w7)).
     __shared__ double Gs[2][W2][W2 + 1];
+    __shared__ double Gx[NW / 2][7][4][64];
     constexpr int KB = 8;  // k-steps of loads in flight per wave
-    mfma_d4 r00 = {0.0, 0.0, 0.0, 0.0}, r01 = r00, r11 = r00, p00 = r00, p01 = r00, p10 = r00, p11 = r00;
+    mfma_d4 t[7];  // Re 00, 01, 11; P 00, 01, 10, 11
+#pragma unroll
+    for (int k = 0; k < 7; ++k) t[k] = mfma_d4{0.0, 0.0, 0.0, 0.0};
     const int c0 = cols[lane & 15], c1 = cols[16 + (lane & 15)];
     const int roff = lane >> 4;
     const int nks = (M + 3) / 4;
     for (int ks0 = wave; ks0 < nks; ks0 += NW * KB) {
       double2 x0[KB], x1[KB];
 #pragma unroll
-      for (int t = 0; t < KB; ++t) {
-        const int r = (ks0 + NW * t) * 4 + roff;
-        x0[t] = (c0 >= 0 && r < M) ? A[(long)c0 * M + r] : cmk(0.0, 0.0);
-        x1[t] = (c1 >= 0 && r < M) ? A[(long)c1 * M + r] : cmk(0.0, 0.0);
+      for (int u = 0; u < KB; ++u) {
+        const int r = (ks0 + NW * u) * 4 + roff;
+        x0[u] = (c0 >= 0 && r < M) ? A[(long)c0 * M + r] : cmk(0.0, 0.0);
+        x1[u] = (c1 >= 0 && r < M) ? A[(long)c1 * M + r] : cmk(0.0, 0.0);
       }
 #pragma unroll
-      for (int t = 0; t < KB; ++t) {
-        r00 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[t].x, x0[t].x, r00, 0, 0, 0);
-        r00 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[t].y, x0[t].y, r00, 0, 0, 0);
-        r01 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[t].x, x1[t].x, r01, 0, 0, 0);
-        r01 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[t].y, x1[t].y, r01, 0, 0, 0);
-        r11 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[t].x, x1[t].x, r11, 0, 0, 0);
-        r11 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[t].y, x1[t].y, r11, 0, 0, 0);
-        p00 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[t].x, x0[t].y, p00, 0, 0, 0);
-        p01 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[t].x, x1[t].y, p01, 0, 0, 0);
-        p10 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[t].x, x0[t].y, p10, 0, 0, 0);
-        p11 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[t].x, x1[t].y, p11, 0, 0, 0);
+      for (int u = 0; u < KB; ++u) {
+        t[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[u].x, x0[u].x, t[0], 0, 0, 0);
+        t[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[u].y, x0[u].y, t[0], 0, 0, 0);
+        t[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[u].x, x1[u].x, t[1], 0, 0, 0);
+        t[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[u].y, x1[u].y, t[1], 0, 0, 0);
+        t[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[u].x, x1[u].x, t[2], 0, 0, 0);
+        t[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[u].y, x1[u].y, t[2], 0, 0, 0);
+        t[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[u].x, x0[u].y, t[3], 0, 0, 0);
+        t[4] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[u].x, x1[u].y, t[4], 0, 0, 0);
+        t[5] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[u].x, x0[u].y, t[5], 0, 0, 0);
+        t[6] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[u].x, x1[u].y, t[6], 0, 0, 0);
       }
     }
-    for (int w = 0; w < NW; ++w) {
-      if (wave == w) {
-        const int j = lane & 15;
+    for (int stride = 1; stride < NW; stride <<= 1) {
+      const int sl = wave / (2 * stride), pos = wave & (2 * stride - 1);
+      if (pos == stride) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = roff + 4 * r;
-          const bool first = w == 0;
-          double* re = &Gs[0][0][0];
-          double* pp = &Gs[1][0][0];
-          auto acc = [&](double* base, int ii, int jj, double v) {
-            double& d = base[ii * (W2 + 1) + jj];
-            d = first ? v : d + v;
-          };
-          acc(re, i, j, r00[r]);
-          acc(re, i, 16 + j, r01[r]);
-          acc(re, 16 + i, 16 + j, r11[r]);
-          acc(pp, i, j, p00[r]);
-          acc(pp, i, 16 + j, p01[r]);
-          acc(pp, 16 + i, j, p10[r]);
-          acc(pp, 16 + i, 16 + j, p11[r]);
-        }
+        for (int k = 0; k < 7; ++k)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) Gx[sl][k][r][lane] = t[k][r];
+      }
+      __syncthreads();
+      if (pos == 0) {
+#pragma unroll
+        for (int k = 0; k < 7; ++k)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) t[k][r] += Gx[sl][k][r][lane];
       }
       __syncthreads();
     }
+    if (wave == 0) {
+      const int j = lane & 15;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = roff + 4 * r;
+        Gs[0][i][j] = t[0][r];
+        Gs[0][i][16 + j] = t[1][r];
+        Gs[0][16 + i][16 + j] = t[2][r];
+        Gs[1][i][j] = t[3][r];
+        Gs[1][i][16 + j] = t[4][r];
+        Gs[1][16 + i][j] = t[5][r];
+        Gs[1][16 + i][16 + j] = t[6][r];
+      }
+    }
+    __syncthreads();
     for (int e = tid; e < W2 * W2; e += NT) {
       const int i = e / W2, j = e % W2;
       // Re G's lower-left tile is the transpose of its upper-right one
@@ -480,7 +594,13 @@ __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* en
   //    Within a sweep, the pairs inside each block are rotated at its first step; the
   //    later steps rotate only the pairs across the two blocks.
   const bool many = nbp >= 16;
-  const int cur = inner_jacobi_block<W2, NT>(Gb, Rb, L, cols, many ? maxin : maxin_few, tol, ztol, many && step > 0);
+  int cur;
+  if constexpr (W2 == 32) {
+    __shared__ StagedRot<W2> K;
+    cur = inner_jacobi_pairs<W2, NT>(Gb, Rb, L, K, cols, many ? maxin : maxin_few, tol, ztol, many && step > 0);
+  } else {
+    cur = inner_jacobi_block<W2, NT>(Gb, Rb, L, cols, many ? maxin : maxin_few, tol, ztol, many && step > 0);
+  }
   const int res_rot = L.any_rot;
   if (clk) phase_clock[2] = wall_clock64();
 
