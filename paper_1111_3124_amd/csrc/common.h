@@ -86,6 +86,7 @@ struct Task2 {
   double* sig2_lo;
   int* perm;            // N: column order, sigma descending
   double* fro2;         // ||thw||_F^2 (zero-column threshold)
+  double* frop;         // its partial sums, one per chunk of kFroChunk elements of thw
   double* stats;        // 8 doubles: W, w, gap, epsdist, k, rank, nu (hi, lo)
   int* flags;           // 3 ints: rotation flags of the current / next / previous sweep
   // three-site gates (first split): theta is 2a x 4d, columns (j*2 + k)*d + delta
@@ -111,6 +112,10 @@ struct Task2 {
   double* qt;
   double2* qT;
 };
+
+// ||theta_w||_F^2 is summed over fixed chunks of thw (partials in a per-task array,
+// then added in chunk order), so that it does not depend on how a launch is shaped
+constexpr int kFroChunk = 4096;
 
 // One entry of a launch list: the task slot a block row works on and, for the
 // Jacobi steps, the slot's current sweep index.

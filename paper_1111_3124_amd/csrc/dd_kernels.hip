@@ -52,7 +52,6 @@ struct ThetaOpDD {
   }
   __device__ void epilogue(int r0, int c0, cdd (&T4)[2][2]) const {
     const int al = r0 >> 1, ga = c0 >> 1, M = t->M;
-    double fro = 0.0;
     if (al < t->a && ga < t->c) {
       const ddr wl = {t->lamL[al], t->lamL_lo[al]};
       cdd Tin[4] = {T4[0][0], T4[0][1], T4[1][0], T4[1][1]};
@@ -71,17 +70,8 @@ struct ThetaOpDD {
             t->thw[(long)(2 * al + i) * t->Nt + (j * t->c + ga)] = make_double2(w.re.hi, -w.im.hi);
           else
             t->thw[idx] = make_double2(w.re.hi, w.im.hi);
-          fro += w.re.hi * w.re.hi + w.im.hi * w.im.hi;
         }
     }
-    __shared__ double red[256];
-    red[threadIdx.x] = fro;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicAdd(t->fro2, red[0]);
   }
 };
 

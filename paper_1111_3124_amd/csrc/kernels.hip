@@ -49,7 +49,6 @@ struct ThetaOp {
   }
   __device__ void epilogue(int r0, int c0, double2 (&acc)[4][4]) const {
     const int a_ = t->a, c_ = t->c, M = t->M;
-    double fro = 0.0;
 #pragma unroll
     for (int da = 0; da < 2; ++da) {
       const int al = (r0 >> 1) + da;
@@ -78,19 +77,9 @@ struct ThetaOp {
               t->thw[(long)(2 * al + i) * t->Nt + (j * c_ + ga)] = cconj(ow);
             else
               t->thw[idx] = ow;
-            fro += ow.x * ow.x + ow.y * ow.y;
           }
       }
     }
-    // block reduction of ||theta_w||^2 (zero-column threshold of the Jacobi)
-    __shared__ double red[256];
-    red[threadIdx.x] = fro;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicAdd(t->fro2, red[0]);
   }
 };
 
@@ -100,6 +89,50 @@ __global__ __launch_bounds__(256) void k_theta2(Task2* tasks, const Ent* ents) {
   if (tm >= t->M || tn >= t->Nt) return;
   ThetaOp op{t};
   cgemm_tile(op, t->M, t->Nt, t->b, tm, tn);
+}
+
+// ------------------------------------------------------------------ ||theta_w||_F^2
+// Partial sums over fixed chunks of kFroChunk elements of thw (each thread 16 of them
+// in order, then a fixed tree), then the partials in chunk order: the result depends
+// only on the task, not on the launch.  (thw holds theta_w or its conjugate
+// transpose: the same squared magnitudes.)
+__global__ __launch_bounds__(256) void k_fro_part(Task2* tasks, const Ent* ents) {
+  const Task2& T = tasks[ents[blockIdx.y].slot];
+  const long mn = (long)T.M * T.Nt;
+  const long c0 = (long)blockIdx.x * kFroChunk;
+  if (c0 >= mn) return;
+  double s = 0.0;
+  for (int q = 0; q < kFroChunk / 256; ++q) {
+    const long e = c0 + q * 256 + threadIdx.x;
+    if (e < mn) {
+      const double2 w = T.thw[e];
+      s += w.x * w.x + w.y * w.y;
+    }
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) T.frop[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_fro_sum(Task2* tasks, const Ent* ents) {
+  const Task2& T = tasks[ents[blockIdx.x].slot];
+  const long mn = (long)T.M * T.Nt;
+  const int nch = (int)((mn + kFroChunk - 1) / kFroChunk);
+  double s = 0.0;
+  for (int c = threadIdx.x; c < nch; c += 256) s += T.frop[c];
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *T.fro2 = red[0];
 }
 
 // ------------------------------------------------------------------ Jacobi step
@@ -1119,6 +1152,15 @@ hipError_t launch_qr_order(Task2* d_tasks, const Ent* d_ents, int nent, hipStrea
 
 hipError_t launch_jacobi_order(Task2* d_tasks, const Ent* d_ents, int nent, hipStream_t st) {
   hipLaunchKernelGGL(k_jacobi_order, dim3(nent), dim3(1024), 0, st, d_tasks, d_ents);
+  MPS_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_fro(Task2* d_tasks, const Ent* d_ents, int nent, long maxMN, hipStream_t st) {
+  const int nch = (int)((maxMN + kFroChunk - 1) / kFroChunk);
+  hipLaunchKernelGGL(k_fro_part, dim3(nch, nent), dim3(256), 0, st, d_tasks, d_ents);
+  MPS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_fro_sum, dim3(nent), dim3(256), 0, st, d_tasks, d_ents);
   MPS_LAUNCH_CHECK();
   return hipSuccess;
 }

@@ -56,7 +56,6 @@ struct Theta3Op {
   __device__ double2 b(int kk, int col) const { return t->B3[(long)(2 * kk + (col & 1)) * t->ld3 + (col >> 1)]; }
   __device__ void epilogue(int r0, int c0, double2 (&acc)[4][4]) const {
     const int al = r0 >> 2, M = t->M, d = t->d;
-    double fro = 0.0;
     if (al < t->a) {
       const double wl = t->lamL[al];
 #pragma unroll
@@ -81,18 +80,9 @@ struct Theta3Op {
             t->thw[(long)(2 * al + i) * t->Nt + (jk * d + de)] = cconj(w);
           else
             t->thw[idx] = w;
-          fro += w.x * w.x + w.y * w.y;
         }
       }
     }
-    __shared__ double red[256];
-    red[threadIdx.x] = fro;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicAdd(t->fro2, red[0]);
   }
 };
 
@@ -112,7 +102,6 @@ __global__ __launch_bounds__(256) void k_mid3(Task2* tasks, const Ent* ents) {
   const Task2& Bt = tasks[ents[blockIdx.z].sweep];
   const int k1 = *A.dim_out, d = A.d, N1 = A.Nt, M2 = Bt.M;
   const int nu = blockIdx.y;
-  double fro = 0.0;
   if (nu < k1) {
     const int col = A.perm[nu];
     const double w = A.lamS[nu];
@@ -126,17 +115,8 @@ __global__ __launch_bounds__(256) void k_mid3(Task2* tasks, const Ent* ents) {
         Bt.thw[(long)(2 * nu + j) * Bt.Nt + (k * d + de)] = cconj(vw);
       else
         Bt.thw[idx] = vw;
-      fro += vw.x * vw.x + vw.y * vw.y;
     }
   }
-  __shared__ double red[256];
-  red[threadIdx.x] = fro;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0 && red[0] != 0.0) atomicAdd(Bt.fro2, red[0]);
 }
 
 // ------------------------------------------------------------------ double-double
@@ -182,7 +162,6 @@ struct Theta3OpDD {
   }
   __device__ void epilogue(int r0, int c0, cdd (&T8)[4][2]) const {
     const int al = r0 >> 2, de = c0 >> 1, M = t->M, d = t->d;
-    double fro = 0.0;
     if (al < t->a && de < d) {
       const ddr wl = {t->lamL[al], t->lamL_lo[al]};
       cdd Tin[8];
@@ -206,17 +185,8 @@ struct Theta3OpDD {
           t->thw[(long)(2 * al + i) * t->Nt + (jk * d + de)] = make_double2(w.re.hi, -w.im.hi);
         else
           t->thw[idx] = make_double2(w.re.hi, w.im.hi);
-        fro += w.re.hi * w.re.hi + w.im.hi * w.im.hi;
       }
     }
-    __shared__ double red[256];
-    red[threadIdx.x] = fro;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicAdd(t->fro2, red[0]);
   }
 };
 
@@ -233,7 +203,6 @@ __global__ __launch_bounds__(256) void k_mid3_dd(Task2* tasks, const Ent* ents) 
   const Task2& Bt = tasks[ents[blockIdx.z].sweep];
   const int k1 = *A.dim_out, d = A.d, N1 = A.Nt, M2 = Bt.M;
   const int nu = blockIdx.y;
-  double fro = 0.0;
   if (nu < k1) {
     const int col = A.perm[nu];
     const ddr w = {A.lamS[nu], A.lamS_lo[nu]};
@@ -247,17 +216,8 @@ __global__ __launch_bounds__(256) void k_mid3_dd(Task2* tasks, const Ent* ents) 
         Bt.thw[(long)(2 * nu + j) * Bt.Nt + (k * d + de)] = make_double2(vw.re.hi, -vw.im.hi);
       else
         Bt.thw[idx] = make_double2(vw.re.hi, vw.im.hi);
-      fro += vw.re.hi * vw.re.hi + vw.im.hi * vw.im.hi;
     }
   }
-  __shared__ double red[256];
-  red[threadIdx.x] = fro;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0 && red[0] != 0.0) atomicAdd(Bt.fro2, red[0]);
 }
 
 // ------------------------------------------------------------------ launchers

@@ -14,6 +14,9 @@ struct AmpArgs {
 };
 
 hipError_t launch_prep2(Task2* d_tasks, const Ent* d_ents, int nent, int maxN, hipStream_t st);
+// ||theta_w||_F^2 of each listed task into *fro2 (after its theta kernels); maxMN: the
+// largest M x Nt of the list
+hipError_t launch_fro(Task2* d_tasks, const Ent* d_ents, int nent, long maxMN, hipStream_t st);
 hipError_t launch_theta2(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, int maxN, hipStream_t st);
 // phase_clock: NULL, or 5 long longs receiving wall_clock64() stamps of block (0, 0)
 // (start, after Gram, after inner Jacobi, end, rotated?) for phase profiling

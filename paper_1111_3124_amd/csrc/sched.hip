@@ -55,6 +55,7 @@ size_t task_ws_bytes(bool dd, int M, int Nt, int t1) {
   b += align_up(N * sizeof(int)) + align_up(N * sizeof(double2)) + align_up(N * sizeof(double)) +
        align_up((size_t)((N + 15) / 16) * 256 * sizeof(double2));
   b += align_up(jg_doubles(N) * sizeof(double));  // split Jacobi step: partial Grams
+  b += align_up(((MN + mpsk::kFroChunk - 1) / mpsk::kFroChunk) * sizeof(double));  // ||theta_w||^2 partials
   return b;
 }
 
@@ -116,6 +117,8 @@ void carve(bool dd, Task2& t, char* w, int* d_flags, double* d_stats, double* d_
   w += align_up((size_t)((t.N + 15) / 16) * 256 * sizeof(double2));
   t.JG = (double*)w;
   w += align_up(jg_doubles(t.N) * sizeof(double));
+  t.frop = (double*)w;
+  w += align_up(((MN + mpsk::kFroChunk - 1) / mpsk::kFroChunk) * sizeof(double));
   t.qr = 0;
   t.JW = t.thw;
   t.JV = t.V;
@@ -799,6 +802,11 @@ int Scheduler::launch_admitted() {
           e = dd ? mpsk::launch_theta2_dd(dt, el, (int)nl.size(), mM, mNt, st)
                  : mpsk::launch_theta2(dt, el, (int)nl.size(), mM, mNt, st);
       }
+      if (e == hipSuccess) {
+        long mn = 0;
+        for (int si : nl) mn = std::max(mn, (long)slot[si].M * slot[si].Nt);
+        e = mpsk::launch_fro(dt, el, (int)nl.size(), mn, st);
+      }
       if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("theta: ") + hipGetErrorString(e));
       std::vector<int> qrs;
       for (int si : nl)
@@ -1101,6 +1109,11 @@ int Scheduler::finalise() {
         Timed tm(E, 0);
         e = mpsk::launch_prep2(dt, eb, (int)newB.size(), mNB, st);
         if (e == hipSuccess) e = mpsk::launch_mid3(dt, em, (int)mids.size(), mN1, mK1, dd, st);
+        if (e == hipSuccess) {
+          long mn = 0;
+          for (int sb : newB) mn = std::max(mn, (long)ht[sb].M * ht[sb].Nt);
+          e = mpsk::launch_fro(dt, eb, (int)newB.size(), mn, st);
+        }
         if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("mid: ") + hipGetErrorString(e));
       }
     }
