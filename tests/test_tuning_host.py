@@ -72,3 +72,9 @@ def test_autotuner_candidates():
             assert dims[g.first] == dims[g.first + 1] == dims[g.first + 2] == chi
         # whole circuits of up to 12 gates: the concurrency rounded up
         assert at.CONCURRENCY[chi] <= len(gates) < at.CONCURRENCY[chi] + 12
+        n3, C3, st3, g3 = at.layer_case(chi, 2, at.FEW, 3)
+        assert len(g3) == at.FEW
+        d3 = [1] + [len(l) for l in st3[0][1]] + [1]
+        for c, g in g3:
+            assert g.k == 3 and g.first + 3 <= n3
+            assert d3[g.first] == d3[g.first + 1] == d3[g.first + 2] == d3[g.first + 3] == chi
