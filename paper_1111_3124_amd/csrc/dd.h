@@ -152,8 +152,14 @@ DD_FN void cacc_fma(cacc& s, cdd a, cdd b) {
   acc_add_prod(s.re, -a.im.hi, b.im.hi);
   acc_add_prod(s.im, a.re.hi, b.im.hi);
   acc_add_prod(s.im, a.im.hi, b.re.hi);
-  s.re.lo += (a.re.hi * b.re.lo + a.re.lo * b.re.hi) - (a.im.hi * b.im.lo + a.im.lo * b.im.hi);
-  s.im.lo += (a.re.hi * b.im.lo + a.re.lo * b.im.hi) + (a.im.hi * b.re.lo + a.im.lo * b.re.hi);
+  // cross terms hi*lo + lo*hi in binary64, each pair as one rounded product and one
+  // fused multiply-add, written out so that no compiler contraction choice changes them
+  const double rr = std::fma(a.re.lo, b.re.hi, a.re.hi * b.re.lo);
+  const double ii = std::fma(a.im.lo, b.im.hi, a.im.hi * b.im.lo);
+  const double ri = std::fma(a.re.lo, b.im.hi, a.re.hi * b.im.lo);
+  const double ir = std::fma(a.im.lo, b.re.hi, a.im.hi * b.re.lo);
+  s.re.lo += rr - ii;
+  s.im.lo += ri + ir;
 }
 
 // s += conj(a) * b
