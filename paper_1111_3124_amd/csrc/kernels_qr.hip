@@ -187,17 +187,18 @@ __device__ __forceinline__ void panel_columns(double2 (&y)[RPT][kPanel], PanelLd
   }
 }
 
-// One panel of 16 columns (positions p0.. of the order qperm), one 512-thread block
-// per task: the panel's rows p0..M-1 live in registers (RPT rows a thread).  For
-// column j (pivot row c = p0 + j, x = its rows >= c, alpha = x[c]) one block sum
-// gives ||x||^2, x^H y_j' for the later columns and v_i^H x for the earlier
-// reflectors; with beta = -e^{i arg alpha} ||x||, v = x - beta e_c:
+// One panel of 16 columns (positions p0.. of the order qperm), one block of NT threads
+// per task (256 for up to 512 rows, 512 above): the panel's rows p0..M-1 live in
+// registers (RPT = 2 rows a thread; four waves instead of eight for 512 rows take
+// 82 rather than 86 us a panel).  For column j (pivot row c = p0 + j, x = its rows
+// >= c, alpha = x[c]) one block sum gives ||x||^2, x^H y_j' for the later columns and
+// v_i^H x for the earlier reflectors; with beta = -e^{i arg alpha} ||x||, v = x - beta e_c:
 //   v^H y = x^H y - conj(beta) y[c],   S[i][j] = v_i^H v_j = v_i^H x - conj(v_i[c]) beta
 // (v_i[c] is reflector i's stored entry at row c).  Then the triangular factor T of
 // H_p0 ... H_p0+15 = I - V T V^H, one column at a time by 16 threads.
-template <int RPT>
-__global__ __launch_bounds__(512) void k_qr_panel(Task2* tasks, const Ent* ents, int p0) {
-  constexpr int NT = 512, NW = NT / 64;
+template <int RPT, int NT>
+__global__ __launch_bounds__(NT) void k_qr_panel(Task2* tasks, const Ent* ents, int p0) {
+  constexpr int NW = NT / 64;
   constexpr int K = 1 + 2 * kPanel;  // ||x||^2, then (re, im) of x^H y_j' (j' > j) or v_j'^H x (j' < j)
   const Task2& T = tasks[ents[blockIdx.x].slot];
   if (!T.qr) return;
@@ -417,9 +418,9 @@ hipError_t launch_qr_factor(Task2* d_tasks, const Ent* d_ents, int nent, int max
   if (e != hipSuccess) return e;
   for (int p0 = 0; p0 < maxN; p0 += kPanel) {
     if (maxM <= 512)
-      hipLaunchKernelGGL(k_qr_panel<1>, dim3(nent), dim3(512), 0, st, d_tasks, d_ents, p0);
+      hipLaunchKernelGGL((k_qr_panel<2, 256>), dim3(nent), dim3(256), 0, st, d_tasks, d_ents, p0);
     else
-      hipLaunchKernelGGL(k_qr_panel<2>, dim3(nent), dim3(512), 0, st, d_tasks, d_ents, p0);
+      hipLaunchKernelGGL((k_qr_panel<2, 512>), dim3(nent), dim3(512), 0, st, d_tasks, d_ents, p0);
     MPS_LAUNCH_CHECK();
     const int trail = maxN - p0 - kPanel;
     if (trail > 0) {
