@@ -19,6 +19,12 @@
 // A pair whose E_pq would exceed 1e-8 (a relative gap below ~1e-5: near-degenerate
 // singular values) voids the pass for that task (nothing is updated) and the task
 // goes to the pairwise dd Jacobi polish instead.
+//
+// Passes are numbered per task; pass q writes its outcome to flags[q % 3] (0: every
+// pair at the convergence level, |1: some pair above it, |2: void) and clears
+// flags[(q + 1) % 3] for the next one.  Pass q > 0 runs only if pass q - 1 ended
+// with exactly 1 (corrected, not yet converged), so consecutive passes can be
+// queued together: those after a converged or void pass leave everything untouched.
 #include "dd.h"
 #include "ddgemm.h"
 #include "ddref.h"
@@ -56,10 +62,16 @@ struct WGramOp {
   }
 };
 
+// pass q > 0 follows a pass that corrected without converging
+__device__ __forceinline__ bool ref_skip(const Task2& T, int pass) {
+  return pass > 0 && T.flags[(pass + 2) % 3] != 1;
+}
+
 __global__ __launch_bounds__(256) void k_ref_gram(Task2* tasks, const Ent* ents) {
   const Task2* t = &tasks[ents[blockIdx.z].slot];
   const int tm = blockIdx.x * 32, tn = blockIdx.y * 32;
   if (tm >= t->N || tn >= t->N || tm > tn) return;  // upper tiles (and the diagonal ones)
+  if (ref_skip(*t, ents[blockIdx.z].sweep)) return;
   if (tm == 0 && tn == 0 && threadIdx.x == 0) t->flags[(ents[blockIdx.z].sweep + 1) % 3] = 0;
   WGramOp op{t};
   ddgemm_tile(op, t->N, t->N, t->JM, tm, tn);
@@ -70,6 +82,7 @@ __global__ __launch_bounds__(256) void k_ref_gram(Task2* tasks, const Ent* ents)
 __global__ __launch_bounds__(256) void k_ref_e(Task2* tasks, const Ent* ents, double tol_mult) {
   const Task2& T = tasks[ents[blockIdx.y].slot];
   const int pass = ents[blockIdx.y].sweep;
+  if (ref_skip(T, pass)) return;  // the whole block: the flag is the task's
   const int N = T.N, M = T.JM;
   const double tol = tol_mult * (double)(M > 16 ? M : 16) * 0x1p-101;
   const double rtol = sqrt(tol / (double)(N > 1 ? N : 1));
@@ -107,7 +120,9 @@ __global__ __launch_bounds__(256) void k_ref_e(Task2* tasks, const Ent* ents, do
   if (threadIdx.x == 0 && (c1 || c2)) atomicOr(&T.flags[pass % 3], (c1 ? 1 : 0) | (c2 ? 2 : 0));
 }
 
-__device__ __forceinline__ bool ref_void(const Task2& T, int pass) { return (T.flags[pass % 3] & 2) != 0; }
+__device__ __forceinline__ bool ref_void(const Task2& T, int pass) {
+  return ref_skip(T, pass) || (T.flags[pass % 3] & 2) != 0;
+}
 
 // F = E + E^2 / 2 into aux2
 struct RefSqOp {

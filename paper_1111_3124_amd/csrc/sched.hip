@@ -31,6 +31,7 @@ struct Slot {
   int partner = -1;  // kind 1: the reserved slot of the second split
   int sweep = 0;
   int fp64_sweeps = 0, dd_sweeps = 0;
+  int passes = 0;  // dd refinement passes queued; `sweep` counts those whose outcome was read
   bool fp64_conv = false, conv = false;
   int M = 0, Nt = 0, JM = 0, N = 0;  // theta rows and columns, Jacobi rows and columns
   int bw = 8, inner_few = 1;          // step kernel configuration (step_cfg)
@@ -340,9 +341,16 @@ class Scheduler {
   // device lists: new2, new3, jacobi (two halves + order, for each of two sweeps), dd,
   // dd-enter, final, final3, mid, znorm, ref, polish, qr z, dd-enter QR tasks, and a
   // ring of kQrRing lists of QR factorisations in flight
-  enum { LN2 = 0, LN3, LJ, LD, LENTER, LFIN, LFIN3, LMID, LZN, LR, LPOL, LJ2, LJO, LQZ, LQL, LJ_1, LJ2_1, LJO_1, LQR0 };
+  enum {
+    LN2 = 0, LN3, LJ, LD, LENTER, LFIN, LFIN3, LMID, LZN, LR, LPOL, LJ2, LJO, LQZ, LQL, LJ_1, LJ2_1, LJO_1,
+    LR_1, LEP0, LEP1, LQR0
+  };
   static constexpr int kQrRing = 4;
-  static constexpr int kLists = 18 + kQrRing;
+  static constexpr int kLists = LQR0 + kQrRing;
+  // dd refinement passes queued together (each after the first runs only if the one
+  // before it corrected without converging), so that an update that needs two
+  // passes reads both outcomes at one tick
+  static constexpr int kRefChain = 2;
   // QR factorisations in flight on stream3, oldest first: completion event and the
   // slots waiting (state 6); polled at the end of each tick, so that a factorisation
   // longer than a sweep does not hold up the other updates' sweeps
@@ -366,6 +374,7 @@ class Scheduler {
   mpsk::Ent* upload_list(int li, const std::vector<mpsk::Ent>& ents);
   std::vector<mpsk::Ent> ents_of(const std::vector<int>& sl) const;
   hipError_t launch_jacobi(const std::vector<int>& jl, int K);
+  hipError_t launch_passes(const std::vector<int>& sl, int l0, int l1);
   hipError_t qr_poll(bool block);
   int take_slot();
   void release_slot(int si);
@@ -539,6 +548,31 @@ std::vector<mpsk::Ent> Scheduler::ents_of(const std::vector<int>& sl) const {
   v.reserve(sl.size());
   for (int si : sl) v.push_back(mpsk::Ent{si, slot[si].sweep});
   return v;
+}
+
+// up to kRefChain dd refinement passes for each slot of `sl` (within the pass
+// limit) on the dd stream, the k-th pass of the chain from the list l0 (k = 0) or
+// l1 (k = 1)
+hipError_t Scheduler::launch_passes(const std::vector<int>& sl, int l0, int l1) {
+  const int lists[kRefChain] = {l0, l1};
+  for (int k = 0; k < kRefChain; ++k) {
+    std::vector<mpsk::Ent> ents;
+    int mM = 0, mN = 0;
+    for (int si : sl)
+      if (slot[si].passes + k < E->max_ref_passes) {
+        ents.push_back(mpsk::Ent{si, slot[si].passes + k});
+        mM = std::max(mM, slot[si].JM);
+        mN = std::max(mN, slot[si].N);
+      }
+    if (ents.empty()) break;
+    mpsk::Ent* el = upload_list(lists[k], ents);
+    if (!el) return hipErrorInvalidValue;
+    Timed tm(E, 6, 1, sd);
+    const hipError_t e = mpsk::launch_ddref_pass(dt, el, (int)ents.size(), mM, mN, E->tol_mult, sd);
+    if (e != hipSuccess) return e;
+  }
+  for (int si : sl) slot[si].passes = std::min(slot[si].passes + kRefChain, E->max_ref_passes);
+  return hipSuccess;
 }
 
 // the FP64 sweeps of the iterating slots `jl` (K of them), as stream launches or
@@ -834,17 +868,16 @@ int Scheduler::sweep() {
   hipError_t e;
   // dd refinement passes and polish sweeps first, on the dd stream, so that they
   // overlap the FP64 sweeps launched below
-  if (!rl.empty() || !dl.empty()) {
-    mpsk::Ent* elr = rl.empty() ? nullptr : upload_list(LR, ents_of(rl));
+  // (slots whose queued passes have not been read yet get no new ones)
+  std::vector<int> rq;
+  for (int si : rl)
+    if (slot[si].passes == slot[si].sweep) rq.push_back(si);
+  if (!rq.empty() || !dl.empty()) {
     mpsk::Ent* eld = dl.empty() ? nullptr : upload_list(LD, ents_of(dl));
-    if ((!rl.empty() && !elr) || (!dl.empty() && !eld)) return fail(err, MPS_EDEVICE, "list upload failed");
+    if (!dl.empty() && !eld) return fail(err, MPS_EDEVICE, "list upload failed");
     HIPCHK(err, fork_dd());
-    if (!rl.empty()) {
-      int mM = 0, mN = 0;
-      for (int si : rl) { mM = std::max(mM, slot[si].JM); mN = std::max(mN, slot[si].N); }
-      Timed tm(E, 6, 1, sd);
-      E->slot_sweeps_dd += (long)rl.size();
-      e = mpsk::launch_ddref_pass(dt, elr, (int)rl.size(), mM, mN, E->tol_mult, sd);
+    if (!rq.empty()) {
+      e = launch_passes(rq, LR, LR_1);
       if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("dd refinement: ") + hipGetErrorString(e));
     }
     if (!dl.empty()) {
@@ -908,6 +941,7 @@ int Scheduler::converge() {
         enter.push_back(si);
         sl.state = E->dd_refine ? 2 : 4;
         sl.sweep = 0;
+        sl.passes = 0;
       } else {
         sl.conv = sl.fp64_conv;
         sl.state = 3;
@@ -917,17 +951,25 @@ int Scheduler::converge() {
   std::vector<int> to_polish;
   for (int si : rl) {
     Slot& sl = slot[si];
-    const int code = hflags[3 * si + sl.sweep % 3];
-    ++sl.sweep;
-    if (code == 0) {
-      sl.dd_sweeps = sl.sweep;
-      sl.conv = true;
-      sl.state = 3;
-    } else if ((code & 2) || sl.sweep >= E->max_ref_passes) {
-      sl.dd_sweeps = sl.sweep;
-      sl.state = 4;
-      sl.sweep = 0;
-      to_polish.push_back(si);
+    // the queued passes in order, up to the first that converged or was void (the
+    // ones after it changed nothing)
+    while (sl.sweep < sl.passes) {
+      const int code = hflags[3 * si + sl.sweep % 3];
+      ++sl.sweep;
+      ++E->slot_sweeps_dd;
+      if (code == 0) {
+        sl.dd_sweeps = sl.sweep;
+        sl.conv = true;
+        sl.state = 3;
+        break;
+      }
+      if ((code & 2) || sl.sweep >= E->max_ref_passes) {
+        sl.dd_sweeps = sl.sweep;
+        sl.state = 4;
+        sl.sweep = 0;
+        to_polish.push_back(si);
+        break;
+      }
     }
   }
   for (int si : dl) {
@@ -983,9 +1025,20 @@ int Scheduler::converge() {
       e = mpsk::launch_qr_left(dt, eql, (int)qrl.size(), qN, sd);
       if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("qr left: ") + hipGetErrorString(e));
     }
-    Timed tm(E, 6, 1, sd);
-    e = mpsk::launch_dd_enter(dt, el, (int)enter.size(), mM, mN, sd);
-    if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("dd enter: ") + hipGetErrorString(e));
+    {
+      Timed tm(E, 6, 1, sd);
+      e = mpsk::launch_dd_enter(dt, el, (int)enter.size(), mM, mN, sd);
+      if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("dd enter: ") + hipGetErrorString(e));
+    }
+    // the first refinement passes follow the promotion at once; their outcome is
+    // read at the next tick
+    std::vector<int> rq;
+    for (int si : enter)
+      if (slot[si].state == 2) rq.push_back(si);
+    if (!rq.empty()) {
+      e = launch_passes(rq, LEP0, LEP1);
+      if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("dd refinement: ") + hipGetErrorString(e));
+    }
   }
   return MPS_OK;
 }
