@@ -85,11 +85,12 @@ enum mps_option {
                                  double-double; the same state up to rounding, since a
                                  one-site unitary keeps every cut's Schmidt values);
                                  multi-site gates are never merged.  0: off             */
-  MPS_OPT_QR = 12             /* 1 (default): two-site Jacobi problems with 64 <= N and
-                                 M <= 1024 (dd: square only) are preconditioned by a
-                                 Householder QR of theta_w with its columns in norm
-                                 order, and the Jacobi runs on R^H (fewer sweeps);
-                                 0: the Jacobi runs on theta_w                           */,
+  MPS_OPT_QR = 12             /* 1 (default): Jacobi problems (two-site updates and both
+                                 splits of three-site gates) with 64 <= N <= M <= 1024
+                                 (dd: square only) are preconditioned by a Householder
+                                 QR of theta_w with its columns in norm order, and the
+                                 Jacobi runs on R^H (fewer sweeps); a wide theta, run
+                                 as theta_w^H, is not; 0: the Jacobi runs on theta_w    */,
   MPS_OPT_STEP_SPLIT = 13     /* block width 8: a Jacobi step launch that serves at most
                                  this many updates (default 4; 0: none) runs as two
                                  launches (partial Grams, then rotations and updates) of

@@ -769,7 +769,7 @@ int Scheduler::admit() {
           const StepCfg cfg = step_cfg(E, t.N);
           sl.bw = cfg.bw;
           sl.inner_few = cfg.inner_few;
-          if (g.k == 2 && cfg.qr) qr_select(dd, t);
+          if (cfg.qr) qr_select(dd, t);  // two-site updates and first splits of three-site gates
           if (t.qr) sl.state = 6;  // waits one tick for its QR factorisation
           mark(si);
           sl.M = t.M;
@@ -1119,7 +1119,7 @@ int Scheduler::finalise() {
     for (int u = 0; u < nu; ++u) std::memcpy(U[u]->dimx.data(), hdims + dims_off[u], sizeof(int) * (U[u]->n + 1));
     // first splits of three-site gates: the second split takes over in the reserved slot
     std::vector<mpsk::Ent> mids;
-    std::vector<int> newB;
+    std::vector<int> newB, qr2;
     int mN1 = 0, mK1 = 0, mNB = 0;
     for (int si : fl3) {
       Slot& sa = slot[si];
@@ -1138,6 +1138,11 @@ int Scheduler::finalise() {
       const StepCfg cfg = step_cfg(E, tb.N);
       sbl.bw = cfg.bw;
       sbl.inner_few = cfg.inner_few;
+      if (cfg.qr) qr_select(dd, tb);
+      if (tb.qr) {  // the second split's theta is factorised too, on stream3 after k_mid3
+        sbl.state = 6;
+        qr2.push_back(sb);
+      }
       sbl.Nt = tb.Nt;
       sbl.JM = tb.JM;
       gsweeps[sa.gate] = sa.fp64_sweeps;
@@ -1168,6 +1173,25 @@ int Scheduler::finalise() {
           e = mpsk::launch_fro(dt, eb, (int)newB.size(), mn, st);
         }
         if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("mid: ") + hipGetErrorString(e));
+      }
+      if (!qr2.empty()) {
+        int qM = 0, qN = 0;
+        for (int sb : qr2) {
+          qM = std::max(qM, ht[sb].M);
+          qN = std::max(qN, ht[sb].N);
+        }
+        if ((int)qr_inflight.size() >= kQrRing) HIPCHK(err, qr_poll(true));  // frees the oldest ring slot
+        mpsk::Ent* eq = upload_list(LQR0 + qr_ring, ents_of(qr2));
+        if (!eq) return fail(err, MPS_EDEVICE, "list upload failed");
+        qr_ring = (qr_ring + 1) % kQrRing;
+        HIPCHK(err, hipEventRecord(E->ev_qr, st));
+        HIPCHK(err, hipStreamWaitEvent(E->stream3, E->ev_qr, 0));
+        e = mpsk::launch_qr_factor(dt, eq, (int)qr2.size(), qM, qN, E->stream3);
+        if (e != hipSuccess) return fail(err, MPS_EDEVICE, std::string("qr: ") + hipGetErrorString(e));
+        hipEvent_t done = ev_get(E);
+        if (!done) return fail(err, MPS_EDEVICE, "event creation failed");
+        HIPCHK(err, hipEventRecord(done, E->stream3));
+        qr_inflight.push_back(QrBatch{done, qr2});
       }
     }
     // a released slot's workspace is reused only by launches queued after the
