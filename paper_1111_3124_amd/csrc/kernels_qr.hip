@@ -108,7 +108,7 @@ __global__ __launch_bounds__(256) void k_qr_colnorm(Task2* tasks, const Ent* ent
 template <int NW, int K>
 struct PanelLds {
   double red[NW][K], tot[K];
-  double2 rowc[kPanel];            // the pivot row of the panel (y's values at row c)
+  double2 rowc[2][kPanel];         // the pivot row of the panel (y's values at row c), by column parity
   double2 S[kPanel][kPanel + 1];  // S[i][j] = v_i^H v_j, i < j
   double2 Tm[kPanel][kPanel + 1];
   double ts[kPanel];
@@ -132,7 +132,7 @@ __device__ __forceinline__ void panel_columns(double2 (&y)[RPT][kPanel], PanelLd
         const int r = p0 + tid + NT * q;
         if (r == c)
 #pragma unroll
-          for (int jj = 0; jj < kPanel; ++jj) L.rowc[jj] = y[q][jj];
+          for (int jj = 0; jj < kPanel; ++jj) L.rowc[J & 1][jj] = y[q][jj];
         if (r < c || r >= M) continue;
         const double2 x = y[q][J];
         sm[0] = fma(x.x, x.x, fma(x.y, x.y, sm[0]));
@@ -147,7 +147,7 @@ __device__ __forceinline__ void panel_columns(double2 (&y)[RPT][kPanel], PanelLd
         }
       }
       block_sum64<K, NW>(sm, L.red, L.tot);
-      const double2 al = L.rowc[J];
+      const double2 al = L.rowc[J & 1][J];
       double2 beta = cmk(0.0, 0.0), v0 = cmk(0.0, 0.0);
       double t = 0.0;
       if (sm[0] > 0.0) {
@@ -167,21 +167,23 @@ __device__ __forceinline__ void panel_columns(double2 (&y)[RPT][kPanel], PanelLd
 #pragma unroll
         for (int jj = J + 1; jj < kPanel; ++jj) {
           if (jj >= nb) continue;
-          const double2 w = csub(cmk(sm[1 + 2 * jj], sm[2 + 2 * jj]), cmul(cb, L.rowc[jj]));
+          const double2 w = csub(cmk(sm[1 + 2 * jj], sm[2 + 2 * jj]), cmul(cb, L.rowc[J & 1][jj]));
           y[q][jj] = csub(y[q][jj], cscale(cmul(vr, w), t));
         }
         if (r == c) y[q][J] = beta;  // R[c][c]; the tail below stays the reflector
       }
       if (tid < J) {  // S[i][J] = v_i^H x - conj(v_i[c]) beta (totals read from LDS)
         const int i = tid;
-        L.S[i][J] = csub(cmk(L.tot[1 + 2 * i], L.tot[2 + 2 * i]), cmul(cconj(L.rowc[i]), beta));
+        L.S[i][J] = csub(cmk(L.tot[1 + 2 * i], L.tot[2 + 2 * i]), cmul(cconj(L.rowc[J & 1][i]), beta));
       }
       if (tid == 0) {
         L.ts[J] = t;
         T.qvd[c] = v0;
         T.qt[c] = t;
       }
-      __syncthreads();  // rowc is rewritten by the next column's owner
+      // no barrier here: the next column writes the other rowc buffer, and every
+      // thread has finished this column before the next column's block sum lets any
+      // thread past it (which is also when red and tot are rewritten)
     }
     panel_columns<J + 1, RPT, NW, K>(y, L, T, p0, nb, M);
   }
@@ -228,18 +230,20 @@ __global__ __launch_bounds__(NT) void k_qr_panel(Task2* tasks, const Ent* ents, 
     for (int j = 0; j < kPanel; ++j)
       if (j < nb) A[(long)pc[j] * M + r] = y[q][j];
   }
-  // T: T[j][j] = t_j, T[i][j] = -t_j sum_{l=i}^{j-1} T[i][l] S[l][j], a column at a time
+  // T: T[j][j] = t_j, T[i][j] = -t_j sum_{l=i}^{j-1} T[i][l] S[l][j].  Row i is formed
+  // by thread i alone, a column at a time: it reads only its own row and the finished
+  // S and t, so the columns need no barrier between them
   if (tid < kPanel * kPanel) L.Tm[tid / kPanel][tid % kPanel] = cmk(0.0, 0.0);
   __syncthreads();
-  for (int j = 0; j < nb; ++j) {
-    if (tid < j) {
+  if (tid < nb) {
+    L.Tm[tid][tid] = cmk(L.ts[tid], 0.0);
+    for (int j = tid + 1; j < nb; ++j) {
       double2 acc = cmk(0.0, 0.0);
       for (int l = tid; l < j; ++l) acc = cfma(L.Tm[tid][l], L.S[l][j], acc);
       L.Tm[tid][j] = cscale(acc, -L.ts[j]);
     }
-    if (tid == j) L.Tm[j][j] = cmk(L.ts[j], 0.0);
-    __syncthreads();
   }
+  __syncthreads();
   if (tid < kPanel * kPanel)
     T.qT[(long)(p0 / kPanel) * kPanel * kPanel + tid] = L.Tm[tid / kPanel][tid % kPanel];
 }
