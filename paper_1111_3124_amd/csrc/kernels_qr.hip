@@ -23,35 +23,56 @@ namespace {
 
 constexpr int kPanel = 16;
 
-// deterministic block sum of K doubles per thread (NW waves): butterfly within
-// each wave, then the waves' sums in wave order; every thread gets the totals
-template <int K, int NW>
-__device__ __forceinline__ void block_sum(double (&v)[K], double (&red)[NW][K], double (&tot)[K]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    double x = v[k];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    v[k] = x;
+// Cross-lane exchanges of one wavefront on the vector ALUs (no LDS traffic): the
+// value of lane l ^ 8, ^ 4, ^ 2 or ^ 1 by DPP row operations, and the two half-wave
+// swaps of gfx950.  Each moves the two 32-bit halves of a double.
+__device__ __forceinline__ double dbl(int lo, int hi) {
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int H>
+__device__ __forceinline__ double lane_xor(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = (int)b, hi = (int)(b >> 32);
+  if constexpr (H == 8) {  // row_ror:8
+    return dbl(__builtin_amdgcn_mov_dpp(lo, 0x128, 0xf, 0xf, false), __builtin_amdgcn_mov_dpp(hi, 0x128, 0xf, 0xf, false));
+  } else if constexpr (H == 4) {  // row_shl:4 into lanes with bit 2 clear, row_shr:4 into the others
+    int l2 = __builtin_amdgcn_update_dpp(lo, lo, 0x104, 0xf, 0x5, false);
+    int h2 = __builtin_amdgcn_update_dpp(hi, hi, 0x104, 0xf, 0x5, false);
+    l2 = __builtin_amdgcn_update_dpp(l2, lo, 0x114, 0xf, 0xa, false);
+    h2 = __builtin_amdgcn_update_dpp(h2, hi, 0x114, 0xf, 0xa, false);
+    return dbl(l2, h2);
+  } else if constexpr (H == 2) {  // quad_perm [2, 3, 0, 1]
+    return dbl(__builtin_amdgcn_mov_dpp(lo, 0x4e, 0xf, 0xf, false), __builtin_amdgcn_mov_dpp(hi, 0x4e, 0xf, 0xf, false));
+  } else {  // quad_perm [1, 0, 3, 2]
+    static_assert(H == 1, "lane_xor takes 8, 4, 2 or 1");
+    return dbl(__builtin_amdgcn_mov_dpp(lo, 0xb1, 0xf, 0xf, false), __builtin_amdgcn_mov_dpp(hi, 0xb1, 0xf, 0xf, false));
   }
-  if (lane == 0)
-#pragma unroll
-    for (int k = 0; k < K; ++k) red[wave][k] = v[k];
-  __syncthreads();
-  if ((int)threadIdx.x < K) {
-    double s = 0.0;
-    for (int w = 0; w < NW; ++w) s += red[w][threadIdx.x];
-    tot[threadIdx.x] = s;
+}
+// x + y over the pair (l, l ^ H) for H = 32 or 16 (v_permlane32_swap / v_permlane16_swap
+// exchange the upper half of x's lanes with the lower half of y's): lanes with bit H
+// clear get their x plus the partner's x, the others their y plus the partner's y
+template <int H>
+__device__ __forceinline__ double swap_add(double x, double y) {
+  const long long bx = __double_as_longlong(x), by = __double_as_longlong(y);
+  const unsigned xl = (unsigned)bx, xh = (unsigned)(bx >> 32), yl = (unsigned)by, yh = (unsigned)(by >> 32);
+  if constexpr (H == 32) {
+    const auto rl = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
+    const auto rh = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
+    return dbl(rl[0], rh[0]) + dbl(rl[1], rh[1]);
+  } else {
+    static_assert(H == 16, "swap_add takes 32 or 16");
+    const auto rl = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+    const auto rh = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
+    return dbl(rl[0], rh[0]) + dbl(rl[1], rh[1]);
   }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = tot[k];
 }
 
-// As block_sum for K <= 64, with a recursive-halving reduce-scatter inside each
-// wave (63 shuffles for any K, against 6 K for the butterfly): after the exchange
-// at distance 32, 16, ..., 1, lane l holds the wave's sum of value l.
+// Deterministic block sum of K <= 64 doubles per thread (NW waves): a recursive-halving
+// reduce-scatter inside each wave (63 lane exchanges for any K), after the exchange at
+// distance 32, 16, ..., 1 lane l holds the wave's sum of value l; then the waves' sums
+// in wave order; every thread gets the totals.  At each distance a lane adds its own
+// value and its partner's (IEEE addition commutes, so the order within a pair does not
+// matter).
 template <int K, int NW>
 __device__ __forceinline__ void block_sum64(double (&v)[K], double (&red)[NW][K], double (&tot)[K]) {
   static_assert(K <= 64, "block_sum64 takes at most 64 values");
@@ -59,16 +80,25 @@ __device__ __forceinline__ void block_sum64(double (&v)[K], double (&red)[NW][K]
   double a[64];
 #pragma unroll
   for (int k = 0; k < 64; ++k) a[k] = k < K ? v[k] : 0.0;
+  // distances 32 and 16: the lower half of the lanes keeps values [0, h), the upper [h, 2h)
 #pragma unroll
-  for (int h = 32; h >= 1; h >>= 1) {
+  for (int i = 0; i < 32; ++i) a[i] = swap_add<32>(a[i], a[32 + i]);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) a[i] = swap_add<16>(a[i], a[16 + i]);
+  auto level = [&](auto hc) {
+    constexpr int h = decltype(hc)::value;
     const bool up = (lane & h) != 0;  // keep the upper half of the live values
 #pragma unroll
     for (int i = 0; i < h; ++i) {
       const double send = up ? a[i] : a[h + i];
       const double keep = up ? a[h + i] : a[i];
-      a[i] = keep + __shfl_xor(send, h);
+      a[i] = keep + lane_xor<h>(send);
     }
-  }
+  };
+  level(std::integral_constant<int, 8>{});
+  level(std::integral_constant<int, 4>{});
+  level(std::integral_constant<int, 2>{});
+  level(std::integral_constant<int, 1>{});
   if (lane < K) red[wave][lane] = a[0];
   __syncthreads();
   if ((int)threadIdx.x < K) {
