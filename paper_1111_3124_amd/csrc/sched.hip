@@ -122,9 +122,11 @@ void carve(bool dd, Task2& t, char* w, int* d_flags, double* d_stats, double* d_
   w += align_up(((MN + mpsk::kFroChunk - 1) / mpsk::kFroChunk) * sizeof(double));
   t.qr = 0;
   t.JW = t.thw;
-  t.JV = t.V;
   t.JR = t.JM;
-  t.jvec = 1;
+  // V is accumulated where something reads it: the split's Z of a tall or square
+  // theta, and the dd refinement; a wide FP64 theta takes Z from W's columns
+  t.jvec = (dd || !t.tr) ? 1 : 0;
+  t.JV = t.jvec ? t.V : nullptr;
   // the split's right factor: V, or for a wide theta W itself (its kept columns are
   // scaled to unit norm after the truncation)
   t.Z = t.tr ? t.thw : t.V;
