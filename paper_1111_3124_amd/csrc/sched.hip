@@ -136,11 +136,12 @@ void carve(bool dd, Task2& t, char* w, int* d_flags, double* d_stats, double* d_
   t.fro2 = d_fro + slot;
 }
 
-// QR preconditioning of a two-site task (theta_w P = Q R, Jacobi on R^H): tall or
-// square thetas with 64 <= N and M <= 1024 (the panel kernel keeps at most two rows
-// a thread), and for double-double only square ones (their refinement then runs on
-// the transposed problem from the left singular vectors Q V).  FP64: the Jacobi's W
-// is R^H in V's storage, V is not accumulated, Z is formed in theta_w's storage.
+// QR preconditioning of a Jacobi problem (theta_w P = Q R, Jacobi on R^H): two-site
+// updates and either split of a three-site gate, tall or square thetas with 64 <= N
+// and M <= 1024 (the panel kernel keeps at most two rows a thread), and for
+// double-double only square ones (their refinement then runs on the transposed
+// problem from the left singular vectors Q V).  FP64: the Jacobi's W is R^H in V's
+// storage, V is not accumulated, Z is formed in theta_w's storage.
 void qr_select(bool dd, Task2& t) {
   if (t.tr || t.N < 64 || t.M > 1024 || t.N > kQrMaxN || (dd && t.M != t.N)) return;
   t.qr = 1;
