@@ -150,7 +150,9 @@ __global__ __launch_bounds__(256) void k_fro_sum(Task2* tasks, const Ent* ents) 
 //      neighbourhood of the old values (double-buffered).  With many blocks, a
 //      block's inner pairs are rotated at the sweep's first step and the later
 //      steps rotate only the pairs across the two blocks (BW rounds, not 2 BW - 1);
-//   3. A_P <- A_P R and V_P <- V_P R (a row per thread), sig2 <- diag(R^H G R).
+//   3. A_P <- A_P R and V_P <- V_P R (16-column pairs: half the rows in tiles of 16 on
+//      the matrix cores, half on the vector units; other widths: a row per thread),
+//      sig2 <- diag(R^H G R).
 // A pair whose off-diagonal entries are all below tol * sqrt(G_pp G_qq) is left
 // alone; a task whose previous sweep rotated nothing is converged and skipped.
 __device__ __forceinline__ int rr_player(int i, int r, int np) { return i == 0 ? 0 : 1 + (i - 1 + r) % (np - 1); }
@@ -183,12 +185,23 @@ struct InnerLds {
 // Partner of column x in an inner round: cross rounds pair x < H with H + (x + rnd)
 // mod H; the full round-robin holds column 0 at position 0 and column x > 0 at
 // position 1 + (x - 1 - rnd) mod (W2 - 1), position k meeting W2 - 1 - k.
+//
+// Branch-free (selects only, so that a round is one basic block the compiler can
+// schedule as a whole): rnd < W2 - 1 and H a power of two keep every intermediate
+// within one period.
 template <int W2>
 __device__ __forceinline__ int inner_partner(int x, int rnd, bool cross) {
   constexpr int H = W2 / 2, np1 = W2 - 1;
-  if (cross) return x < H ? H + (x + rnd) % H : (x - rnd) % H;
-  const int k = x == 0 ? 0 : 1 + ((x - 1 - rnd) % np1 + np1) % np1;
-  return rr_player(np1 - k, rnd, W2);
+  static_assert((H & (H - 1)) == 0, "H a power of two");
+  const bool lo = x < H;
+  const int pc = ((x + (lo ? rnd : -rnd)) & (H - 1)) + (lo ? H : 0);
+  int v = x - 1 - rnd;
+  v = v < 0 ? v + np1 : v;
+  const int m = np1 - (x == 0 ? 0 : 1 + v);  // the partner's position
+  int q = m - 1 + rnd;
+  q = q >= np1 ? q - np1 : q;
+  const int pf = m == 0 ? 0 : 1 + q;
+  return cross ? pc : pf;
 }
 
 // Rotation of one column pair (p < q) from the Gram entries al = G_pp, be = G_qq,
@@ -219,11 +232,15 @@ __device__ __forceinline__ RotCoef inner_coef(double al, double be, double2 g, b
   const double u = fabs(zeta) + x * rsq_nr(x);
   const double w = rsq_nr(fma(u, u, 1.0));
   const double c = u * w, sn = zeta < 0.0 ? -w : w;
-  const double2 e = cmk(g.x * ig, -g.y * ig);
+  const double ex = g.x * ig, ey = -g.y * ig;
+  // every candidate formed, then selected component by component (no branches)
+  const double cex = ex * c, cey = ey * c, sex = ex * -sn, sey = ey * -sn;
   RotCoef k;
   k.rot = rot ? 1 : 0;
-  k.ra = !rot ? cmk(1.0, 0.0) : (xp ? cmk(c, 0.0) : cscale(e, c));
-  k.rb = !rot ? cmk(0.0, 0.0) : (xp ? cscale(e, -sn) : cmk(sn, 0.0));
+  k.ra.x = rot ? (xp ? c : cex) : 1.0;
+  k.ra.y = rot ? (xp ? 0.0 : cey) : 0.0;
+  k.rb.x = rot ? (xp ? sex : sn) : 0.0;
+  k.rb.y = rot ? (xp ? sey : 0.0) : 0.0;
   return k;
 }
 
@@ -376,12 +393,178 @@ __device__ int inner_jacobi_block(double2 (&G)[2][W2][W2 + 1], double2 (&R)[2][W
   return cur;
 }
 
+// The same inner Jacobi with each column's coefficients formed once a round: W2
+// threads form them (column x from its pair's Gram entries, as in inner_jacobi_block)
+// and stage them in LDS; after a barrier every thread forms one element, of J^H G J
+// (the first W2^2 threads) or of R J (the next W2^2), from the staged coefficients by
+// the expressions of inner_jacobi_block.  Two barriers a round, but no thread forms a
+// rotation twice and the elements spread over all the block's waves.  The fused and
+// the split step both use it for 16-column pairs, so they form the same G and R.
+template <int W2, int NT>
+__device__ int inner_jacobi_staged(double2 (&G)[2][W2][W2 + 1], double2 (&R)[2][W2][W2 + 1], InnerLds<W2>& L,
+                                   StagedRot<W2>& K, const int (&cols)[W2], int inner, double tol, double ztol,
+                                   bool cross) {
+  constexpr int E = W2 * W2;
+  static_assert(NT >= W2, "one thread per column");
+  const int tid = threadIdx.x;
+  for (int e = tid; e < E; e += NT) R[0][e / W2][e % W2] = cmk(e / W2 == e % W2 ? 1.0 : 0.0, 0.0);
+  __syncthreads();
+  int cur = 0, any_rot = 0;
+  const int nrnd = cross ? W2 / 2 : W2 - 1;
+  for (int isw = 0; isw < inner; ++isw) {
+    int mine = 0;
+    for (int rnd = 0; rnd < nrnd; ++rnd) {
+      const double2(*Gc)[W2 + 1] = G[cur];
+      if (tid < W2) {  // column tid's coefficients in this round's unitary
+        const int x = tid, px = inner_partner<W2>(x, rnd, cross);
+        const bool xp = x < px;
+        const int p = xp ? x : px, q = xp ? px : x;
+        const bool v = (cols[x] >= 0) & (cols[px] >= 0);
+        const RotCoef c = inner_coef(Gc[p][p].x, Gc[q][q].x, Gc[p][q], v, xp, tol, ztol);
+        K.ra[x] = c.ra;
+        K.rb[x] = c.rb;
+        K.rot[x] = c.rot;
+        mine |= c.rot;
+      }
+      __syncthreads();
+      for (int e = tid; e < 2 * E; e += NT) {
+        const bool isG = e < E;
+        const int i = (e % E) / W2, j = e % W2;
+        const int pi_ = inner_partner<W2>(i, rnd, cross), pj = inner_partner<W2>(j, rnd, cross);
+        const double2 ra_j = K.ra[j], rb_j = K.rb[j];
+        if (isG) {
+          const double2 ra_i = K.ra[i], rb_i = K.rb[i];
+          const int rot_i = K.rot[i];
+          const double2 g_ij = Gc[i][j], g_iq = Gc[i][pj], g_pj = Gc[pi_][j], g_pq = Gc[pi_][pj];
+          const double2 colj = cadd(cmul(ra_j, g_ij), cmul(rb_j, g_iq));
+          const double2 colpj = cadd(cmul(ra_j, g_pj), cmul(rb_j, g_pq));
+          double2 v = cadd(cmul(cconj(ra_i), colj), cmul(cconj(rb_i), colpj));
+          if (rot_i && j == pi_) v = cmk(0.0, 0.0);  // the rotated pair's off-diagonal is zero
+          if (i == j) v.y = 0.0;
+          G[cur ^ 1][i][j] = v;
+        } else {
+          R[cur ^ 1][i][j] = cadd(cmul(ra_j, R[cur][i][j]), cmul(rb_j, R[cur][i][pj]));
+        }
+      }
+      cur ^= 1;
+      __syncthreads();
+    }
+    if (!__syncthreads_or(mine)) break;
+    any_rot = 1;
+  }
+  if (tid == 0) L.any_rot = any_rot;
+  __syncthreads();
+  return cur;
+}
+
+// A_P <- A_P R for 16-column pairs over the stacked rows (W's rows in tiles of 16 from
+// row 0, then V's), split between the two FP64 pipelines, whose peaks are equal: the
+// first half of the tiles on the matrix cores (rot_tiles), the rest on the vector units
+// (rot_rows), in different waves so that both issue at once.  Each row is formed by
+// the same instructions wherever it is computed, so the fused and split steps give the
+// same rows bit for bit.
+//
+// rot_tiles: per tile Y^T = R^T X^T as four k-steps of v_mfma_f64_16x16x4f64 over the
+// pair's columns, complex as
+//   Re Y^T = Re R^T Re X^T - Im R^T Im X^T,   Im Y^T = Im R^T Re X^T + Re R^T Im X^T.
+// R^T is the A operand (k-step s: lane l holds R[4 s + l / 16][l % 16]), loaded from LDS
+// once a block; X^T the B operand (lane l holds X[row0 + l % 16][column 4 s + l / 16]);
+// element r of lane l's result is Y[row0 + l % 16][column l / 16 + 4 r].  Each element
+// of X is loaded and stored by the same lane, so the update is in place.  R's rows and
+// columns for absent columns (cols < 0) are the identity's and their loads read zero.
+struct RotA {
+  double re[4], im[4];
+};
+
+__device__ __forceinline__ RotA rot_operand(const double2 (*R)[17], int lane) {
+  RotA a;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const double2 v = R[4 * s + (lane >> 4)][lane & 15];
+    a.re[s] = v.x;
+    a.im[s] = v.y;
+  }
+  return a;
+}
+
+// where stacked tile tt's row j lives
+struct TileRow {
+  double2* X;
+  int rows, r;
+};
+__device__ __forceinline__ TileRow tile_row(const Task2& T, int tt, int j) {
+  const int tw = (T.JR + 15) / 16;
+  const bool inW = tt < tw;
+  return TileRow{inW ? T.JW : T.JV, inW ? T.JR : T.N, 16 * (inW ? tt : tt - tw) + j};
+}
+
+// tiles t0, t0 + stride, ... below t1, four a group: the group's loads first, then
+// each tile's products and stores
+__device__ __forceinline__ void rot_tiles(const Task2& T, int t0, int t1, int stride, const int (&cols)[16],
+                                          const RotA& a, int lane) {
+  constexpr int G = 4;
+  const int j = lane & 15, kq = lane >> 4;
+  for (int t = t0; t < t1; t += G * stride) {
+    double2 x[G][4];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int tt = t + u * stride;
+      const TileRow w = tile_row(T, tt, j);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int c = cols[4 * s + kq];
+        x[u][s] = (tt < t1 && c >= 0 && w.r < w.rows) ? w.X[(long)c * w.rows + w.r] : cmk(0.0, 0.0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int tt = t + u * stride;
+      if (tt >= t1) break;
+      mfma_d4 yr = {0.0, 0.0, 0.0, 0.0}, yi = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        yr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re[s], x[u][s].x, yr, 0, 0, 0);
+        yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im[s], x[u][s].x, yi, 0, 0, 0);
+        yr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im[s], -x[u][s].y, yr, 0, 0, 0);
+        yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re[s], x[u][s].y, yi, 0, 0, 0);
+      }
+      const TileRow w = tile_row(T, tt, j);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = cols[kq + 4 * q];
+        if (c >= 0 && w.r < w.rows) w.X[(long)c * w.rows + w.r] = cmk(yr[q], yi[q]);
+      }
+    }
+  }
+}
+
+// rows of the stacked tiles [t0, t1), one a thread (threads i0, i0 + nth, ...): the row
+// times R on the vector units
+__device__ __forceinline__ void rot_rows(const Task2& T, int t0, int t1, int i0, int nth, const int (&cols)[16],
+                                         const double2 (*R)[17]) {
+  for (int e = i0; e < (t1 - t0) * 16; e += nth) {
+    const TileRow w = tile_row(T, t0 + e / 16, e % 16);
+    if (w.r >= w.rows) continue;
+    double2 x[16];
+#pragma unroll
+    for (int l = 0; l < 16; ++l) x[l] = cols[l] >= 0 ? w.X[(long)cols[l] * w.rows + w.r] : cmk(0.0, 0.0);
+#pragma unroll 4
+    for (int pc = 0; pc < 16; ++pc) {
+      double2 y = cmk(0.0, 0.0);
+#pragma unroll
+      for (int l = 0; l < 16; ++l) y = cfma(x[l], R[l][pc], y);
+      if (cols[pc] >= 0) w.X[(long)cols[pc] * w.rows + w.r] = y;
+    }
+  }
+}
+
 // One Jacobi step: blockIdx.x is a column-block pair (I, J) of the round-robin
 // schedule, blockIdx.y a task; 512 threads.  Rotating the pair's 2 BW columns:
 //   1. G = A_P^H A_P (W2 x W2, A_P = the pair's columns of W) from row chunks staged
 //      in LDS, D chunks of loads in flight;
 //   2. inner two-sided Jacobi on G (inner_jacobi_block), R accumulating the rotations;
-//   3. A_P <- A_P R and V_P <- V_P R (a row a thread), sig2 <- diag(R^H G R).
+//   3. A_P <- A_P R and V_P <- V_P R (16-column pairs: rot_tiles and rot_rows side by
+//      side; other widths: a row a thread), sig2 <- diag(R^H G R).
 template <int BW>
 __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* ents, int step, double tol_mult,
                                                         int maxin, int maxin_few, long long* phase_clock) {
@@ -631,6 +814,9 @@ __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* en
   if constexpr (W2 == 32) {
     __shared__ StagedRot<W2> K;
     cur = inner_jacobi_pairs<W2, NT>(Gb, Rb, L, K, cols, many ? maxin : maxin_few, tol, ztol, many && step > 0);
+  } else if constexpr (W2 == 16) {
+    __shared__ StagedRot<W2> K;
+    cur = inner_jacobi_staged<W2, NT>(Gb, Rb, L, K, cols, many ? maxin : maxin_few, tol, ztol, many && step > 0);
   } else {
     cur = inner_jacobi_block<W2, NT>(Gb, Rb, L, cols, many ? maxin : maxin_few, tol, ztol, many && step > 0);
   }
@@ -639,7 +825,17 @@ __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* en
 
   // 3. A_P <- A_P R and V_P <- V_P R over the JR + N rows (W's, then V's; W's alone
   //    when V is not accumulated)
-  if (res_rot) {
+  if constexpr (W2 == 16) {
+    if (res_rot) {  // waves 0-3: the first half of the tiles on MFMA; 4-7: the rest
+      const int tiles = (M + 15) / 16 + (T.jvec ? (N + 15) / 16 : 0);
+      const int tb = (tiles + 1) / 2;
+      if (wave < NW / 2)
+        rot_tiles(T, wave, tb, NW / 2, cols, rot_operand(Rb[cur], lane), lane);
+      else
+        rot_rows(T, tb, tiles, tid - NT / 2, NT / 2, cols, Rb[cur]);
+      if (tid == 0) flags[sweep % 3] = 1;
+    }
+  } else if (res_rot) {
     const int total = M + (T.jvec ? N : 0);
     {
       const double2(*R)[W2 + 1] = Rb[cur];
@@ -691,8 +887,8 @@ __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* en
 //   k_jacobi_gram: the half's partial Gram of the pair's columns of W over its rows
 //     (MFMA as in the fused kernel; Re part and P = Xr^T Xi part) into JG;
 //   k_jacobi_rot: both halves' partials added (h = 0 first), so that both blocks of a
-//     pair form the same G, the same inner Jacobi and the same R; each block updates
-//     its half of the W and V rows.
+//     pair form the same G, the same inner Jacobi and the same R; block h = 0 updates
+//     the first half of the 16-row tiles of W and V (rot_tiles), h = 1 the rest (rot_rows).
 // The launch boundary orders every Gram read of a step before its updates.
 namespace {
 constexpr int kSplitNT = 256;
@@ -803,28 +999,15 @@ __global__ __launch_bounds__(256) void k_jacobi_rot(Task2* tasks, const Ent* ent
   const double tol = tol_mult * (double)(M > 16 ? M : 16) * 0x1p-53;
   const double ztol = fro2 * 0x1p-88;
   const bool many = nbp >= 16;
-  const int cur = inner_jacobi_block<W2, NT>(Gb, Rb, L, cols, many ? maxin : maxin_few, tol, ztol, many && step > 0);
-  if (L.any_rot) {
-    const int total = M + (T.jvec ? N : 0);
-    const int Th = (total + 1) / 2;
-    const int r_beg = h * Th, r_end = min(total, r_beg + Th);
-    const double2(*R)[W2 + 1] = Rb[cur];
-    for (int rr = r_beg + tid; rr < r_end; rr += NT) {
-      const bool inA = rr < M;
-      double2* X = inA ? T.JW : T.JV;
-      const int rows = inA ? M : N;
-      const int r = inA ? rr : rr - M;
-      double2 x[W2];
-#pragma unroll
-      for (int l = 0; l < W2; ++l) x[l] = cols[l] >= 0 ? X[(long)cols[l] * rows + r] : cmk(0.0, 0.0);
-#pragma unroll 4
-      for (int pc = 0; pc < W2; ++pc) {
-        double2 y = cmk(0.0, 0.0);
-#pragma unroll
-        for (int l = 0; l < W2; ++l) y = cfma(x[l], R[l][pc], y);
-        if (cols[pc] >= 0) X[(long)cols[pc] * rows + r] = y;
-      }
-    }
+  __shared__ StagedRot<W2> K;
+  const int cur = inner_jacobi_staged<W2, NT>(Gb, Rb, L, K, cols, many ? maxin : maxin_few, tol, ztol, many && step > 0);
+  if (L.any_rot) {  // h = 0: the first half of the tiles (MFMA), h = 1: the rest
+    const int tiles = (M + 15) / 16 + (T.jvec ? (N + 15) / 16 : 0);
+    const int tb = (tiles + 1) / 2;
+    if (h == 0)
+      rot_tiles(T, tid >> 6, tb, NT / 64, cols, rot_operand(Rb[cur], tid & 63), tid & 63);
+    else
+      rot_rows(T, tb, tiles, tid, NT, cols, Rb[cur]);
     if (tid == 0) T.flags[sweep % 3] = 1;
   }
   if (h == 0 && tid < W2 && cols[tid] >= 0) T.sig2[cols[tid]] = Gb[cur][tid][tid].x;
