@@ -105,6 +105,12 @@ struct Task2 {
   // the split Jacobi step's partial Grams: per column-block pair and row half, the
   // 16 x 16 Re part and P = Xr^T Xi part (2 x 2 x 256 doubles a pair)
   double* JG;
+  // V's rotations deferred by one step (fused step, block width 8): per step parity and
+  // column-block pair, R (16 x 16, row-major) in VPR and in VPC the pair's 16 columns
+  // and a tag (one more than the global step g = sweep * steps + step that wrote it;
+  // 0 once applied or when nothing rotated)
+  double2* VPR;
+  int* VPC;
   // QR preconditioning (qr = 1): column order, reflector heads, scales, panel factors
   int qr;
   int* qperm;

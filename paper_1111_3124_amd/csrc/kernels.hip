@@ -29,6 +29,10 @@ __global__ __launch_bounds__(256) void k_prep2(Task2* tasks, const Ent* ents) {
   }
   if (blockIdx.x == 0)
     for (int j = threadIdx.x; j < N; j += 256) T.perm[j] = j;  // the first sweep's column order
+  // no deferred V rotation pending (the workspace may hold another task's data; the
+  // tags a task writes grow with its steps, so none of its own can match a later one)
+  if (blockIdx.x == 0)
+    for (int j = threadIdx.x; j < 2 * (((N + 7) / 8 + 2) / 2); j += 256) T.VPC[j * 17 + 16] = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *T.fro2 = 0.0;
     T.flags[0] = T.flags[1] = T.flags[2] = 0;
@@ -487,33 +491,39 @@ __device__ __forceinline__ RotA rot_operand(const double2 (*R)[17], int lane) {
   return a;
 }
 
-// where stacked tile tt's row j lives
-struct TileRow {
-  double2* X;
-  int rows, r;
+// The rows an update rotates: W (Mw rows) and V (Nv rows; either may be absent, with 0
+// rows).  Each matrix's first half of 16-row tiles (hw, hv tiles) goes to the matrix
+// cores, its remaining rows to the vector units, wherever it is updated, so every row
+// is formed by the same instructions in the fused step, the split step and the
+// deferred V update.  The matrix-core part is indexed as W's tiles, then V's; the
+// vector part as W's remaining rows, then V's.
+struct RotSet {
+  double2* W;
+  double2* V;
+  int Mw, Nv, hw, hv;
 };
-__device__ __forceinline__ TileRow tile_row(const Task2& T, int tt, int j) {
-  const int tw = (T.JR + 15) / 16;
-  const bool inW = tt < tw;
-  return TileRow{inW ? T.JW : T.JV, inW ? T.JR : T.N, 16 * (inW ? tt : tt - tw) + j};
+__device__ __forceinline__ RotSet rot_set(double2* W, int Mw, double2* V, int Nv) {
+  return RotSet{W, V, Mw, Nv, ((Mw + 15) / 16 + 1) / 2, ((Nv + 15) / 16 + 1) / 2};
 }
 
-// tiles t0, t0 + stride, ... below t1, four a group: the group's loads first, then
-// each tile's products and stores
-__device__ __forceinline__ void rot_tiles(const Task2& T, int t0, int t1, int stride, const int (&cols)[16],
-                                          const RotA& a, int lane) {
+// matrix-core tiles t0, t0 + stride, ... below hw + hv, four a group: the group's loads
+// first, then each tile's products and stores
+__device__ __forceinline__ void rot_tiles(const RotSet& S, int t0, int stride, const int (&cols)[16], const RotA& a,
+                                          int lane) {
   constexpr int G = 4;
-  const int j = lane & 15, kq = lane >> 4;
+  const int j = lane & 15, kq = lane >> 4, t1 = S.hw + S.hv;
   for (int t = t0; t < t1; t += G * stride) {
     double2 x[G][4];
 #pragma unroll
     for (int u = 0; u < G; ++u) {
       const int tt = t + u * stride;
-      const TileRow w = tile_row(T, tt, j);
+      const bool inW = tt < S.hw;
+      double2* X = inW ? S.W : S.V;
+      const int rows = inW ? S.Mw : S.Nv, r = 16 * (inW ? tt : tt - S.hw) + j;
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int c = cols[4 * s + kq];
-        x[u][s] = (tt < t1 && c >= 0 && w.r < w.rows) ? w.X[(long)c * w.rows + w.r] : cmk(0.0, 0.0);
+        x[u][s] = (tt < t1 && c >= 0 && r < rows) ? X[(long)c * rows + r] : cmk(0.0, 0.0);
       }
     }
 #pragma unroll
@@ -528,34 +538,78 @@ __device__ __forceinline__ void rot_tiles(const Task2& T, int t0, int t1, int st
         yr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im[s], -x[u][s].y, yr, 0, 0, 0);
         yi = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re[s], x[u][s].y, yi, 0, 0, 0);
       }
-      const TileRow w = tile_row(T, tt, j);
+      const bool inW = tt < S.hw;
+      double2* X = inW ? S.W : S.V;
+      const int rows = inW ? S.Mw : S.Nv, r = 16 * (inW ? tt : tt - S.hw) + j;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int c = cols[kq + 4 * q];
-        if (c >= 0 && w.r < w.rows) w.X[(long)c * w.rows + w.r] = cmk(yr[q], yi[q]);
+        // recomputed, not kept from the loads (16 live 64-bit addresses would cost
+        // the block its second slot on the CU)
+        long off = (long)c * rows + r;
+        __asm__ volatile("" : "+v"(off));
+        if (c >= 0 && r < rows) X[off] = cmk(yr[q], yi[q]);
       }
     }
   }
 }
 
-// rows of the stacked tiles [t0, t1), one a thread (threads i0, i0 + nth, ...): the row
-// times R on the vector units
-__device__ __forceinline__ void rot_rows(const Task2& T, int t0, int t1, int i0, int nth, const int (&cols)[16],
+// the vector units' rows, one a thread (threads i0, i0 + nth, ...): the row times R
+__device__ __forceinline__ void rot_rows(const RotSet& S, int i0, int nth, const int (&cols)[16],
                                          const double2 (*R)[17]) {
-  for (int e = i0; e < (t1 - t0) * 16; e += nth) {
-    const TileRow w = tile_row(T, t0 + e / 16, e % 16);
-    if (w.r >= w.rows) continue;
+  const int rw = S.Mw > 16 * S.hw ? S.Mw - 16 * S.hw : 0, rv = S.Nv > 16 * S.hv ? S.Nv - 16 * S.hv : 0;
+  for (int e = i0; e < rw + rv; e += nth) {
+    const bool inW = e < rw;
+    double2* X = inW ? S.W : S.V;
+    const int rows = inW ? S.Mw : S.Nv, r = inW ? 16 * S.hw + e : 16 * S.hv + e - rw;
     double2 x[16];
 #pragma unroll
-    for (int l = 0; l < 16; ++l) x[l] = cols[l] >= 0 ? w.X[(long)cols[l] * w.rows + w.r] : cmk(0.0, 0.0);
+    for (int l = 0; l < 16; ++l) x[l] = cols[l] >= 0 ? X[(long)cols[l] * rows + r] : cmk(0.0, 0.0);
 #pragma unroll 4
     for (int pc = 0; pc < 16; ++pc) {
       double2 y = cmk(0.0, 0.0);
 #pragma unroll
       for (int l = 0; l < 16; ++l) y = cfma(x[l], R[l][pc], y);
-      if (cols[pc] >= 0) w.X[(long)cols[pc] * w.rows + w.r] = y;
+      if (cols[pc] >= 0) X[(long)cols[pc] * rows + r] = y;
     }
   }
+}
+
+// the set's update by a whole 512-thread block: matrix-core part by waves 0-3, vector
+// part by waves 4-7
+__device__ __forceinline__ void rot_update(const RotSet& S, const int (&cols)[16], const double2 (*R)[17]) {
+  const int tid = threadIdx.x;
+  if (tid < 256)
+    rot_tiles(S, tid >> 6, 4, cols, rot_operand(R, tid & 63), tid & 63);
+  else
+    rot_rows(S, tid - 256, 256, cols, R);
+}
+
+// entry of Task2::VPR / VPC written by pair `pair` at global step g (two step parities
+// of ((N + 7) / 8 + 2) / 2 pairs each, enough for the padded block count)
+__device__ __forceinline__ long vp_entry(int N, int g, int pair) {
+  return (long)(g & 1) * (((N + 7) / 8 + 2) / 2) + pair;
+}
+
+// V's deferred rotation of pair pv at global step g (see Task2::VPR): the rotation
+// the pair's block stored at step g - 1, applied to V if its tag says so, then marked
+// as applied.  A whole 512-thread block; R and cols staged in LDS.
+__device__ __forceinline__ void apply_deferred_v(const Task2& T, int pv, int g, double2 (*R)[17], int (&cols)[16]) {
+  const int tid = threadIdx.x;
+  if (g < 1) return;
+  const long e = vp_entry(T.N, g - 1, pv);
+  int* c = T.VPC + e * 17;
+  // the entry's columns and R loaded together with its tag (one memory latency, not
+  // two; the entry lies in the task's workspace whatever the tag says)
+  const int cl = tid < 16 ? c[tid] : 0;
+  const double2 rv = tid < 256 ? T.VPR[e * 256 + tid] : cmk(0.0, 0.0);
+  if (c[16] != g) return;  // (uniform: every thread reads the same tag)
+  if (tid < 16) cols[tid] = cl;
+  if (tid < 256) R[tid / 16][tid % 16] = rv;
+  __syncthreads();
+  rot_update(rot_set(nullptr, 0, T.JV, T.N), cols, R);
+  __syncthreads();
+  if (tid == 0) c[16] = 0;
 }
 
 // One Jacobi step: blockIdx.x is a column-block pair (I, J) of the round-robin
@@ -565,9 +619,15 @@ __device__ __forceinline__ void rot_rows(const Task2& T, int t0, int t1, int i0,
 //   2. inner two-sided Jacobi on G (inner_jacobi_block), R accumulating the rotations;
 //   3. A_P <- A_P R and V_P <- V_P R (16-column pairs: rot_tiles and rot_rows side by
 //      side; other widths: a row a thread), sig2 <- diag(R^H G R).
+//   Block width 8: V_P's update waits one step.  The pair's block stores R, and a
+//   second set of blocks in the grid, one a pair (`defer`: the host sets it for every
+//   launch that holds a task accumulating V), applies the previous step's stored
+//   rotations to V while the pairs' blocks run; a flush applies the last step's.  V's
+//   rows are formed by the same instructions as in the split step, which updates V at
+//   once.
 template <int BW>
 __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* ents, int step, double tol_mult,
-                                                        int maxin, int maxin_few, long long* phase_clock) {
+                                                        int maxin, int maxin_few, int defer, long long* phase_clock) {
   constexpr int NT = 512, NW = NT / 64;
   constexpr int W2 = 2 * BW;
   constexpr int TB = W2 / 8;
@@ -581,19 +641,25 @@ __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* en
   const int N = T.N, M = T.JR;
   const int nb = (N + BW - 1) / BW;
   const int nbp = nb + (nb & 1);
-  const int pi = blockIdx.x;
-  if (step >= nbp - 1 || pi >= nbp / 2) return;
-  int* flags = T.flags;
   const int tid = threadIdx.x;
-  // slot (sweep+1)%3 is neither read nor written during this sweep: clear it for the
-  // next one (also for converged tasks, whose later sweeps must read 0)
-  if (step == 0 && pi == 0 && tid == 0) flags[(sweep + 1) % 3] = 0;
-  if (sweep > 0 && flags[(sweep + 2) % 3] == 0) return;
-
   __shared__ int cols[W2];
   __shared__ double2 Gb[2][W2][W2 + 1];
   __shared__ double2 Rb[2][W2][W2 + 1];
   __shared__ InnerLds<W2> L;
+  if constexpr (W2 == 16) {
+    if (defer && (int)blockIdx.x >= (int)gridDim.x / 2) {  // V's rotations of the previous step
+      const int pv = blockIdx.x - gridDim.x / 2;
+      if (T.jvec && pv < nbp / 2) apply_deferred_v(T, pv, sweep * (nbp - 1) + min(step, nbp - 1), Rb[0], cols);
+      return;
+    }
+  }
+  const int pi = blockIdx.x;
+  if (step >= nbp - 1 || pi >= nbp / 2) return;
+  int* flags = T.flags;
+  // slot (sweep+1)%3 is neither read nor written during this sweep: clear it for the
+  // next one (also for converged tasks, whose later sweeps must read 0)
+  if (step == 0 && pi == 0 && tid == 0) flags[(sweep + 1) % 3] = 0;
+  if (sweep > 0 && flags[(sweep + 2) % 3] == 0) return;
 
   const bool clk = phase_clock && pi == 0 && blockIdx.y == 0 && tid == 0;
   if (clk) phase_clock[0] = wall_clock64();
@@ -826,14 +892,16 @@ __global__ __launch_bounds__(512) void k_jacobi_step(Task2* tasks, const Ent* en
   // 3. A_P <- A_P R and V_P <- V_P R over the JR + N rows (W's, then V's; W's alone
   //    when V is not accumulated)
   if constexpr (W2 == 16) {
-    if (res_rot) {  // waves 0-3: the first half of the tiles on MFMA; 4-7: the rest
-      const int tiles = (M + 15) / 16 + (T.jvec ? (N + 15) / 16 : 0);
-      const int tb = (tiles + 1) / 2;
-      if (wave < NW / 2)
-        rot_tiles(T, wave, tb, NW / 2, cols, rot_operand(Rb[cur], lane), lane);
-      else
-        rot_rows(T, tb, tiles, tid - NT / 2, NT / 2, cols, Rb[cur]);
+    if (res_rot) {
+      rot_update(rot_set(T.JW, M, nullptr, 0), cols, Rb[cur]);
       if (tid == 0) flags[sweep % 3] = 1;
+    }
+    if (T.jvec) {  // V's update left to the next step's blocks (or the flush)
+      const int g = sweep * (nbp - 1) + step;
+      const long e = vp_entry(N, g, pi);
+      if (tid < 256) T.VPR[e * 256 + tid] = Rb[cur][tid / 16][tid % 16];
+      if (tid < 16) T.VPC[e * 17 + tid] = cols[tid];
+      if (tid == 0) T.VPC[e * 17 + 16] = res_rot ? g + 1 : 0;
     }
   } else if (res_rot) {
     const int total = M + (T.jvec ? N : 0);
@@ -1001,13 +1069,12 @@ __global__ __launch_bounds__(256) void k_jacobi_rot(Task2* tasks, const Ent* ent
   const bool many = nbp >= 16;
   __shared__ StagedRot<W2> K;
   const int cur = inner_jacobi_staged<W2, NT>(Gb, Rb, L, K, cols, many ? maxin : maxin_few, tol, ztol, many && step > 0);
-  if (L.any_rot) {  // h = 0: the first half of the tiles (MFMA), h = 1: the rest
-    const int tiles = (M + 15) / 16 + (T.jvec ? (N + 15) / 16 : 0);
-    const int tb = (tiles + 1) / 2;
+  if (L.any_rot) {  // h = 0: the matrix-core part of W's and V's update, h = 1: the vector part
+    const RotSet S = rot_set(T.JW, M, T.jvec ? T.JV : nullptr, T.jvec ? N : 0);
     if (h == 0)
-      rot_tiles(T, tid >> 6, tb, NT / 64, cols, rot_operand(Rb[cur], tid & 63), tid & 63);
+      rot_tiles(S, tid >> 6, NT / 64, cols, rot_operand(Rb[cur], tid & 63), tid & 63);
     else
-      rot_rows(T, tb, tiles, tid, NT, cols, Rb[cur]);
+      rot_rows(S, tid, NT, cols, Rb[cur]);
     if (tid == 0) T.flags[sweep % 3] = 1;
   }
   if (h == 0 && tid < W2 && cols[tid] >= 0) T.sig2[cols[tid]] = Gb[cur][tid][tid].x;
@@ -1298,18 +1365,38 @@ hipError_t launch_theta2(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, 
 }
 
 hipError_t launch_jacobi_step(Task2* d_tasks, const Ent* d_ents, int nent, int maxN, int bw, int step,
-                              double tol_mult, int maxin, int maxin_few, hipStream_t st, long long* phase_clock) {
+                              double tol_mult, int maxin, int maxin_few, int defer, hipStream_t st,
+                              long long* phase_clock) {
   const int nb = (maxN + bw - 1) / bw;
-  const dim3 grid((nb + (nb & 1)) / 2, nent);
+  if (defer && bw != 8) return hipErrorInvalidValue;
+  const dim3 grid((nb + (nb & 1)) / 2 * (defer ? 2 : 1), nent);
   switch (bw) {
     case 4: hipLaunchKernelGGL(k_jacobi_step<4>, grid, dim3(512), 0, st, d_tasks, d_ents, step, tol_mult, maxin,
-                                   maxin_few, phase_clock); break;
+                                   maxin_few, 0, phase_clock); break;
     case 8: hipLaunchKernelGGL(k_jacobi_step<8>, grid, dim3(512), 0, st, d_tasks, d_ents, step, tol_mult, maxin,
-                                   maxin_few, phase_clock); break;
+                                   maxin_few, defer, phase_clock); break;
     case 16: hipLaunchKernelGGL(k_jacobi_step<16>, grid, dim3(512), 0, st, d_tasks, d_ents, step, tol_mult, maxin,
-                                   maxin_few, phase_clock); break;
+                                   maxin_few, 0, phase_clock); break;
     default: return hipErrorInvalidValue;
   }
+  MPS_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+// V's rotations left by the last step of each listed task's sweep
+__global__ __launch_bounds__(512) void k_jacobi_vflush(Task2* tasks, const Ent* ents) {
+  __shared__ int cols[16];
+  __shared__ double2 R[16][17];
+  const Task2& T = tasks[ents[blockIdx.y].slot];
+  const int nb = (T.N + 7) / 8, nbp = nb + (nb & 1);
+  const int pv = blockIdx.x;
+  if (!T.jvec || pv >= nbp / 2) return;
+  apply_deferred_v(T, pv, (ents[blockIdx.y].sweep + 1) * (nbp - 1), R, cols);
+}
+
+hipError_t launch_jacobi_vflush(Task2* d_tasks, const Ent* d_ents, int nent, int maxN, hipStream_t st) {
+  const int nb = (maxN + 7) / 8;
+  hipLaunchKernelGGL(k_jacobi_vflush, dim3((nb + (nb & 1)) / 2, nent), dim3(512), 0, st, d_tasks, d_ents);
   MPS_LAUNCH_CHECK();
   return hipSuccess;
 }

@@ -20,8 +20,13 @@ hipError_t launch_fro(Task2* d_tasks, const Ent* d_ents, int nent, long maxMN, h
 hipError_t launch_theta2(Task2* d_tasks, const Ent* d_ents, int nent, int maxM, int maxN, hipStream_t st);
 // phase_clock: NULL, or 5 long longs receiving wall_clock64() stamps of block (0, 0)
 // (start, after Gram, after inner Jacobi, end, rotated?) for phase profiling
+// defer (block width 8): V's update of each step is left to the next step's launch,
+// whose grid then holds a second block a pair; launch_jacobi_vflush applies the last
+// step's after a launch sequence
 hipError_t launch_jacobi_step(Task2* d_tasks, const Ent* d_ents, int nent, int maxN, int bw, int step, double tol_mult,
-                              int maxin, int maxin_few, hipStream_t st, long long* phase_clock = nullptr);
+                              int maxin, int maxin_few, int defer, hipStream_t st, long long* phase_clock = nullptr);
+// V's rotations still deferred after the listed tasks' sweep (the list of that sweep)
+hipError_t launch_jacobi_vflush(Task2* d_tasks, const Ent* d_ents, int nent, int maxN, hipStream_t st);
 // the same step as two launches (partial Grams, then rotations and updates) of two
 // 256-thread blocks a column-block pair; block width 8
 hipError_t launch_jacobi_split(Task2* d_tasks, const Ent* d_ents, int nent, int maxN, int step, double tol_mult,

@@ -44,6 +44,8 @@ struct Slot {
 // partial Grams of the split Jacobi step (block width 8): the pairs of the padded
 // block count, two row halves, two 16 x 16 parts
 size_t jg_doubles(int N) { return (size_t)((N + 7) / 8 + 2) / 2 * 2 * 2 * 256; }
+// V's deferred rotations: two step parities of the pairs of the padded block count
+size_t vp_pairs(int N) { return (size_t)((N + 7) / 8 + 2) / 2 * 2; }
 
 size_t task_ws_bytes(bool dd, int M, int Nt, int t1) {
   const int N = std::min(M, Nt), P = dd ? 2 : 1;
@@ -56,6 +58,7 @@ size_t task_ws_bytes(bool dd, int M, int Nt, int t1) {
   b += align_up(N * sizeof(int)) + align_up(N * sizeof(double2)) + align_up(N * sizeof(double)) +
        align_up((size_t)((N + 15) / 16) * 256 * sizeof(double2));
   b += align_up(jg_doubles(N) * sizeof(double));  // split Jacobi step: partial Grams
+  b += align_up(vp_pairs(N) * 256 * sizeof(double2)) + align_up(vp_pairs(N) * 17 * sizeof(int));  // deferred V
   b += align_up(((MN + mpsk::kFroChunk - 1) / mpsk::kFroChunk) * sizeof(double));  // ||theta_w||^2 partials
   return b;
 }
@@ -118,6 +121,10 @@ void carve(bool dd, Task2& t, char* w, int* d_flags, double* d_stats, double* d_
   w += align_up((size_t)((t.N + 15) / 16) * 256 * sizeof(double2));
   t.JG = (double*)w;
   w += align_up(jg_doubles(t.N) * sizeof(double));
+  t.VPR = (double2*)w;
+  w += align_up(vp_pairs(t.N) * 256 * sizeof(double2));
+  t.VPC = (int*)w;
+  w += align_up(vp_pairs(t.N) * 17 * sizeof(int));
   t.frop = (double*)w;
   w += align_up(((MN + mpsk::kFroChunk - 1) / mpsk::kFroChunk) * sizeof(double));
   t.qr = 0;
@@ -220,6 +227,7 @@ struct SweepGroup {
   int oa = 0, ob = 0;  // their offsets in the sweep's half lists
   int mNa = 0, mNb = 0;
   bool split_a = false, split_b = false;
+  bool defer_a = false, defer_b = false;  // fused steps with V's rotations deferred
 };
 
 struct SweepPlan {
@@ -257,13 +265,15 @@ hipError_t enqueue_sweeps(Engine* E, Task2* dt, const SweepPlan& P, hipStream_t 
     }
     for (int stp = 0; stp < nsteps; ++stp) {
       for (const SweepGroup& g : P.groups) {
-        long long* pc = (P.phase && k == 0 && stp == nsteps / 2 && &g == &P.groups[0]) ? P.phase : nullptr;
+        // (one-launch steps only: the two-launch form has no stamps)
+        long long* pc =
+            (P.phase && k == 0 && stp == nsteps / 2 && &g == &P.groups[0] && !g.split_a) ? P.phase : nullptr;
         if (g.na && stp < steps_of(g.mNa, g.bw)) {
-          e = (g.split_a && !pc)
+          e = g.split_a
                   ? mpsk::launch_jacobi_split(dt, P.la[k] + g.oa, g.na, g.mNa, stp, E->tol_mult, E->max_inner,
                                               g.inner_few, st)
                   : mpsk::launch_jacobi_step(dt, P.la[k] + g.oa, g.na, g.mNa, g.bw, stp, E->tol_mult, E->max_inner,
-                                             g.inner_few, st, pc);
+                                             g.inner_few, g.defer_a, st, pc);
           if (e != hipSuccess) return e;
         }
         if (g.nb && stp < steps_of(g.mNb, g.bw)) {
@@ -271,9 +281,17 @@ hipError_t enqueue_sweeps(Engine* E, Task2* dt, const SweepPlan& P, hipStream_t 
           e = g.split_b ? mpsk::launch_jacobi_split(dt, P.lb[k] + g.ob, g.nb, g.mNb, stp, E->tol_mult, E->max_inner,
                                                     g.inner_few, s2)
                         : mpsk::launch_jacobi_step(dt, P.lb[k] + g.ob, g.nb, g.mNb, g.bw, stp, E->tol_mult,
-                                                   E->max_inner, g.inner_few, s2, nullptr);
+                                                   E->max_inner, g.inner_few, g.defer_b, s2, nullptr);
           if (e != hipSuccess) return e;
         }
+      }
+    }
+    if (k == P.K - 1) {  // V's rotations still deferred after the last step
+      for (const SweepGroup& g : P.groups) {
+        if (g.defer_a && (e = mpsk::launch_jacobi_vflush(dt, P.la[k] + g.oa, g.na, g.mNa, st)) != hipSuccess) return e;
+        if (g.defer_b &&
+            (e = mpsk::launch_jacobi_vflush(dt, P.lb[k] + g.ob, g.nb, g.mNb, P.two ? E->stream2 : st)) != hipSuccess)
+          return e;
       }
     }
     if (P.two) {
@@ -295,7 +313,8 @@ std::vector<long long> graph_key(const Engine* E, const Task2* dt, const SweepPl
   for (int i = 0; i < P.K; ++i)
     for (const mpsk::Ent* l : {P.la[i], P.lb[i], P.lo[i]}) k.push_back((long long)(uintptr_t)l);
   for (const SweepGroup& g : P.groups)
-    for (long long v : {g.bw, g.inner_few, g.na, g.nb, g.oa, g.ob, g.mNa, g.mNb, (int)g.split_a, (int)g.split_b})
+    for (long long v : {g.bw, g.inner_few, g.na, g.nb, g.oa, g.ob, g.mNa, g.mNb, (int)g.split_a, (int)g.split_b,
+                        (int)g.defer_a, (int)g.defer_b})
       k.push_back(v);
   return k;
 }
@@ -613,6 +632,15 @@ hipError_t Scheduler::launch_jacobi(const std::vector<int>& jl, int K) {
     for (int si : gb[gi]) g.mNb = std::max(g.mNb, slot[si].N);
     g.split_a = g.bw == 8 && g.na <= E->split_max;
     g.split_b = g.bw == 8 && g.nb <= E->split_max;
+    auto any_v = [&](const std::vector<int>& v) {
+      for (int si : v)
+        if (ht[si].jvec) return true;
+      return false;
+    };
+    // the one-launch step of block width 8 defers V's rotations by a step (its launches
+    // then carry the V blocks)
+    g.defer_a = g.bw == 8 && !g.split_a && any_v(ga[gi]);
+    g.defer_b = g.bw == 8 && !g.split_b && any_v(gb[gi]);
     all_a.insert(all_a.end(), ga[gi].begin(), ga[gi].end());
     all_b.insert(all_b.end(), gb[gi].begin(), gb[gi].end());
     P.groups.push_back(g);

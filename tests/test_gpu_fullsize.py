@@ -61,17 +61,22 @@ def test_update_chi256(B, fixture, prec, tol, bw):
     assert err <= tol * scale
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_update_chi256_split_step_bit_identical(B, fixture, prec):
+@pytest.mark.parametrize("prec,qr", [(0, 1), (1, 1), (0, 0)])
+def test_update_chi256_split_step_bit_identical(B, fixture, prec, qr):
     """The Jacobi step as one fused launch or as the two-launch split form (used for
-    launches of few updates) forms the same Gram in the same order: the update's
-    Schmidt values and amplitudes agree bit for bit."""
+    launches of few updates) forms the same Gram in the same order and every row of W
+    and V by the same instructions; the fused form applies V's rotation one step late
+    (extra blocks of the next launch, then a flush), the split form at once.  The
+    update's Schmidt values and amplitudes agree bit for bit.  V is accumulated by dd
+    updates and by FP64 ones without QR preconditioning."""
     _, inp = fixture
-    print(f"split vs fused step: prec={prec} n={inp['n']} site={inp['first']}", flush=True)
+    print(f"split vs fused step: prec={prec} qr={qr} n={inp['n']} site={inp['first']}", flush=True)
     out = []
     for limit in (0, 4):
         d = B.MPS(inp["n"], inp["chi"], inp["eps"], prec)
         d.set_option(B.MPS_OPT_STEP_SPLIT, limit)
+        if not qr:
+            d.set_option(B.MPS_OPT_QR, 0)
         d.load(inp["B"], inp["lam"])
         d.apply(inp["first"], 2, inp["U"])
         lam = d.schmidt_dd(inp["first"]) if prec else (d.schmidt(inp["first"]),)
@@ -82,3 +87,4 @@ def test_update_chi256_split_step_bit_identical(B, fixture, prec):
     assert dims0 == dims1 and sw0 == sw1
     for a, b in zip(lam0 + amp0, lam1 + amp1):
         assert np.array_equal(a, b)
+
