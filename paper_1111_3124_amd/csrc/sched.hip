@@ -452,6 +452,7 @@ class Scheduler {
   long g1_maxel = 0;
   std::vector<int> jl, rl, dl;  // slots in FP64 sweeps, dd refinement, dd polish
   int K = 1;                    // FP64 sweeps this tick
+  bool stamped = false;         // MPS_DEBUG_PHASES: this tick's launches stamped one step
 };
 
 int Scheduler::setup() {
@@ -658,6 +659,8 @@ hipError_t Scheduler::launch_jacobi(const std::vector<int>& jl, int K) {
     if (!P.la[k] || !P.lb[k] || !P.lo[k]) return hipErrorInvalidValue;
   }
   P.phase = E->d_phase;
+  // (the stamps come from a one-launch step of the first group's half a)
+  stamped = E->d_phase && !P.groups.empty() && P.groups[0].na && !P.groups[0].split_a;
   Timed tm(E, 1, K * plan_steps(P));
   if (E->graphs_on && !E->d_phase) return launch_sweep_graph(E, dt, P, st);
   return enqueue_sweeps(E, dt, P, st);
@@ -925,6 +928,7 @@ int Scheduler::sweep() {
     }
   }
   K = 1;  // sweeps this tick
+  stamped = false;
   if (!jl.empty()) {
     K = std::max(1, std::min(2, E->tick_sweeps));
     for (int si : jl) K = std::min(K, E->max_sweeps - slot[si].sweep);
@@ -945,7 +949,7 @@ int Scheduler::converge() {
     HIPCHK(err, hipMemcpyAsync(hflags, d_flags, sizeof(int) * 3 * S, hipMemcpyDeviceToHost, st));
     HIPCHK(err, hipStreamSynchronize(st));
     unsynced = false;
-    if (E->d_phase && !jl.empty()) {
+    if (stamped && !jl.empty()) {
       long long pc[5];
       HIPCHK(err, hipMemcpy(pc, E->d_phase, sizeof(pc), hipMemcpyDeviceToHost));
       // wall_clock64 runs at 100 MHz on gfx950
