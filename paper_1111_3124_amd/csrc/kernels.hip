@@ -461,10 +461,10 @@ __device__ int inner_jacobi_staged(double2 (&G)[2][W2][W2 + 1], double2 (&R)[2][
   return cur;
 }
 
-// A_P <- A_P R for 16-column pairs over the stacked rows (W's rows in tiles of 16 from
-// row 0, then V's), split between the two FP64 pipelines, whose peaks are equal: the
-// first half of the tiles on the matrix cores (rot_tiles), the rest on the vector units
-// (rot_rows), in different waves so that both issue at once.  Each row is formed by
+// A_P <- A_P R (and V_P <- V_P R) for 16-column pairs, split between the two FP64
+// pipelines, whose peaks are equal: the first half of each matrix's 16-row tiles on
+// the matrix cores (rot_tiles), its remaining rows on the vector units (rot_rows), in
+// different waves so that both issue at once (RotSet below).  Each row is formed by
 // the same instructions wherever it is computed, so the fused and split steps give the
 // same rows bit for bit.
 //
