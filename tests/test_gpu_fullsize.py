@@ -88,3 +88,32 @@ def test_update_chi256_split_step_bit_identical(B, fixture, prec, qr):
     for a, b in zip(lam0 + amp0, lam1 + amp1):
         assert np.array_equal(a, b)
 
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_update_chi256_fused_launch_modes_bit_identical(B, fixture, prec):
+    """The one-launch step (V's rotations applied one step late by extra blocks of the
+    next launch, the last step's by a flush after each tick's sweeps) under every
+    launch mode: one or two sweeps a tick, launched one by one or replayed from a
+    captured graph.  The same state bit for bit; FP64 without QR preconditioning, so
+    that V is accumulated there too."""
+    _, inp = fixture
+    out = []
+    for ts, gr in ((2, 0), (1, 0), (2, 1), (1, 1)):
+        print(f"fused-step launch modes: prec={prec} tick_sweeps={ts} graph={gr}", flush=True)
+        d = B.MPS(inp["n"], inp["chi"], inp["eps"], prec)
+        d.set_option(B.MPS_OPT_STEP_SPLIT, 0)
+        d.set_option(B.MPS_OPT_TICK_SWEEPS, ts)
+        d.set_option(B.MPS_OPT_GRAPH, gr)
+        if not prec:
+            d.set_option(B.MPS_OPT_QR, 0)
+        d.load(inp["B"], inp["lam"])
+        d.apply(inp["first"], 2, inp["U"])
+        lam = d.schmidt_dd(inp["first"]) if prec else (d.schmidt(inp["first"]),)
+        amp = d.amplitudes(inp["bits"], dd=True) if prec else (d.amplitudes(inp["bits"]),)
+        out.append((d.bond_dims(), lam, amp))
+        d.close()
+    for dims, lam, amp in out[1:]:
+        assert dims == out[0][0]
+        for a, b in zip(lam + amp, out[0][1] + out[0][2]):
+            assert np.array_equal(a, b)
