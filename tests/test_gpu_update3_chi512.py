@@ -64,3 +64,28 @@ def test_update3_chi512(B, case, prec, tol):
     print(f"  max |amplitude error| {err:.3e} (scale {scale:.3e})", flush=True)
     assert err <= tol * scale
     d.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_update3_chi512_fused_vs_split_bit_identical(B, case, prec):
+    """The same update with every Jacobi step as one launch (V's rotations applied one
+    step late by extra blocks, then a flush: the wide first split accumulates V at
+    N = 1024 in dd) and as the two-launch split form (V updated at once): the same
+    bond dims, Schmidt values and amplitudes bit for bit."""
+    _, inp = case
+    out = []
+    for limit in (0, 1 << 20):
+        print(f"config 3 update, fused vs split step: prec={prec} split limit={limit}", flush=True)
+        d = B.MPS(inp["n"], inp["chi"], inp["eps"], prec)
+        d.set_option(B.MPS_OPT_STEP_SPLIT, limit)
+        d.load(inp["B"], inp["lam"])
+        d.apply(inp["first"], 3, inp["U"])
+        lam = []
+        for bond in (inp["first"], inp["first"] + 1):
+            lam += list(d.schmidt_dd(bond)) if prec else [d.schmidt(bond)]
+        amp = list(d.amplitudes(inp["bits"], dd=True)) if prec else [d.amplitudes(inp["bits"])]
+        out.append((d.bond_dims(), lam + amp))
+        d.close()
+    assert out[0][0] == out[1][0]
+    for a, b in zip(out[0][1], out[1][1]):
+        assert np.array_equal(a, b)
